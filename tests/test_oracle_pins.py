@@ -1,0 +1,263 @@
+"""Pins of the CPU oracle against facts fixed outside it.
+
+Each test names what it pins.  The oracle is only trusted for the GPU parity tests
+because these pass: a dropped term, a wrong sign or index, or a transposed
+operand anywhere in it breaks at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import sph_harm_y
+
+import oracle
+from paper_2208_10154_amd import synth
+
+from . import brute
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------------------- geometry
+@pytest.mark.parametrize("nside", [1, 2, 3, 4, 5, 16, 128])
+def test_ring_counts_and_offsets(nside):
+    r = oracle.ring_info(nside)
+    assert len(r["n"]) == 4 * nside - 1
+    assert r["n"].sum() == 12 * nside * nside
+    assert np.all(r["first"][1:] == r["first"][:-1] + r["n"][:-1])
+    assert r["first"][0] == 0
+    assert np.all(np.diff(r["z"]) < 0)
+    np.testing.assert_allclose(r["z"], -r["z"][::-1], atol=1e-15)
+    np.testing.assert_allclose(r["sth"] ** 2 + r["z"] ** 2, 1.0, atol=1e-15)
+
+
+@pytest.mark.parametrize("nside", [1, 2, 3, 7, 16, 64])
+def test_ring_centres_bisect_equal_area_bands(nside):
+    """Equal-area property of HEALPix: the cap above a ring centre holds exactly the
+    pixels of the rings above plus half of the ring: 2 pi (1 - z_i) = dsigma (first_i + N_i/2)."""
+    r = oracle.ring_info(nside)
+    dsig = 4 * math.pi / (12 * nside * nside)
+    np.testing.assert_allclose(2 * math.pi * (1 - r["z"]), dsig * (r["first"] + r["n"] / 2), rtol=0, atol=1e-13)
+
+
+def test_nside1_base_pixel_centres_golden():
+    ref = np.loadtxt(os.path.join(GOLD, "healpix_nside1_centres.txt"))
+    th, ph = oracle.pixel_angles(1)
+    np.testing.assert_allclose(np.cos(th), ref[:, 1], atol=1e-15)
+    np.testing.assert_allclose(ph / (math.pi / 4), ref[:, 2], atol=1e-14)
+
+
+# ----------------------------------------------------------------------------- Legendre functions
+@pytest.mark.parametrize("m", [0, 1, 2, 7, 30])
+def test_lambda0_matches_mpmath_and_scipy(m):
+    """Orthonormal Condon-Shortley lambda_lm against mpmath's associated Legendre
+    function at 40 digits (tight) and scipy's sph_harm_y (double precision, whose
+    own rounding of cos(theta) limits it to ~1e-13)."""
+    import mpmath as mp
+    mp.mp.dps = 30
+    lmax = 64
+    for th in [0.05, 0.4, 1.0, 1.5707963, 2.3, 3.1]:
+        lam = oracle.lambda0(lmax, m, th)
+        x = mp.cos(mp.mpf(th))
+        lsel = range(m, lmax + 1, 7)
+        ref = np.array([float(mp.sqrt((2 * l + 1) / (4 * mp.pi) * mp.factorial(l - m) / mp.factorial(l + m))
+                              * mp.legenp(l, m, x)) for l in lsel])
+        np.testing.assert_allclose(lam[list(lsel)], ref, rtol=0, atol=2e-15)
+        sc = np.array([sph_harm_y(l, m, th, 0.0).real for l in range(m, lmax + 1)])
+        np.testing.assert_allclose(lam[m:], sc, rtol=0, atol=2e-13)
+
+
+def test_lambda0_closed_forms():
+    th = 0.83
+    np.testing.assert_allclose(oracle.lambda0(2, 0, th)[0], 1 / math.sqrt(4 * math.pi), rtol=1e-15)
+    np.testing.assert_allclose(oracle.lambda0(2, 0, th)[1], math.sqrt(3 / (4 * math.pi)) * math.cos(th), rtol=1e-15)
+    np.testing.assert_allclose(oracle.lambda0(2, 1, th)[1], -math.sqrt(3 / (8 * math.pi)) * math.sin(th), rtol=1e-15)
+
+
+@pytest.mark.parametrize("s", [2, -2])
+def test_lambda_spin_matches_goldberg_sum(s):
+    lmax = 8
+    for th in [0.1, 0.7, 1.6, 2.9]:
+        for m in range(-lmax, lmax + 1):
+            lam = oracle.lambda_spin(lmax, m, s, th)
+            for l in range(lmax + 1):
+                ref = brute.goldberg(s, l, m, np.array([th]), np.array([0.0]))[0]
+                assert abs(ref.imag) < 1e-14
+                assert abs(lam[l] - ref.real) < 1e-13, (s, l, m, th, lam[l], ref)
+
+
+def test_lambda_spin_closed_form():
+    th = 1.1
+    np.testing.assert_allclose(oracle.lambda_spin(3, 0, 2, th)[2], math.sqrt(15 / (32 * math.pi)) * math.sin(th) ** 2,
+                               rtol=1e-15)
+    np.testing.assert_allclose(oracle.lambda_spin(3, 0, -2, th)[2], math.sqrt(15 / (32 * math.pi)) * math.sin(th) ** 2,
+                               rtol=1e-15)
+
+
+def test_lambda_spin_reflection_identity():
+    """Wigner-d reflection d^l_{m,-s}(pi - t) = (-1)^{l+m} d^l_{m,s}(t) (large l, recursion path)."""
+    lmax, th = 300, 0.37
+    for m in [0, 1, 2, 5, 150]:
+        a = oracle.lambda_spin(lmax, m, 2, math.pi - th)
+        b = oracle.lambda_spin(lmax, m, -2, th)
+        sg = np.array([(-1) ** (l + m) for l in range(lmax + 1)])
+        np.testing.assert_allclose(a, sg * b, rtol=0, atol=1e-13)
+
+
+def test_lambda0_high_order_underflow_safe():
+    """lambda_mm ~ sin^m underflows double precision at high m near the pole; the
+    long-double recursion must still produce the O(1) values further along l."""
+    th = 0.6   # sin^1500(0.6) ~ 1e-372, turning point l sin(th) = m at l ~ 2650
+    lam = oracle.lambda0(3000, 1500, th)
+    assert np.all(np.isfinite(lam))
+    # Past the turning point (l sin(th) > m) the function is oscillatory with O(1) amplitude.
+    assert np.max(np.abs(lam[2900:])) > 1e-2
+    assert np.max(np.abs(lam[1500:1505])) < 1e-300
+
+
+# ----------------------------------------------------------------------------- spin-0 transforms
+def _cplx(L):
+    return np.zeros((1, L + 1, L + 1), dtype=np.complex128)
+
+
+def test_spin0_closed_form_maps():
+    nside, L = 8, 10
+    th, ph = oracle.pixel_angles(nside)
+    a = _cplx(L); a[0, 0, 0] = math.sqrt(4 * math.pi)
+    np.testing.assert_allclose(oracle.alm2map(nside, L, a)[0], 1.0, atol=1e-15)
+    a = _cplx(L); a[0, 1, 0] = 1.0
+    np.testing.assert_allclose(oracle.alm2map(nside, L, a)[0], math.sqrt(3 / (4 * math.pi)) * np.cos(th), atol=1e-15)
+    a = _cplx(L); a[0, 1, 1] = 1.0
+    np.testing.assert_allclose(oracle.alm2map(nside, L, a)[0],
+                               -2 * math.sqrt(3 / (8 * math.pi)) * np.sin(th) * np.cos(ph), atol=1e-15)
+    a = _cplx(L); a[0, 2, 2] = 1j
+    lam22 = math.sqrt(15 / (32 * math.pi)) * np.sin(th) ** 2
+    np.testing.assert_allclose(oracle.alm2map(nside, L, a)[0], -2 * lam22 * np.sin(2 * ph), atol=1e-15)
+
+
+@pytest.mark.parametrize("nside", [2, 5, 8])
+def test_spin0_analysis_of_constant_map(nside):
+    L = 3 * nside - 1
+    a = oracle.map2alm(nside, L, np.ones((1, 12 * nside * nside)))[0]
+    assert abs(a[0, 0] - math.sqrt(4 * math.pi)) < 1e-14
+    for l in range(L + 1):
+        for m in range(l + 1):
+            if m % 4 != 0 or (m == 0 and l % 2 == 1):
+                assert abs(a[l, m]) < 1e-14, (l, m, a[l, m])
+
+
+@pytest.mark.parametrize("nside", [2, 4])
+def test_spin0_bruteforce_both_directions(nside):
+    L = 3 * nside - 1
+    alm = synth.gaussian_alm(L, 1, False, workload=90)[0]
+    alm[0, 0] = 0.3; alm[1, 0] = -0.2; alm[1, 1] = 0.1 + 0.05j
+    T = oracle.alm2map(nside, L, alm[None])[0]
+    Tb = brute.synth0(nside, alm)
+    assert np.max(np.abs(Tb.imag)) < 1e-13
+    np.testing.assert_allclose(T, Tb.real, rtol=0, atol=1e-13)
+    t = synth.white_maps(12 * nside * nside, 1, 1, workload=91)[0, 0]
+    a = oracle.map2alm(nside, L, t[None])[0]
+    np.testing.assert_allclose(a, brute.anal0(nside, t, L), rtol=0, atol=1e-13)
+
+
+# ----------------------------------------------------------------------------- spin-2 transforms
+def test_spin2_closed_form_maps():
+    nside, L = 8, 10
+    th, _ = oracle.pixel_angles(nside)
+    f = math.sqrt(15 / (32 * math.pi)) * np.sin(th) ** 2
+    E = _cplx(L); B = _cplx(L); E[0, 2, 0] = 1.0
+    Q, U = oracle.alm2map_spin2(nside, L, E, B)
+    np.testing.assert_allclose(Q[0], -f, atol=1e-15); np.testing.assert_allclose(U[0], 0, atol=1e-15)
+    E = _cplx(L); B = _cplx(L); B[0, 2, 0] = 1.0
+    Q, U = oracle.alm2map_spin2(nside, L, E, B)
+    np.testing.assert_allclose(Q[0], 0, atol=1e-15); np.testing.assert_allclose(U[0], -f, atol=1e-15)
+
+
+@pytest.mark.parametrize("nside", [2, 3])
+def test_spin2_bruteforce_both_directions(nside):
+    L = 3 * nside - 1
+    a = synth.gaussian_alm(L, 1, True, workload=92)[0]
+    Q, U = oracle.alm2map_spin2(nside, L, a[1][None], a[2][None])
+    Qb, Ub = brute.synth2(nside, a[1], a[2])
+    np.testing.assert_allclose(Q[0], Qb, atol=1e-13)
+    np.testing.assert_allclose(U[0], Ub, atol=1e-13)
+    w = synth.white_maps(12 * nside * nside, 1, 2, workload=93)[0]
+    E, B = oracle.map2alm_spin2(nside, L, w[0][None], w[1][None])
+    Eb, Bb = brute.anal2(nside, w[0], w[1], L)
+    np.testing.assert_allclose(E[0], Eb, atol=1e-13)
+    np.testing.assert_allclose(B[0], Bb, atol=1e-13)
+
+
+# ----------------------------------------------------------------------------- identities
+def _wdot(a, b):
+    """sum_l sum_{m>=0} w_m Re(a conj b), w_0 = 1, w_{m>0} = 2."""
+    L = a.shape[-1] - 1
+    w = np.full(L + 1, 2.0); w[0] = 1.0
+    return float(np.sum(w * (a * np.conj(b)).real))
+
+
+@pytest.mark.parametrize("pol", [False, True])
+def test_weighted_adjoint_identity(pol):
+    nside, L = 8, 23
+    npx = 12 * nside * nside
+    dsig = 4 * math.pi / npx
+    a = synth.gaussian_alm(L, 1, pol, workload=94)
+    t = synth.white_maps(npx, 1, 3 if pol else 1, workload=95)
+    if not pol:
+        lhs = float(np.sum(oracle.alm2map(nside, L, a)[0] * t[0, 0]))
+        rhs = _wdot(a[0], oracle.map2alm(nside, L, t[:, 0])[0]) / dsig
+    else:
+        lhs = float(np.sum(oracle.alm2map_iqu(nside, L, a) * t))
+        b = oracle.map2alm_iqu(nside, L, t)
+        rhs = sum(_wdot(a[0, c], b[0, c]) for c in range(3)) / dsig
+    assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs))
+
+
+def test_linearity():
+    nside, L = 4, 11
+    a1 = synth.gaussian_alm(L, 1, True, 96); a2 = synth.gaussian_alm(L, 1, True, 97)
+    m = oracle.alm2map_iqu(nside, L, 0.7 * a1 - 1.3 * a2)
+    np.testing.assert_allclose(m, 0.7 * oracle.alm2map_iqu(nside, L, a1) - 1.3 * oracle.alm2map_iqu(nside, L, a2),
+                               atol=1e-13)
+
+
+def test_sampled_evaluations_match_full_transforms():
+    nside, L = 8, 23
+    a = synth.gaussian_alm(L, 1, True, 98)
+    maps = oracle.alm2map_iqu(nside, L, a)[0]
+    pix = np.array([0, 5, 100, 383, 500, 767])
+    np.testing.assert_allclose(oracle.synth_pixels(nside, L, a[0], pix, pol=True), maps[:, pix], atol=1e-13)
+    full = oracle.map2alm_iqu(nside, L, maps[None])[0]
+    ls = np.array([2, 5, 23, 10, 17]); ms = np.array([0, 3, 23, 10, 4])
+    np.testing.assert_allclose(oracle.analyze_lm(nside, L, maps, ls, ms, pol=True), full[:, ls, ms], atol=1e-13)
+
+
+# ----------------------------------------------------------------------------- storage, iteration
+def test_compact_storage_matches_paper_rule_and_is_bijective():
+    L = 2
+    rows = [ln.split() for ln in open(os.path.join(GOLD, "compact_storage_lmax2.txt")) if not ln.startswith("#")]
+    a = np.zeros((L + 1, L + 1), dtype=complex)
+    for part, l, m, r, c in rows:
+        l, m = int(l), int(m)
+        val = 10 * l + m + 1
+        a[l, m] += val if part == "re" else 1j * val
+    comp = oracle.to_compact(a)
+    for part, l, m, r, c in rows:
+        assert comp[int(c) * (L + 1) + int(r)] == 10 * int(l) + int(m) + 1
+    L = 9
+    z = synth.gaussian_alm(L, 1, False, 99)[0] + 0.01
+    z[:, 0] = z[:, 0].real
+    z = np.where(np.tril(np.ones((L + 1, L + 1))) > 0, z, 0)
+    np.testing.assert_array_equal(oracle.from_compact(oracle.to_compact(z), L), z)
+    idx = oracle.to_compact(oracle.from_compact(np.arange((L + 1) ** 2, dtype=float), L))
+    np.testing.assert_array_equal(idx, np.arange((L + 1) ** 2))
+
+
+def test_jacobi_iteration_reduces_round_trip_residual():
+    nside, L = 8, 15
+    a = synth.gaussian_alm(L, 2, False, 100)
+    maps = oracle.alm2map(nside, L, a)
+    _, res = oracle.map2alm_iter(nside, L, maps, 3)
+    assert np.all(np.diff(res) < 0), res
+    assert res[-1] < 0.05 * res[0]
