@@ -1,0 +1,128 @@
+/*
+ * sht.h -- C ABI of the batched HEALPix spherical harmonic transform for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those of Tian, Li & Liu, "Accelerating spherical harmonic
+ * transforms for a large number of sky maps" (arXiv:2208.10154):
+ *
+ *   map2alm   a_lm = dsigma sum_p T(p) Y*_lm(p), dsigma = 4 pi / Npix
+ *             (Sec. 2.1, eq. 1 and eq. "mm"; Algorithm 1); for polarisation the
+ *             E/B coefficients of Sec. 2.3 (eqs. alm-EB and the 2x2 block form).
+ *   alm2map   T(p) = sum_{l,m} a_lm Y_lm(p) (Sec. 2.1, backward equation), and the
+ *             transposed block form of Sec. 2.3 for Q/U.
+ *   map2alm_iter  the "traditional" iteration of Sec. 4 / Algorithm 2:
+ *             a_0 = A m, a_n = a_{n-1} + A (m - Y a_{n-1}), run between the
+ *             ring Fourier coefficients and a_lm (Sec. 3.1 item 8).
+ *
+ * Problem statement (Algorithm 1 "Data"/"Result"): a batch of sky maps in, their
+ * spherical harmonic coefficients out, or the reverse.
+ *
+ * Layouts (all boundary data is FP64 in every precision mode):
+ *   maps : double[nmaps][ncomp][12 nside^2], HEALPix RING order, ncomp = 1 (T)
+ *          for spin 0 and 3 (I, Q, U) for spin 2.
+ *   alm  : double[nmaps][ncomp][lmax+1][lmax+1] in the paper's compact real
+ *          storage (Appendix A.2): component (T) or (T, E, B); within one
+ *          component, column-major with flat index col*(lmax+1) + row, where
+ *          Re a_lm sits at (row l, col m) and Im a_lm (m >= 1) at
+ *          (row l-m, col lmax+1-m).  All a_lm with l < 2 of E and B are zero.
+ *
+ * All data pointers passed to the transform calls are DEVICE pointers on the
+ * plan's device; the caller owns them.  Calls are asynchronous and ordered on
+ * the plan's stream.  The plan owns its tables and (unless one is supplied) its
+ * workspace.  A plan is not thread safe: use one plan per host thread/stream.
+ *
+ * Every call returns SHT_OK (0) or a negative status; sht_last_error() gives a
+ * message (thread local).  Argument errors are detected before any device work
+ * and leave the plan unchanged.  Asynchronous device faults surface at the next
+ * call or at sht_plan_sync().
+ */
+#ifndef SHT_H
+#define SHT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sht_plan_s* sht_plan;
+
+enum sht_status {
+    SHT_OK = 0,
+    SHT_ERR_ARG = -1,         /* invalid argument: nothing was done */
+    SHT_ERR_NOMEM = -2,       /* device or host allocation failed */
+    SHT_ERR_DEVICE = -3,      /* a HIP call or kernel failed */
+    SHT_ERR_UNSUPPORTED = -4  /* valid request outside what this build implements */
+};
+
+/* Precision of the Legendre contraction.  The recursion (with its exponent
+ * rescaling), dsigma, the FFTs and the iteration residual are FP64 in all modes. */
+enum sht_precision {
+    SHT_FP64 = 0,   /* FP64 MFMA, FP64 ring Fourier coefficients */
+    SHT_FP32 = 1,   /* FP32 MFMA, FP32 ring Fourier coefficients */
+    SHT_BF16X3 = 2  /* split-BF16 (hi*hi + hi*lo + lo*hi) MFMA accumulated in FP32 */
+};
+
+/* Create a plan for HEALPix resolution nside, band limit lmax and spin 0 (T maps)
+ * or 2 (IQU map triples), for batches of up to nmaps map sets per call.
+ * Requires 1 <= nside <= 8192, 0 <= lmax <= 4*nside-1 (spin 2: lmax >= 2),
+ * nmaps >= 1.  Builds the ring tables, FFT plans and Legendre seed tables on the
+ * current HIP device (the paper's once-only initialisation, Sec. 3.3) and
+ * allocates the workspace for one chunk of map sets (see sht_plan_set_chunk). */
+int sht_plan_create(sht_plan* out, int nside, int lmax, int spin, int nmaps);
+
+/* Release every device and host resource of the plan (NULL is accepted). */
+int sht_plan_destroy(sht_plan plan);
+
+/* Select the contraction precision (enum sht_precision).  Default SHT_FP64.
+ * Reallocates the workspace when the element size changes. */
+int sht_plan_set_precision(sht_plan plan, int precision);
+
+/* Stream on which all later calls of this plan are enqueued (a hipStream_t;
+ * NULL = the default stream). */
+int sht_plan_set_stream(sht_plan plan, void* hip_stream);
+
+/* Number of map sets processed by the next calls, 1 <= n <= the nmaps given at
+ * creation.  Default: that nmaps. */
+int sht_plan_set_nmaps(sht_plan plan, int n);
+
+/* Map sets transformed per internal chunk (bounds the workspace).  The default
+ * keeps the workspace under about 8 GB.  Reallocates the workspace. */
+int sht_plan_set_chunk(sht_plan plan, int maps_per_chunk);
+
+/* Bytes of device workspace the plan uses with its current chunk and precision
+ * (for admission control by a caller). */
+size_t sht_plan_workspace_bytes(sht_plan plan);
+
+/* Bytes of device memory held by the plan's own tables (excluding workspace). */
+size_t sht_plan_table_bytes(sht_plan plan);
+
+/* Use caller-owned device memory of at least sht_plan_workspace_bytes() bytes as
+ * workspace (the plan frees its own).  Passing NULL returns to a plan-owned
+ * workspace. */
+int sht_plan_set_workspace(sht_plan plan, void* dev_ptr, size_t bytes);
+
+/* Backward transform (alm -> maps) of the current batch.  Device pointers. */
+int sht_alm2map(sht_plan plan, const double* alm, double* map);
+
+/* Forward transform (maps -> alm) of the current batch.  Device pointers. */
+int sht_map2alm(sht_plan plan, const double* map, double* alm);
+
+/* Iterative forward transform with niter >= 0 correction rounds (Algorithm 2).
+ * If resid is not NULL it receives niter+1 host doubles: the RMS over all pixels
+ * of all maps of the residual m - Y a_n after estimate n (n = 0 .. niter),
+ * computed in FP64 from the ring Fourier coefficients (Parseval); this call then
+ * synchronises the stream. */
+int sht_map2alm_iter(sht_plan plan, const double* map, double* alm, int niter, double* resid);
+
+/* Wait for the plan's stream and report any asynchronous device error. */
+int sht_plan_sync(sht_plan plan);
+
+/* Message describing the last error on this thread ("" if none). */
+const char* sht_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHT_H */

@@ -1,0 +1,739 @@
+// Host side of libsht: plan construction (ring geometry, FFT plans, Legendre seed
+// tables, work lists, workspace) and the C ABI declared in include/sht.h.
+#include "../../include/sht.h"
+#include "sht_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace sht;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            int c_ = (e_ == hipErrorOutOfMemory) ? SHT_ERR_NOMEM : SHT_ERR_DEVICE;           \
+            return fail(c_, std::string(#expr) + ": " + hipGetErrorString(e_));               \
+        }                                                                                    \
+    } while (0)
+
+typedef long double ld;
+const ld PI_L = 3.141592653589793238462643383279502884197L;
+
+// Device allocation that records its size (for the table accounting).
+struct Dev {
+    void* p = nullptr;
+    size_t n = 0;
+};
+
+struct SeedSet {
+    int spin = -1;
+    Dev mu, kk, seedoff, lsig, tileoff;
+    int64_t stride = 0;  // seeds per SoA array
+    int ntiles = 0;      // map2alm l tiles over all m
+};
+
+}  // namespace
+
+struct sht_plan_s {
+    int device = 0;
+    int nside = 0, lmax = 0, spin = 0, ncomp = 1, cap = 0, nmaps = 0, chunk = 0, prec = SHT_FP64;
+    int nring = 0, rn = 0, nrc = 0;
+    int64_t npix = 0;
+    hipStream_t stream = nullptr;
+
+    std::vector<RingDev> rings;
+    std::vector<FftLen> lens;
+    std::vector<Dev> owned;  // all table allocations
+    RingDev* d_rings = nullptr;
+    FftLen* d_lens = nullptr;
+    double2* d_tw = nullptr;
+    double2* d_bhat = nullptr;
+    SeedSet s0, s2;
+
+    // FFT work items for the current chunk size
+    Dev items_dev;
+    std::vector<FftClass> classes;
+    int items_npairs = -1;
+
+    // workspace
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    // iteration buffers (data spectra, residual norms), plan owned, lazily allocated
+    double* F = nullptr;
+    size_t F_bytes = 0;
+    double* norms = nullptr;
+    size_t table_bytes = 0;
+};
+
+namespace {
+
+int dev_alloc(sht_plan p, Dev& d, size_t bytes)
+{
+    d.n = bytes;
+    if (bytes == 0) { d.p = nullptr; return SHT_OK; }
+    hipError_t e = hipMalloc(&d.p, bytes);
+    if (e != hipSuccess) {
+        d.p = nullptr;
+        return fail(SHT_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    }
+    p->owned.push_back(d);
+    p->table_bytes += bytes;
+    return SHT_OK;
+}
+
+template <typename T>
+int upload(sht_plan p, Dev& d, const std::vector<T>& v)
+{
+    int rc = dev_alloc(p, d, v.size() * sizeof(T));
+    if (rc) return rc;
+    if (!v.empty()) HIPCHK(hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return SHT_OK;
+}
+
+// --------------------------------------------------------------------------
+// HEALPix RING geometry (Gorski et al. 2005): ring i = 1 .. 4 nside - 1
+// --------------------------------------------------------------------------
+void build_rings(sht_plan p)
+{
+    const int64_t ns = p->nside;
+    p->nring = 4 * p->nside - 1;
+    p->rn = 2 * p->nside;  // northern rings including the equator
+    p->npix = 12 * ns * ns;
+    p->rings.resize(p->nring);
+    for (int64_t i = 1; i <= 4 * ns - 1; ++i) {
+        RingDev r{};
+        ld z, sth;
+        if (i < ns || i > 3 * ns) {
+            int64_t j = (i < ns) ? i : 4 * ns - i;
+            ld onemz = (ld)(j * j) / (3.0L * (ld)ns * (ld)ns);
+            z = 1.0L - onemz;
+            sth = sqrtl(onemz * (2.0L - onemz));
+            r.n = (int)(4 * j);
+            r.s = 1;
+            if (i < ns) r.first = 2 * j * (j - 1);
+            else { r.first = p->npix - 2 * j * (j + 1); z = -z; }
+        } else {
+            z = (ld)(4 * ns - 2 * i) / (3.0L * (ld)ns);
+            sth = sqrtl((1.0L - z) * (1.0L + z));
+            r.n = (int)(4 * ns);
+            r.s = ((i - ns) % 2 == 0) ? 1 : 0;
+            r.first = 2 * ns * (ns - 1) + (i - ns) * 4 * ns;
+        }
+        r.z = (double)z;
+        r.sth = (double)sth;
+        p->rings[i - 1] = r;
+    }
+}
+
+// --------------------------------------------------------------------------
+// FFT plans
+// --------------------------------------------------------------------------
+bool factor_radices(int n, std::vector<int>& rad)
+{
+    rad.clear();
+    int t = n;
+    while (t % 4 == 0) { rad.push_back(4); t /= 4; }
+    while (t % 2 == 0) { rad.push_back(2); t /= 2; }
+    for (int q : {3, 5, 7})
+        while (t % q == 0) { rad.push_back(q); t /= q; }
+    return t == 1;
+}
+
+int smooth_at_least(int x)
+{
+    for (int m = x;; ++m) {
+        int t = m;
+        for (int q : {2, 3, 5, 7})
+            while (t % q == 0) t /= q;
+        if (t == 1) return m;
+    }
+}
+
+void push_twiddles(std::vector<double2>& pool, int n)
+{
+    // e^{-i pi j / n}, j = 0 .. 2n-1, from long-double sin/cos of the exact angle
+    for (int j = 0; j < 2 * n; ++j) {
+        ld ang = PI_L * (ld)j / (ld)n;
+        pool.push_back(make_double2((double)cosl(ang), (double)(-sinl(ang))));
+    }
+}
+
+int build_fft(sht_plan p)
+{
+    std::map<int, int> len_index;
+    std::map<int, int64_t> tw_of;  // length -> twiddle offset
+    std::vector<double2> pool;
+    std::vector<int> blue;
+    int64_t bhat_total = 0;
+    int max_blue_m = 0;
+    for (auto& r : p->rings) {
+        auto it = len_index.find(r.n);
+        if (it != len_index.end()) { r.len = it->second; continue; }
+        FftLen L{};
+        L.n = r.n;
+        std::vector<int> rad;
+        bool direct = factor_radices(r.n, rad);
+        if (!tw_of.count(r.n)) { tw_of[r.n] = (int64_t)pool.size(); push_twiddles(pool, r.n); }
+        L.tw = tw_of[r.n];
+        int len = r.n;
+        if (!direct) {
+            L.blue = 1;
+            L.m = smooth_at_least(2 * r.n - 1);
+            factor_radices(L.m, rad);
+            if (!tw_of.count(L.m)) { tw_of[L.m] = (int64_t)pool.size(); push_twiddles(pool, L.m); }
+            L.twm = tw_of[L.m];
+            L.bhat = bhat_total;
+            bhat_total += L.m;
+            len = L.m;
+            max_blue_m = std::max(max_blue_m, L.m);
+        }
+        if ((int)rad.size() > MAX_STAGES) return fail(SHT_ERR_UNSUPPORTED, "ring FFT needs too many stages");
+        L.nstage = (int)rad.size();
+        for (size_t k = 0; k < rad.size(); ++k) L.radix[k] = rad[k];
+        if (len > 16 * FFT_THREADS) return fail(SHT_ERR_UNSUPPORTED, "ring FFT length beyond the LDS plan");
+        // map pairs per workgroup: fill up to 1024 complex values when small, else 4096
+        int cap = (len <= 1024) ? 1024 : (len <= 4096 ? 4096 : 8192);
+        L.nseq = std::max(1, std::min(16, cap / len));
+        L.ldsc = L.nseq * len;
+        r.len = (int)p->lens.size();
+        len_index[r.n] = r.len;
+        if (L.blue) blue.push_back(r.len);
+        p->lens.push_back(L);
+    }
+    Dev drings, dlens, dtw, dbhat, dblue;
+    int rc;
+    if ((rc = upload(p, drings, p->rings))) return rc;
+    if ((rc = upload(p, dlens, p->lens))) return rc;
+    if ((rc = upload(p, dtw, pool))) return rc;
+    if ((rc = dev_alloc(p, dbhat, std::max<int64_t>(1, bhat_total) * sizeof(double2)))) return rc;
+    p->d_rings = (RingDev*)drings.p;
+    p->d_lens = (FftLen*)dlens.p;
+    p->d_tw = (double2*)dtw.p;
+    p->d_bhat = (double2*)dbhat.p;
+    if (!blue.empty()) {
+        if ((rc = upload(p, dblue, blue))) return rc;
+        HIPCHK(launch_bluestein_init(p->d_lens, (const int*)dblue.p, (int)blue.size(), p->d_tw, p->d_bhat,
+                                     max_blue_m, p->stream));
+    }
+    return SHT_OK;
+}
+
+// FFT work items (ring, first pair) for npairs map pairs, grouped by LDS class.
+int build_items(sht_plan p, int npairs)
+{
+    if (p->items_npairs == npairs) return SHT_OK;
+    std::vector<FftItem> cls_items[3];
+    int lds[3] = {0, 0, 0};
+    for (int r = 0; r < p->nring; ++r) {
+        const FftLen& L = p->lens[p->rings[r].len];
+        int c = (L.ldsc <= 2 * FFT_THREADS) ? 0 : (L.ldsc <= 8 * FFT_THREADS ? 1 : 2);
+        lds[c] = std::max(lds[c], L.ldsc);
+        for (int q = 0; q < npairs; q += L.nseq) cls_items[c].push_back(FftItem{r, q});
+    }
+    std::vector<FftItem> all;
+    size_t off[3];
+    for (int c = 0; c < 3; ++c) { off[c] = all.size(); all.insert(all.end(), cls_items[c].begin(), cls_items[c].end()); }
+    if (p->items_dev.p) {
+        (void)hipFree(p->items_dev.p);
+        p->table_bytes -= p->items_dev.n;
+        p->items_dev.p = nullptr;
+    }
+    size_t bytes = std::max<size_t>(1, all.size()) * sizeof(FftItem);
+    HIPCHK(hipMalloc(&p->items_dev.p, bytes));
+    p->items_dev.n = bytes;
+    p->table_bytes += bytes;
+    HIPCHK(hipMemcpy(p->items_dev.p, all.data(), all.size() * sizeof(FftItem), hipMemcpyHostToDevice));
+    p->classes.clear();
+    const int elems[3] = {2, 8, 16};
+    for (int c = 0; c < 3; ++c)
+        p->classes.push_back(FftClass{(const FftItem*)p->items_dev.p + off[c], (int)cls_items[c].size(), lds[c], elems[c]});
+    p->items_npairs = npairs;
+    return SHT_OK;
+}
+
+// --------------------------------------------------------------------------
+// Legendre seeds
+// --------------------------------------------------------------------------
+// scaled form of a value given its log2 magnitude: mu * 2^(-600 k), |mu| in [2^-100, 2^500)
+void scaled(ld log2abs, double sign, double& mu, int& k)
+{
+    k = 0;
+    if (log2abs < (ld)SIG_LOG2) k = (int)ceill(((ld)SIG_LOG2 - log2abs) / (ld)SCALE_BITS);
+    mu = sign * (double)exp2l(log2abs + (ld)SCALE_BITS * k);
+}
+
+int build_seeds(sht_plan p, SeedSet& S, int spin)
+{
+    S.spin = spin;
+    const int L = p->lmax, rn = p->rn;
+    // start values lambda_{lb}(theta_r) per (m, north ring) in scaled form
+    std::vector<double> start((size_t)(spin == 0 ? 1 : 2) * (L + 1) * rn);
+    std::vector<int> startk((size_t)(L + 1) * rn);
+    if (spin == 0) {
+        // lambda_mm = (-1)^m (4 pi)^{-1/2} prod_{k=1}^m sqrt((2k+1)/(2k)) sin^m(theta)
+        ld lognorm = -0.5L * log2l(4.0L * PI_L);
+        for (int m = 0; m <= L; ++m) {
+            if (m > 0) lognorm += 0.5L * log2l((ld)(2 * m + 1) / (ld)(2 * m));
+            double sign = (m & 1) ? -1.0 : 1.0;
+            for (int r = 0; r < rn; ++r) {
+                ld t = lognorm + (ld)m * log2l((ld)p->rings[r].sth);
+                scaled(t, sign, start[(size_t)m * rn + r], startk[(size_t)m * rn + r]);
+            }
+        }
+    } else {
+        // {}_{+-2}lambda_{lb} = sqrt((2lb+1)/4pi) d^{lb}_{m,-+2}(theta), lb = max(m, 2)
+        for (int m = 0; m <= L; ++m) {
+            int lb = std::max(m, 2);
+            ld lnorm = 0.5L * logl((ld)(2 * lb + 1) / (4.0L * PI_L));
+            for (int r = 0; r < rn; ++r) {
+                ld z = (ld)p->rings[r].z;
+                ld lc = 0.5L * logl((1.0L + z) / 2.0L), ls = 0.5L * logl((1.0L - z) / 2.0L);
+                ld lP, lM;
+                double sP, sM;
+                if (m >= 2) {
+                    ld f = 0.5L * (lgammal(2.0L * m + 1) - lgammal((ld)m - 1) - lgammal((ld)m + 3));
+                    lP = f + (ld)(m - 2) * lc + (ld)(m + 2) * ls;
+                    lM = f + (ld)(m + 2) * lc + (ld)(m - 2) * ls;
+                    sP = sM = (m & 1) ? -1.0 : 1.0;
+                } else {
+                    ld f = 0.5L * (logl(24.0L) - lgammal(3.0L - m) - lgammal(3.0L + m));
+                    lP = f + (ld)(2 - m) * lc + (ld)(2 + m) * ls;
+                    lM = f + (ld)(2 + m) * lc + (ld)(2 - m) * ls;
+                    sP = (m & 1) ? -1.0 : 1.0;
+                    sM = 1.0;
+                }
+                lP += lnorm;
+                lM += lnorm;
+                ld lmax2 = std::max(lP, lM) / logl(2.0L);
+                int k = 0;
+                if (lmax2 < (ld)SIG_LOG2) k = (int)ceill(((ld)SIG_LOG2 - lmax2) / (ld)SCALE_BITS);
+                ld sh = (ld)SCALE_BITS * k * logl(2.0L);
+                start[(size_t)m * rn + r] = sP * (double)expl(lP + sh);
+                start[(size_t)(L + 1) * rn + (size_t)m * rn + r] = sM * (double)expl(lM + sh);
+                startk[(size_t)m * rn + r] = k;
+            }
+        }
+    }
+    std::vector<int64_t> seedoff(L + 2);
+    std::vector<int> tileoff(L + 2);
+    int64_t tot = 0;
+    int tt = 0;
+    for (int m = 0; m <= L; ++m) {
+        seedoff[m] = tot;
+        tileoff[m] = tt;
+        int ns = nsegs(spin, L, m);
+        tot += (int64_t)ns * rn;
+        tt += (ns + 1) / 2;  // TL = 2 SEG
+    }
+    seedoff[L + 1] = tot;
+    tileoff[L + 1] = tt;
+    S.stride = tot;
+    S.ntiles = tt;
+    int rc;
+    const int nmu = (spin == 0) ? 2 : 4;
+    if ((rc = dev_alloc(p, S.mu, (size_t)std::max<int64_t>(1, tot) * nmu * sizeof(double)))) return rc;
+    if ((rc = dev_alloc(p, S.kk, (size_t)std::max<int64_t>(1, tot) * sizeof(int)))) return rc;
+    if ((rc = upload(p, S.seedoff, seedoff))) return rc;
+    if ((rc = upload(p, S.tileoff, tileoff))) return rc;
+    if ((rc = dev_alloc(p, S.lsig, (size_t)(L + 1) * p->nrc * sizeof(int)))) return rc;
+    HIPCHK(hipMemsetD32Async((hipDeviceptr_t)S.lsig.p, L + 1, (size_t)(L + 1) * p->nrc, p->stream));
+    void* d_start = nullptr;
+    void* d_startk = nullptr;
+    HIPCHK(hipMalloc(&d_start, start.size() * sizeof(double)));
+    HIPCHK(hipMalloc(&d_startk, startk.size() * sizeof(int)));
+    HIPCHK(hipMemcpy(d_start, start.data(), start.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_startk, startk.data(), startk.size() * sizeof(int), hipMemcpyHostToDevice));
+    SeedArgs a{};
+    a.rings = p->d_rings;
+    a.start = (const double*)d_start;
+    a.startk = (const int*)d_startk;
+    a.mu = (double*)S.mu.p;
+    a.kk = (int*)S.kk.p;
+    a.seedoff = (const int64_t*)S.seedoff.p;
+    a.seedstride = S.stride;
+    a.lsig = (int*)S.lsig.p;
+    a.nrc = p->nrc;
+    a.lmax = L;
+    a.rn = rn;
+    a.spin = spin;
+    hipError_t e = launch_seeds(a, p->stream);
+    hipError_t e2 = hipStreamSynchronize(p->stream);
+    (void)hipFree(d_start);
+    (void)hipFree(d_startk);
+    HIPCHK(e);
+    HIPCHK(e2);
+    return SHT_OK;
+}
+
+// --------------------------------------------------------------------------
+// workspace
+// --------------------------------------------------------------------------
+size_t esize(int prec) { return prec == SHT_FP64 ? sizeof(double) : sizeof(float); }
+
+int64_t ldx_for(int chunk) { return 2 * (int64_t)((chunk + 31) / 32 * 32); }
+
+int64_t xcomp_elems(sht_plan p) { return (int64_t)(p->lmax + 1) * p->nring * ldx_for(p->chunk); }
+
+size_t ws_need(sht_plan p) { return (size_t)p->ncomp * (size_t)xcomp_elems(p) * esize(p->prec); }
+
+int default_chunk(sht_plan p)
+{
+    const double budget = 8.0e9;
+    double per = (double)p->ncomp * (p->lmax + 1) * p->nring * 2.0 * esize(p->prec);
+    int c = (int)std::max(1.0, std::floor(budget / per));
+    if (c >= 32) c = c / 32 * 32;
+    return std::min(c, p->cap);
+}
+
+int ensure_workspace(sht_plan p)
+{
+    size_t need = ws_need(p);
+    if (p->ws && p->ws_bytes >= need) return SHT_OK;
+    if (p->ws && !p->ws_owned)
+        return fail(SHT_ERR_ARG, "caller workspace of " + std::to_string(p->ws_bytes) + " bytes is smaller than the " +
+                                     std::to_string(need) + " bytes needed");
+    if (p->ws) { (void)hipFree(p->ws); p->ws = nullptr; p->ws_bytes = 0; }
+    hipError_t e = hipMalloc(&p->ws, need);
+    if (e != hipSuccess) {
+        p->ws = nullptr;
+        return fail(SHT_ERR_NOMEM, "workspace hipMalloc of " + std::to_string(need) + " bytes failed");
+    }
+    p->ws_bytes = need;
+    p->ws_owned = true;
+    return SHT_OK;
+}
+
+int ensure_iter_buffers(sht_plan p)
+{
+    size_t need = (size_t)p->chunk * p->ncomp * (size_t)p->npix * sizeof(double);
+    if (p->F && p->F_bytes >= need) return SHT_OK;
+    if (p->F) (void)hipFree(p->F);
+    if (p->norms) (void)hipFree(p->norms);
+    p->F = nullptr;
+    p->norms = nullptr;
+    HIPCHK(hipMalloc((void**)&p->F, need));
+    HIPCHK(hipMalloc((void**)&p->norms, (size_t)p->chunk * p->ncomp * sizeof(double) + 64));
+    p->F_bytes = need;
+    return SHT_OK;
+}
+
+// --------------------------------------------------------------------------
+// kernel argument assembly
+// --------------------------------------------------------------------------
+FftArgs fft_args(sht_plan p, int nmaps_chunk)
+{
+    FftArgs a{};
+    a.rings = p->d_rings;
+    a.lens = p->d_lens;
+    a.tw = p->d_tw;
+    a.bhat = p->d_bhat;
+    a.X = p->ws;
+    a.npix = p->npix;
+    a.ncomp = p->ncomp;
+    a.comp0 = 0;
+    a.nmaps = nmaps_chunk;
+    a.ldx = ldx_for(p->chunk);
+    a.npairs = (int)(a.ldx / 4);
+    a.lmax = p->lmax;
+    a.nring = p->nring;
+    a.xcomp = xcomp_elems(p);
+    a.x32 = (p->prec != SHT_FP64);
+    return a;
+}
+
+LegArgs leg_args(sht_plan p, const SeedSet& S, double* alm, int nmaps_chunk)
+{
+    LegArgs a{};
+    a.rings = p->d_rings;
+    a.mu = (const double*)S.mu.p;
+    a.kk = (const int*)S.kk.p;
+    a.seedoff = (const int64_t*)S.seedoff.p;
+    a.seedstride = S.stride;
+    a.lsig = (const int*)S.lsig.p;
+    a.nrc = p->nrc;
+    a.tiles = (const int*)S.tileoff.p;
+    a.ntiles = S.ntiles;
+    a.X = p->ws;
+    a.xcomp = xcomp_elems(p);
+    a.alm = alm;
+    a.almstride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
+    a.compT = 0;
+    a.nmaps = nmaps_chunk;
+    a.ldx = ldx_for(p->chunk);
+    a.lmax = p->lmax;
+    a.rn = p->rn;
+    a.nring = p->nring;
+    a.spin = S.spin;
+    a.scale = 1.0;
+    a.accumulate = 0;
+    return a;
+}
+
+int prep(sht_plan p)
+{
+    int rc = ensure_workspace(p);
+    if (rc) return rc;
+    return build_items(p, (int)(ldx_for(p->chunk) / 4));
+}
+
+int run_a2m(sht_plan p, const double* alm, int nm)
+{
+    LegArgs a = leg_args(p, p->s0, const_cast<double*>(alm), nm);
+    HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
+    if (p->spin == 2) {
+        LegArgs b = leg_args(p, p->s2, const_cast<double*>(alm), nm);
+        HIPCHK(launch_leg_a2m(b, p->prec, p->stream));
+    }
+    return SHT_OK;
+}
+
+int run_m2a(sht_plan p, double* alm, int nm, int accumulate)
+{
+    const double dsig = 4.0 * M_PI / (double)p->npix;
+    LegArgs a = leg_args(p, p->s0, alm, nm);
+    a.scale = dsig;
+    a.accumulate = accumulate;
+    HIPCHK(launch_leg_m2a(a, p->prec, p->stream));
+    if (p->spin == 2) {
+        LegArgs b = leg_args(p, p->s2, alm, nm);
+        b.scale = dsig;
+        b.accumulate = accumulate;
+        HIPCHK(launch_leg_m2a(b, p->prec, p->stream));
+    }
+    return SHT_OK;
+}
+
+int check_ready(sht_plan p)
+{
+    if (!p) return fail(SHT_ERR_ARG, "null plan");
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != p->device) return fail(SHT_ERR_ARG, "current HIP device differs from the plan's device");
+    HIPCHK(hipGetLastError());
+    return SHT_OK;
+}
+
+void destroy_all(sht_plan p)
+{
+    for (auto& d : p->owned)
+        if (d.p) (void)hipFree(d.p);
+    if (p->items_dev.p) (void)hipFree(p->items_dev.p);
+    if (p->ws && p->ws_owned) (void)hipFree(p->ws);
+    if (p->F) (void)hipFree(p->F);
+    if (p->norms) (void)hipFree(p->norms);
+    delete p;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* sht_last_error(void) { return g_err.c_str(); }
+
+int sht_plan_create(sht_plan* out, int nside, int lmax, int spin, int nmaps)
+{
+    g_err.clear();
+    if (!out) return fail(SHT_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (nside < 1 || nside > 8192) return fail(SHT_ERR_ARG, "nside must be in [1, 8192]");
+    if (lmax < 0 || lmax > 4 * nside - 1) return fail(SHT_ERR_ARG, "lmax must be in [0, 4*nside-1]");
+    if (spin != 0 && spin != 2) return fail(SHT_ERR_ARG, "spin must be 0 or 2");
+    if (spin == 2 && lmax < 2) return fail(SHT_ERR_ARG, "spin 2 needs lmax >= 2");
+    if (nmaps < 1) return fail(SHT_ERR_ARG, "nmaps must be >= 1");
+    if (lmax > 4094) return fail(SHT_ERR_UNSUPPORTED, "lmax above 4094 is not supported");
+    if (nside > 1024) return fail(SHT_ERR_UNSUPPORTED, "nside above 1024 is not supported (ring FFT LDS plan)");
+    sht_plan p = new sht_plan_s();
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { delete p; return fail(SHT_ERR_DEVICE, "no HIP device"); }
+    p->device = dev;
+    p->nside = nside;
+    p->lmax = lmax;
+    p->spin = spin;
+    p->ncomp = (spin == 0) ? 1 : 3;
+    p->cap = nmaps;
+    p->nmaps = nmaps;
+    p->stream = nullptr;
+    build_rings(p);
+    p->nrc = (p->rn + RCHUNK - 1) / RCHUNK;
+    int rc = build_fft(p);
+    if (!rc) rc = build_seeds(p, p->s0, 0);
+    if (!rc && spin == 2) rc = build_seeds(p, p->s2, 2);
+    if (!rc) {
+        p->chunk = default_chunk(p);
+        rc = prep(p);
+    }
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) rc = fail(SHT_ERR_DEVICE, std::string("plan set-up: ") + hipGetErrorString(e));
+    }
+    if (rc) { destroy_all(p); return rc; }
+    *out = p;
+    return SHT_OK;
+}
+
+int sht_plan_destroy(sht_plan p)
+{
+    if (!p) return SHT_OK;
+    (void)hipStreamSynchronize(p->stream);
+    destroy_all(p);
+    return SHT_OK;
+}
+
+int sht_plan_set_precision(sht_plan p, int prec)
+{
+    if (!p) return fail(SHT_ERR_ARG, "null plan");
+    if (prec != SHT_FP64 && prec != SHT_FP32 && prec != SHT_BF16X3) return fail(SHT_ERR_ARG, "unknown precision");
+    if (prec == SHT_BF16X3) return fail(SHT_ERR_UNSUPPORTED, "BF16x3 contraction is not built yet");
+    p->prec = prec;
+    return prep(p);
+}
+
+int sht_plan_set_stream(sht_plan p, void* s)
+{
+    if (!p) return fail(SHT_ERR_ARG, "null plan");
+    p->stream = (hipStream_t)s;
+    return SHT_OK;
+}
+
+int sht_plan_set_nmaps(sht_plan p, int n)
+{
+    if (!p) return fail(SHT_ERR_ARG, "null plan");
+    if (n < 1 || n > p->cap) return fail(SHT_ERR_ARG, "nmaps must be in [1, capacity]");
+    p->nmaps = n;
+    return SHT_OK;
+}
+
+int sht_plan_set_chunk(sht_plan p, int c)
+{
+    if (!p) return fail(SHT_ERR_ARG, "null plan");
+    if (c < 1) return fail(SHT_ERR_ARG, "chunk must be >= 1");
+    p->chunk = std::min(c, p->cap);
+    return prep(p);
+}
+
+size_t sht_plan_workspace_bytes(sht_plan p) { return p ? ws_need(p) : 0; }
+
+size_t sht_plan_table_bytes(sht_plan p) { return p ? p->table_bytes : 0; }
+
+int sht_plan_set_workspace(sht_plan p, void* ptr, size_t bytes)
+{
+    if (!p) return fail(SHT_ERR_ARG, "null plan");
+    if (ptr && bytes < ws_need(p)) return fail(SHT_ERR_ARG, "workspace too small");
+    if (p->ws && p->ws_owned) (void)hipFree(p->ws);
+    p->ws = ptr;
+    p->ws_bytes = ptr ? bytes : 0;
+    p->ws_owned = false;
+    if (!ptr) return ensure_workspace(p);
+    return SHT_OK;
+}
+
+int sht_alm2map(sht_plan p, const double* alm, double* map)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
+    if ((rc = prep(p))) return rc;
+    const int64_t astride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
+    const int64_t mstride = (int64_t)p->ncomp * p->npix;
+    for (int k0 = 0; k0 < p->nmaps; k0 += p->chunk) {
+        int nm = std::min(p->chunk, p->nmaps - k0);
+        if ((rc = run_a2m(p, alm + k0 * astride, nm))) return rc;
+        FftArgs f = fft_args(p, nm);
+        f.maps_out = map + k0 * mstride;
+        HIPCHK(launch_fft_inverse(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+    }
+    return SHT_OK;
+}
+
+int sht_map2alm(sht_plan p, const double* map, double* alm)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
+    if ((rc = prep(p))) return rc;
+    const int64_t astride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
+    const int64_t mstride = (int64_t)p->ncomp * p->npix;
+    for (int k0 = 0; k0 < p->nmaps; k0 += p->chunk) {
+        int nm = std::min(p->chunk, p->nmaps - k0);
+        FftArgs f = fft_args(p, nm);
+        f.maps_in = map + k0 * mstride;
+        HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+        if ((rc = run_m2a(p, alm + k0 * astride, nm, 0))) return rc;
+    }
+    return SHT_OK;
+}
+
+int sht_map2alm_iter(sht_plan p, const double* map, double* alm, int niter, double* resid)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
+    if (niter < 0) return fail(SHT_ERR_ARG, "niter must be >= 0");
+    if ((rc = prep(p))) return rc;
+    if ((rc = ensure_iter_buffers(p))) return rc;
+    const int64_t astride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
+    const int64_t mstride = (int64_t)p->ncomp * p->npix;
+    std::vector<double> sums(niter + 1, 0.0), hn;
+    for (int k0 = 0; k0 < p->nmaps; k0 += p->chunk) {
+        int nm = std::min(p->chunk, p->nmaps - k0);
+        double* a = alm + k0 * astride;
+        FftArgs f = fft_args(p, nm);
+        f.maps_in = map + k0 * mstride;
+        f.F = p->F;
+        HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+        if ((rc = run_m2a(p, a, nm, 0))) return rc;
+        const int rounds = niter + (resid ? 1 : 0);
+        for (int it = 1; it <= rounds; ++it) {
+            if ((rc = run_a2m(p, a, nm))) return rc;
+            FftArgs r = fft_args(p, nm);
+            r.F = p->F;
+            r.norms = resid ? p->norms : nullptr;
+            r.iteration_sub = (it <= niter);
+            if (resid) HIPCHK(hipMemsetAsync(p->norms, 0, (size_t)nm * p->ncomp * sizeof(double), p->stream));
+            HIPCHK(launch_residual(r, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+            if (resid) {
+                hn.resize((size_t)nm * p->ncomp);
+                HIPCHK(hipMemcpyAsync(hn.data(), p->norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+                HIPCHK(hipStreamSynchronize(p->stream));
+                for (double v : hn) sums[it - 1] += v;
+            }
+            if (it <= niter)
+                if ((rc = run_m2a(p, a, nm, 1))) return rc;
+        }
+    }
+    if (resid) {
+        double cnt = (double)p->nmaps * p->ncomp * (double)p->npix;
+        for (int n = 0; n <= niter; ++n) resid[n] = std::sqrt(sums[n] / cnt);
+    }
+    return SHT_OK;
+}
+
+int sht_plan_sync(sht_plan p)
+{
+    if (!p) return fail(SHT_ERR_ARG, "null plan");
+    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPCHK(hipGetLastError());
+    return SHT_OK;
+}
+
+}  // extern "C"

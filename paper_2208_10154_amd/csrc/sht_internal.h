@@ -1,0 +1,153 @@
+// Internal types shared by the host plan code and the HIP kernels of libsht.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace sht {
+
+// ----------------------------------------------------------------------------
+// Scaled representation of Legendre values: true value = mu * 2^(-SCALE_BITS*k).
+// k >= 1 means |true| < 2^-100, which is treated as exactly zero when the value
+// is fed to the contraction (ring skipping and underflow handling in one rule).
+// ----------------------------------------------------------------------------
+constexpr int SCALE_BITS = 600;
+constexpr double SCALE_DOWN = 0x1p-600;   // 2^-SCALE_BITS
+constexpr double RESCALE_AT = 0x1p500;    // rescale when |mu| exceeds this and k >= 1
+constexpr int SIG_LOG2 = -100;            // values below 2^SIG_LOG2 count as zero
+
+// Legendre tiling: l segments of SEG values start at lb(m) + SEG*j; contraction
+// tiles cover TL = 2*SEG values of l.
+constexpr int SEG = 32;
+constexpr int TL = 64;
+constexpr int RCHUNK = 32;   // ring granularity of the skip table
+
+// ----------------------------------------------------------------------------
+// FFT tables
+// ----------------------------------------------------------------------------
+constexpr int MAX_STAGES = 16;
+struct FftLen {
+    int n;                  // ring length
+    int blue;               // 1: Bluestein through length m
+    int m;                  // Bluestein FFT length (0 if direct)
+    int nstage;             // stages of the FFT actually run (length n or m)
+    int radix[MAX_STAGES];
+    int64_t tw;             // offset of e^{-i pi j / n}, j < 2n
+    int64_t twm;            // offset of e^{-i pi j / m}, j < 2m (Bluestein)
+    int64_t bhat;           // offset of the Bluestein kernel spectrum (m entries, scaled by 1/m)
+    int nseq;               // map pairs per workgroup
+    int ldsc;               // complex LDS elements per workgroup = nseq * (blue ? m : n)
+};
+
+struct RingDev {
+    double z;               // cos(theta)
+    double sth;             // sin(theta)
+    int64_t first;          // first pixel
+    int n;                  // pixels
+    int s;                  // phase shift: first pixel at phi = pi s / n
+    int len;                // index into FftLen table
+    int pad;
+};
+
+struct FftItem {
+    int ring;
+    int pair0;
+};
+
+// ----------------------------------------------------------------------------
+// Kernel argument blocks
+// ----------------------------------------------------------------------------
+struct FftArgs {
+    const RingDev* rings;
+    const FftLen* lens;
+    const FftItem* items;
+    const double2* tw;      // twiddle pool
+    const double2* bhat;    // Bluestein spectra pool
+    const double* maps_in;  // forward: maps of the chunk (component stride npix, map-set stride ncomp*npix)
+    double* maps_out;       // inverse: output maps
+    void* X;                // ring Fourier coefficients, [m][ring][ldx] (double or float)
+    double* F;              // optional halfcomplex spectra [map-set][comp][npix] (iteration data)
+    double* norms;          // optional per map-set/comp residual sum of squares (K_RES)
+    int64_t npix;
+    int ncomp;
+    int comp0;              // first component index handled by this launch (blockIdx.y adds to it)
+    int nmaps;              // map sets in the chunk
+    int npairs;             // padded map-set pairs (ldx / 4)
+    int lmax;
+    int nring;
+    int64_t ldx;            // columns of X (2 * padded map sets)
+    int64_t xcomp;          // element stride between the X arrays of consecutive components
+    int x32;                // X stored as float
+    int iteration_sub;      // K_RES: subtract N*C from F into X
+};
+
+struct LegArgs {
+    const RingDev* rings;   // all rings; north ring r (0-based) is rings[r]
+    // seeds: for (m, segment j, north ring r): index seedoff[m] + j*rn + r
+    const double* mu;       // spin 0: 2 values (l, l+1); spin 2: 4 values (P_l, P_l+1, M_l, M_l+1), SoA
+    const int* kk;          // exponent counter k at the segment start
+    const int64_t* seedoff;
+    int64_t seedstride;     // distance between SoA arrays of mu
+    const int* lsig;        // [m][ring chunk of RCHUNK]: first l with a significant value (or lmax+1)
+    int nrc;                // ring chunks of RCHUNK per m
+    const int* tiles;       // map2alm: tileoff[m] = l tiles of all m' < m (lmax+2 entries)
+    int ntiles;             // map2alm: total l tiles (tileoff[lmax+1])
+    void* X;                // [m][ring][ldx], component arrays xcomp apart (T | Q | U)
+    int64_t xcomp;
+    double* alm;            // compact alm of the chunk's first map set
+    int64_t almstride;      // doubles between consecutive map sets (= ncomp*(lmax+1)^2)
+    int compT;              // component index of T / the spin-0 field in the alm array
+    int nmaps;              // valid map sets (columns beyond 2*nmaps are padding)
+    int64_t ldx;
+    int lmax, rn, nring, spin;
+    int ctiles;             // column tiles
+    double scale;           // dsigma for map2alm, 1 for alm2map
+    int accumulate;         // map2alm: alm += scale * result instead of =
+};
+
+// first l of the recursion for (spin, m)
+__host__ __device__ inline int lbase(int spin, int m) { return spin == 2 ? (m > 2 ? m : 2) : m; }
+__host__ __device__ inline int nsegs(int spin, int lmax, int m)
+{
+    int lb = lbase(spin, m);
+    return lb > lmax ? 0 : (lmax - lb + SEG) / SEG;
+}
+
+// ----------------------------------------------------------------------------
+// Launch wrappers (defined in the .hip files)
+// ----------------------------------------------------------------------------
+// FFT work is launched per LDS class so that small rings are not held to the
+// occupancy of the largest ones.  Workgroups have FFT_THREADS threads;
+// elems = complex values per thread per FFT stage (lds / FFT_THREADS).
+constexpr int FFT_THREADS = 512;
+struct FftClass {
+    const FftItem* items;
+    int nitems;
+    int lds;     // complex LDS elements per workgroup
+    int elems;   // 2, 8 or 16
+};
+hipError_t launch_fft_forward(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
+hipError_t launch_fft_inverse(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
+hipError_t launch_residual(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
+hipError_t launch_bluestein_init(const FftLen* lens, const int* blue_lens, int nblue, const double2* tw,
+                                 double2* bhat, int lds, hipStream_t st);
+
+struct SeedArgs {
+    const RingDev* rings;
+    const double* start;    // spin 0: lambda_lb (scaled mantissa); spin 2: P, M; [m][r] (SoA for spin 2)
+    const int* startk;      // [m][r]
+    double* mu;
+    int* kk;
+    const int64_t* seedoff;
+    int64_t seedstride;
+    int* lsig;
+    int nrc;
+    int lmax, rn, spin;
+};
+hipError_t launch_seeds(const SeedArgs& a, hipStream_t st);
+
+// prec: 0 FP64, 1 FP32, 2 BF16x3
+hipError_t launch_leg_m2a(const LegArgs& a, int prec, hipStream_t st);
+hipError_t launch_leg_a2m(const LegArgs& a, int prec, hipStream_t st);
+
+}  // namespace sht
