@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Throughput of the batched HEALPix SHT: IQU map triples per second through
+alm2map + map2alm (one step = both directions over the whole batch).
+
+Default workload: nside 512, lmax 1535, 1000 IQU map triples with Gaussian
+random a_lm (C_l^TT = 1/(l+1)^2, C^EE = 0.1 C^TT, C^BB = 0.01 C^TT, TE correlation
+0.5), inputs resident in HBM before timing.  FP64 is the headline `value`; the
+mixed-precision contractions are reported beside it on the same GPU.
+
+Prints one JSON line.  Only N = 1 GPU is supported (the build targets one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "IQU maps/s (alm2map+map2alm) nside 512, FP64 vs mixed; serve p50/p99 ms"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def compact_scale(lmax: int):
+    """sqrt of the per-entry variance of a unit-C_l Gaussian field in the compact
+    (lmax+1)^2 storage: 1 for Re at m = 0, 1/2 for Re and Im at m > 0; and the l
+    of every entry."""
+    import torch
+    L1 = lmax + 1
+    idx = torch.arange(L1 * L1, dtype=torch.int64)
+    col, row = idx // L1, idx % L1
+    is_re = row >= col
+    l = torch.where(is_re, row, row + L1 - col)
+    m = torch.where(is_re, col, L1 - col)
+    cl = 1.0 / (l.double() + 1.0) ** 2
+    cl[l < 2] = 0.0
+    return torch.sqrt(cl) * torch.where(m == 0, 1.0, math.sqrt(0.5)).double()
+
+
+def fill_alm(alm, lmax: int, seed: int, block: int = 25) -> None:
+    """Seeded Gaussian IQU a_lm written block by block on the device."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    s = compact_scale(lmax).to("cuda")
+    n = alm.shape[0]
+    rho = 0.5
+    for k0 in range(0, n, block):
+        k1 = min(n, k0 + block)
+        z = torch.randn((k1 - k0, 3, s.numel()), generator=g, device="cuda", dtype=torch.float64)
+        alm[k0:k1, 0] = s * z[:, 0]
+        alm[k0:k1, 1] = math.sqrt(0.1) * s * (rho * z[:, 0] + math.sqrt(1 - rho * rho) * z[:, 1])
+        alm[k0:k1, 2] = math.sqrt(0.01) * s * z[:, 2]
+        del z
+
+
+def leg_flops(nside: int, lmax: int, spin: int, nmaps: int) -> float:
+    """Algorithmic flops of one direction of the Legendre contraction for nmaps map
+    sets, with the two hemispheres folded (north rings incl. the equator, rn =
+    2 nside): spin 0: 4 rn sum_m (L+1-m); spin 2 (E/B or Q/U): 16 rn sum_m (L+1-max(m,2))."""
+    rn = 2 * nside
+    if spin == 0:
+        rows = sum(lmax + 1 - m for m in range(lmax + 1))
+        return 4.0 * rn * rows * nmaps
+    rows = sum(lmax + 1 - max(m, 2) for m in range(lmax + 1))
+    return 16.0 * rn * rows * nmaps
+
+
+def paper_form_flops(nside: int, lmax: int) -> float:
+    """The paper-form count per IQU triple and direction (all rings, 4 real products
+    for Q/U): 5 * 2 R (L+1)(L+2), R = 4 nside - 1."""
+    return 5 * 2.0 * (4 * nside - 1) * (lmax + 1) * (lmax + 2)
+
+
+def run_precision(sht, args, prec, alm, maps, alm_out):
+    import torch
+    nside, lmax, n = args.nside, args.lmax, args.nmaps
+    t0 = time.perf_counter()
+    p = sht.Plan(nside, lmax, 2, n, precision=prec, chunk=args.chunk)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    log(f"{prec}: plan {init_s:.2f}s, workspace {p.workspace_bytes() / 1e9:.1f} GB, tables {p.table_bytes() / 1e9:.2f} GB")
+    stream = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        p.alm2map(alm, maps, stream)
+        p.map2alm(maps, alm_out, stream)
+        torch.cuda.synchronize()
+        log(f"{prec}: warmup {w + 1}/{args.warmup} done")
+    p.set_profiling(True)
+    p.profile(reset=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for k in range(args.steps):
+        p.alm2map(alm, maps, stream)
+        p.map2alm(maps, alm_out, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = ev0.elapsed_time(ev1)
+    prof = p.profile(reset=True)
+    p.set_profiling(False)
+    p.close()
+    del p
+    per_step = ms / args.steps
+    log(f"{prec}: {per_step:.1f} ms/step ({wall:.2f}s wall for {args.steps} steps)")
+    return {"ms_per_step": per_step, "value": n * 1000.0 / per_step, "init_s": init_s, "stages": prof}
+
+
+def roofline(args, prec, res):
+    """Dominant Legendre kernel's achieved FLOP rate from the live stage timings."""
+    st = res["stages"]
+    cand = {k: v for k, v in st.items() if k.startswith(("m2a", "a2m")) and v[1] > 0}
+    name = max(cand, key=lambda k: cand[k][0])
+    ms, launches = cand[name]
+    spin = 0 if name.endswith("spin0") else 2
+    flops_per_step = leg_flops(args.nside, args.lmax, spin, args.nmaps)
+    achieved = flops_per_step * args.steps / (ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    return {
+        "kernel": {"m2a_spin0": "k_m2a_spin0", "m2a_spin2": "k_m2a_spin2", "a2m_spin0": "k_a2m_spin0",
+                   "a2m_spin2": "k_a2m_spin2"}[name] + ("<double>" if prec == "fp64" else "<float>"),
+        "bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4), "traffic": None,
+        "launches": launches, "avg_launch_ms": round(ms / launches, 3),
+        "flops_per_launch": flops_per_step * args.steps / launches,
+    }
+
+
+def fft_rate(args, prec, res):
+    """Ring-FFT stages: algorithmic HBM bytes (maps in/out + the m-major
+    coefficients written/read once) over their measured time."""
+    es = 8 if prec == "fp64" else 4
+    npix = 12 * args.nside ** 2
+    nring = 4 * args.nside - 1
+    per_map = 8 * npix + 2 * es * nring * (args.lmax + 1)
+    tot = 3 * args.nmaps * per_map * args.steps
+    out = {}
+    for k in ("fft_fwd", "fft_inv"):
+        ms, n = res["stages"][k]
+        if n:
+            out[k] = {"GB/s": round(tot / (ms * 1e-3) / 1e9, 1), "frac_hbm": round(tot / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 3)}
+    return out
+
+
+def cpu_baseline(args):
+    """The oracle on a bounded stratified sample of the same workload: one IQU
+    triple, every `stride`-th ring (alm2map) and every `stride`-th m (map2alm)."""
+    import numpy as np
+    import oracle
+    from paper_2208_10154_amd import synth
+    stride = args.cpu_stride
+    a = synth.gaussian_alm(args.lmax, 1, True, workload=3)[0]
+    m = synth.white_maps(12 * args.nside ** 2, 1, 3, workload=3)[0]
+    t_a2m, t_m2a = oracle.timing_sample_iqu(args.nside, args.lmax, a, m, stride)
+    sec_per_triple = stride * (t_a2m + t_m2a)
+    return {"value": round(1.0 / sec_per_triple, 6), "unit": "IQU map triples/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": (f"1 IQU triple at nside {args.nside}, lmax {args.lmax}: alm2map on every {stride}th ring, "
+                       f"map2alm on every {stride}th m ({t_a2m + t_m2a:.1f} s measured), scaled by {stride}"),
+            "seconds_per_triple": round(sec_per_triple, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nside", type=int, default=512)
+    ap.add_argument("--lmax", type=int, default=None)
+    ap.add_argument("--nmaps", type=int, default=1000, help="IQU map triples per step")
+    ap.add_argument("--chunk", type=int, default=125)
+    ap.add_argument("--precisions", default="fp64,fp32")
+    ap.add_argument("--cpu-stride", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU split "
+              "(map batch or m-range per GPU) is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    if args.lmax is None:
+        args.lmax = 3 * args.nside - 1
+    import torch
+    from paper_2208_10154_amd import sht
+    sht.lib()
+    n, L = args.nmaps, args.lmax
+    log(f"workload nside {args.nside} lmax {L} nmaps {n} (IQU), chunk {args.chunk}")
+    alm = torch.empty((n, 3, (L + 1) ** 2), dtype=torch.float64, device="cuda")
+    fill_alm(alm, L, seed=220810154)
+    maps = torch.empty((n, 3, 12 * args.nside ** 2), dtype=torch.float64, device="cuda")
+    alm_out = torch.empty_like(alm)
+    torch.cuda.synchronize()
+    log(f"inputs resident: {(alm.numel() * 2 + maps.numel()) * 8 / 1e9:.1f} GB")
+    results = {}
+    for prec in args.precisions.split(","):
+        results[prec] = run_precision(sht, args, prec, alm, maps, alm_out)
+    head = "fp64" if "fp64" in results else list(results)[0]
+    r = results[head]
+    line = {
+        "metric": METRIC, "value": round(r["value"], 3), "unit": "IQU map triples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if head == "fp64" else head,
+        "data": "synthetic (seeded Gaussian a_lm, C_l = 1/(l+1)^2 spectra)",
+        "config": {"workload": f"healpix_iqu_nside{args.nside}_lmax{L}_x{n}", "nside": args.nside, "lmax": L,
+                   "map_triples": n, "spin": 2, "chunk": args.chunk, "step": "alm2map+map2alm"},
+        "by_precision": {k: {"value": round(v["value"], 3), "ms_per_step": round(v["ms_per_step"], 3),
+                             "plan_init_s": round(v["init_s"], 2),
+                             "stages_ms_per_step": {s: round(t / args.steps, 3) for s, (t, c) in v["stages"].items() if c}}
+                         for k, v in results.items()},
+        "roofline": roofline(args, head, r),
+        "paper_form_tflops_equiv": round(2 * paper_form_flops(args.nside, L) * n / (r["ms_per_step"] * 1e-3) / 1e12, 2),
+        "fft_hbm": fft_rate(args, head, r),
+    }
+    if "fp64" in results:
+        line["mixed_over_fp64"] = {k: round(v["value"] / results["fp64"]["value"], 3) for k, v in results.items() if k != "fp64"}
+        for k in results:
+            if k != head:
+                line["by_precision"][k]["roofline"] = roofline(args, k, results[k])
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample) ...")
+        line["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

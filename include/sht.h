@@ -115,6 +115,27 @@ int sht_map2alm(sht_plan plan, const double* map, double* alm);
  * synchronises the stream. */
 int sht_map2alm_iter(sht_plan plan, const double* map, double* alm, int niter, double* resid);
 
+/* Stages timed by the optional profiler. */
+enum sht_stage {
+    SHT_STAGE_FFT_FWD = 0,     /* ring FFT + m-unfold (maps -> ring coefficients) */
+    SHT_STAGE_FFT_INV = 1,     /* alias fold + inverse ring FFT */
+    SHT_STAGE_RESIDUAL = 2,    /* iteration residual in the Fourier domain */
+    SHT_STAGE_M2A_SPIN0 = 3,   /* Legendre contraction, map2alm, T */
+    SHT_STAGE_M2A_SPIN2 = 4,   /* Legendre contraction, map2alm, E/B */
+    SHT_STAGE_A2M_SPIN0 = 5,   /* Legendre contraction, alm2map, T */
+    SHT_STAGE_A2M_SPIN2 = 6,   /* Legendre contraction, alm2map, Q/U */
+    SHT_NSTAGE = 7
+};
+
+/* Enable (1) or disable (0) per-stage timing: when enabled every stage's kernel
+ * launches are bracketed by HIP events on the plan's stream.  Off by default. */
+int sht_plan_set_profiling(sht_plan plan, int enable);
+
+/* Synchronise the plan's stream and return, per stage (arrays of SHT_NSTAGE),
+ * the summed device time in milliseconds and the number of timed launches since
+ * the last reset; reset != 0 clears the record. */
+int sht_plan_get_profile(sht_plan plan, double* ms, long long* launches, int reset);
+
 /* Wait for the plan's stream and report any asynchronous device error. */
 int sht_plan_sync(sht_plan plan);
 

@@ -63,6 +63,10 @@ def _L():
         lib.orc_synth_pixels_spin2.argtypes = [L_, L_, _d, _d, L_, _l, _d, _d]
         lib.orc_analyze_lm_spin0.argtypes = [L_, L_, _d, L_, _l, _l, _d]
         lib.orc_analyze_lm_spin2.argtypes = [L_, L_, _d, _d, L_, _l, _l, _d, _d]
+        lib.orc_alm2map_spin0_strided.argtypes = [L_, L_, L_, _d, _d, L_]
+        lib.orc_map2alm_spin0_strided.argtypes = [L_, L_, L_, _d, _d, L_]
+        lib.orc_alm2map_spin2_strided.argtypes = [L_, L_, L_, _d, _d, _d, _d, L_]
+        lib.orc_map2alm_spin2_strided.argtypes = [L_, L_, L_, _d, _d, _d, _d, L_]
         lib.orc_num_threads.restype = I_
         _lib = lib
     return _lib
@@ -208,6 +212,29 @@ def map2alm_iter(nside: int, lmax: int, maps: np.ndarray, niter: int, pol: bool 
             break
         a = a + analyse(nside, lmax, r, pol)
     return a, np.array(res)
+
+
+def timing_sample_iqu(nside: int, lmax: int, alm1: np.ndarray, maps1: np.ndarray, stride: int):
+    """Run the oracle's IQU alm2map on every `stride`-th ring and its map2alm on
+    every `stride`-th m, for ONE map triple (alm1 complex [3, L+1, L+1], maps1
+    [3, Npix]).  Returns (seconds_alm2map, seconds_map2alm) of the sample; the
+    full transforms visit stride times as many rings / m values."""
+    import time
+    L = lmax
+    msk = _tri_mask(L)
+    a = [np.ascontiguousarray(alm1[c][None] * msk, dtype=np.complex128) for c in range(3)]
+    out = np.zeros((3, 1, npix(nside)))
+    t0 = time.perf_counter()
+    _L().orc_alm2map_spin0_strided(nside, L, 1, _p(_c2r(a[0])), _p(out[0]), stride)
+    _L().orc_alm2map_spin2_strided(nside, L, 1, _p(_c2r(a[1])), _p(_c2r(a[2])), _p(out[1]), _p(out[2]), stride)
+    t1 = time.perf_counter()
+    mp = [np.ascontiguousarray(maps1[c][None], dtype=np.float64) for c in range(3)]
+    r = np.zeros((3, 1, L + 1, L + 1), dtype=np.complex128)
+    _L().orc_map2alm_spin0_strided(nside, L, 1, _p(mp[0]), _p(r[0].view(np.float64)), stride)
+    _L().orc_map2alm_spin2_strided(nside, L, 1, _p(mp[1]), _p(mp[2]), _p(r[1].view(np.float64)),
+                                   _p(r[2].view(np.float64)), stride)
+    t2 = time.perf_counter()
+    return t1 - t0, t2 - t1
 
 
 # --------------------------------------------------------------------------- sampled

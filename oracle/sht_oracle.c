@@ -182,7 +182,8 @@ void orc_lambda_spin(long lmax, long m, long s, double theta, double* out)
 
 /* backward transform: T(p) = sum_m e^{i m phi} sum_l a_lm lambda_lm, m = -lmax..lmax,
  * written over m >= 0 with the reality condition (weight 1 for m = 0, 2 for m > 0). */
-void orc_alm2map_spin0(long nside, long lmax, long nmaps, const double* alm, double* map)
+/* rstep > 1 evaluates only every rstep-th ring (a timing sample; other rings untouched) */
+void orc_alm2map_spin0_strided(long nside, long lmax, long nmaps, const double* alm, double* map, long rstep)
 {
     long nring = 4 * nside - 1, npix = 12 * nside * nside, L = lmax;
 #pragma omp parallel
@@ -191,7 +192,7 @@ void orc_alm2map_spin0(long nside, long lmax, long nmaps, const double* alm, dou
         ld* cre = (ld*)malloc(sizeof(ld) * nmaps * (L + 1));
         ld* cim = (ld*)malloc(sizeof(ld) * nmaps * (L + 1));
 #pragma omp for schedule(dynamic)
-        for (long i = 1; i <= nring; ++i) {
+        for (long i = 1; i <= nring; i += rstep) {
             oring r = ring_of(nside, i);
             for (long m = 0; m <= L; ++m) {
                 lam_spin0(L, m, r.z, r.sth, lam);
@@ -222,8 +223,14 @@ void orc_alm2map_spin0(long nside, long lmax, long nmaps, const double* alm, dou
     }
 }
 
-/* forward transform: a_lm = dsigma sum_rings lambda_lm(theta_i) sum_n T(i,n) e^{-i m phi_n} */
-void orc_map2alm_spin0(long nside, long lmax, long nmaps, const double* map, double* alm)
+void orc_alm2map_spin0(long nside, long lmax, long nmaps, const double* alm, double* map)
+{
+    orc_alm2map_spin0_strided(nside, lmax, nmaps, alm, map, 1);
+}
+
+/* forward transform: a_lm = dsigma sum_rings lambda_lm(theta_i) sum_n T(i,n) e^{-i m phi_n};
+ * mstep > 1 evaluates only every mstep-th m (a timing sample) */
+void orc_map2alm_spin0_strided(long nside, long lmax, long nmaps, const double* map, double* alm, long mstep)
 {
     long nring = 4 * nside - 1, npix = 12 * nside * nside, L = lmax;
     ld dsig = 4.0L * PI_L / (ld)npix;
@@ -235,7 +242,7 @@ void orc_map2alm_spin0(long nside, long lmax, long nmaps, const double* map, dou
         ld* aim = (ld*)malloc(sizeof(ld) * nmaps * (L + 1));
         ld* cs = (ld*)malloc(sizeof(ld) * 2 * 4 * nside);
 #pragma omp for schedule(dynamic)
-        for (long m = 0; m <= L; ++m) {
+        for (long m = 0; m <= L; m += mstep) {
             for (long j = 0; j < nmaps * (L + 1); ++j) are[j] = aim[j] = 0.0L;
             for (long i = 1; i <= nring; ++i) {
                 oring r = ring_of(nside, i);
@@ -261,6 +268,11 @@ void orc_map2alm_spin0(long nside, long lmax, long nmaps, const double* map, dou
     }
 }
 
+void orc_map2alm_spin0(long nside, long lmax, long nmaps, const double* map, double* alm)
+{
+    orc_map2alm_spin0_strided(nside, lmax, nmaps, map, alm, 1);
+}
+
 /* ------------------------------------------------------------------------- */
 /* spin 2: Q + iU = sum_{l>=2} sum_{m=-l..l} a_{2,lm} {}_2Y_lm with           */
 /* a_{2,lm} = -(a_E,lm + i a_B,lm) (inverse of eq. alm-EB), all m.            */
@@ -277,8 +289,8 @@ static void get_eb(const double* aE, const double* aB, long k, long l, long m, l
     *bi = sg * cj * (ld)ALM(aB, k, l, am, L)[1];
 }
 
-void orc_alm2map_spin2(long nside, long lmax, long nmaps, const double* aE, const double* aB,
-                       double* Q, double* U)
+void orc_alm2map_spin2_strided(long nside, long lmax, long nmaps, const double* aE, const double* aB,
+                               double* Q, double* U, long rstep)
 {
     long nring = 4 * nside - 1, npix = 12 * nside * nside, L = lmax;
     long nm = 2 * L + 1;
@@ -288,7 +300,7 @@ void orc_alm2map_spin2(long nside, long lmax, long nmaps, const double* aE, cons
         ld* cre = (ld*)malloc(sizeof(ld) * nmaps * nm);
         ld* cim = (ld*)malloc(sizeof(ld) * nmaps * nm);
 #pragma omp for schedule(dynamic)
-        for (long i = 1; i <= nring; ++i) {
+        for (long i = 1; i <= nring; i += rstep) {
             oring r = ring_of(nside, i);
             for (long m = -L; m <= L; ++m) {
                 lam_spin(L, m, 2, r.z, lam);
@@ -325,9 +337,15 @@ void orc_alm2map_spin2(long nside, long lmax, long nmaps, const double* aE, cons
     }
 }
 
+void orc_alm2map_spin2(long nside, long lmax, long nmaps, const double* aE, const double* aB,
+                       double* Q, double* U)
+{
+    orc_alm2map_spin2_strided(nside, lmax, nmaps, aE, aB, Q, U, 1);
+}
+
 /* a_{+-2,lm} = dsigma sum_p (Q +- iU)(p) {}_{+-2}Y*_lm(p); then eq. alm-EB. m >= 0. */
-void orc_map2alm_spin2(long nside, long lmax, long nmaps, const double* Q, const double* U,
-                       double* aE, double* aB)
+void orc_map2alm_spin2_strided(long nside, long lmax, long nmaps, const double* Q, const double* U,
+                               double* aE, double* aB, long mstep)
 {
     long nring = 4 * nside - 1, npix = 12 * nside * nside, L = lmax;
     ld dsig = 4.0L * PI_L / (ld)npix;
@@ -340,7 +358,7 @@ void orc_map2alm_spin2(long nside, long lmax, long nmaps, const double* Q, const
         ld* acc = (ld*)malloc(sizeof(ld) * 4 * nmaps * (L + 1)); /* a_2 re,im ; a_-2 re,im */
         ld* cs = (ld*)malloc(sizeof(ld) * 2 * 4 * nside);
 #pragma omp for schedule(dynamic)
-        for (long m = 0; m <= L; ++m) {
+        for (long m = 0; m <= L; m += mstep) {
             for (long j = 0; j < 4 * nmaps * (L + 1); ++j) acc[j] = 0.0L;
             for (long i = 1; i <= nring; ++i) {
                 oring r = ring_of(nside, i);
@@ -379,6 +397,12 @@ void orc_map2alm_spin2(long nside, long lmax, long nmaps, const double* Q, const
         }
         free(lp); free(lm); free(acc); free(cs);
     }
+}
+
+void orc_map2alm_spin2(long nside, long lmax, long nmaps, const double* Q, const double* U,
+                       double* aE, double* aB)
+{
+    orc_map2alm_spin2_strided(nside, lmax, nmaps, Q, U, aE, aB, 1);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -80,9 +80,33 @@ struct sht_plan_s {
     size_t F_bytes = 0;
     double* norms = nullptr;
     size_t table_bytes = 0;
+
+    // optional per-stage profiling
+    bool profiling = false;
+    struct Rec { int stage; hipEvent_t a, b; };
+    std::vector<Rec> recs;
 };
 
 namespace {
+
+// Brackets the launches of one stage with HIP events when profiling is on.
+struct StageTimer {
+    sht_plan p;
+    int stage;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(sht_plan p_, int stage_) : p(p_), stage(stage_)
+    {
+        if (!p->profiling) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        (void)hipEventRecord(a, p->stream);
+    }
+    ~StageTimer()
+    {
+        if (!a) return;
+        (void)hipEventRecord(b, p->stream);
+        p->recs.push_back(sht_plan_s::Rec{stage, a, b});
+    }
+};
 
 int dev_alloc(sht_plan p, Dev& d, size_t bytes)
 {
@@ -496,9 +520,13 @@ int prep(sht_plan p)
 int run_a2m(sht_plan p, const double* alm, int nm)
 {
     LegArgs a = leg_args(p, p->s0, const_cast<double*>(alm), nm);
-    HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
+    {
+        StageTimer t(p, SHT_STAGE_A2M_SPIN0);
+        HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
+    }
     if (p->spin == 2) {
         LegArgs b = leg_args(p, p->s2, const_cast<double*>(alm), nm);
+        StageTimer t(p, SHT_STAGE_A2M_SPIN2);
         HIPCHK(launch_leg_a2m(b, p->prec, p->stream));
     }
     return SHT_OK;
@@ -510,11 +538,15 @@ int run_m2a(sht_plan p, double* alm, int nm, int accumulate)
     LegArgs a = leg_args(p, p->s0, alm, nm);
     a.scale = dsig;
     a.accumulate = accumulate;
-    HIPCHK(launch_leg_m2a(a, p->prec, p->stream));
+    {
+        StageTimer t(p, SHT_STAGE_M2A_SPIN0);
+        HIPCHK(launch_leg_m2a(a, p->prec, p->stream));
+    }
     if (p->spin == 2) {
         LegArgs b = leg_args(p, p->s2, alm, nm);
         b.scale = dsig;
         b.accumulate = accumulate;
+        StageTimer t(p, SHT_STAGE_M2A_SPIN2);
         HIPCHK(launch_leg_m2a(b, p->prec, p->stream));
     }
     return SHT_OK;
@@ -530,8 +562,18 @@ int check_ready(sht_plan p)
     return SHT_OK;
 }
 
+void drop_records(sht_plan p)
+{
+    for (auto& r : p->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    p->recs.clear();
+}
+
 void destroy_all(sht_plan p)
 {
+    drop_records(p);
     for (auto& d : p->owned)
         if (d.p) (void)hipFree(d.p);
     if (p->items_dev.p) (void)hipFree(p->items_dev.p);
@@ -660,6 +702,7 @@ int sht_alm2map(sht_plan p, const double* alm, double* map)
         if ((rc = run_a2m(p, alm + k0 * astride, nm))) return rc;
         FftArgs f = fft_args(p, nm);
         f.maps_out = map + k0 * mstride;
+        StageTimer t(p, SHT_STAGE_FFT_INV);
         HIPCHK(launch_fft_inverse(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
     }
     return SHT_OK;
@@ -677,7 +720,10 @@ int sht_map2alm(sht_plan p, const double* map, double* alm)
         int nm = std::min(p->chunk, p->nmaps - k0);
         FftArgs f = fft_args(p, nm);
         f.maps_in = map + k0 * mstride;
-        HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+        {
+            StageTimer t(p, SHT_STAGE_FFT_FWD);
+            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+        }
         if ((rc = run_m2a(p, alm + k0 * astride, nm, 0))) return rc;
     }
     return SHT_OK;
@@ -700,7 +746,10 @@ int sht_map2alm_iter(sht_plan p, const double* map, double* alm, int niter, doub
         FftArgs f = fft_args(p, nm);
         f.maps_in = map + k0 * mstride;
         f.F = p->F;
-        HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+        {
+            StageTimer t(p, SHT_STAGE_FFT_FWD);
+            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+        }
         if ((rc = run_m2a(p, a, nm, 0))) return rc;
         const int rounds = niter + (resid ? 1 : 0);
         for (int it = 1; it <= rounds; ++it) {
@@ -710,7 +759,10 @@ int sht_map2alm_iter(sht_plan p, const double* map, double* alm, int niter, doub
             r.norms = resid ? p->norms : nullptr;
             r.iteration_sub = (it <= niter);
             if (resid) HIPCHK(hipMemsetAsync(p->norms, 0, (size_t)nm * p->ncomp * sizeof(double), p->stream));
-            HIPCHK(launch_residual(r, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+            {
+                StageTimer t(p, SHT_STAGE_RESIDUAL);
+                HIPCHK(launch_residual(r, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+            }
             if (resid) {
                 hn.resize((size_t)nm * p->ncomp);
                 HIPCHK(hipMemcpyAsync(hn.data(), p->norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
@@ -725,6 +777,29 @@ int sht_map2alm_iter(sht_plan p, const double* map, double* alm, int niter, doub
         double cnt = (double)p->nmaps * p->ncomp * (double)p->npix;
         for (int n = 0; n <= niter; ++n) resid[n] = std::sqrt(sums[n] / cnt);
     }
+    return SHT_OK;
+}
+
+int sht_plan_set_profiling(sht_plan p, int enable)
+{
+    if (!p) return fail(SHT_ERR_ARG, "null plan");
+    p->profiling = (enable != 0);
+    return SHT_OK;
+}
+
+int sht_plan_get_profile(sht_plan p, double* ms, long long* launches, int reset)
+{
+    if (!p) return fail(SHT_ERR_ARG, "null plan");
+    if (!ms || !launches) return fail(SHT_ERR_ARG, "null output array");
+    HIPCHK(hipStreamSynchronize(p->stream));
+    for (int i = 0; i < SHT_NSTAGE; ++i) { ms[i] = 0.0; launches[i] = 0; }
+    for (auto& r : p->recs) {
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+        ms[r.stage] += t;
+        launches[r.stage] += 1;
+    }
+    if (reset) drop_records(p);
     return SHT_OK;
 }
 

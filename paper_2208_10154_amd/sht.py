@@ -23,7 +23,9 @@ PRECISIONS = {"fp64": SHT_FP64, "fp32": SHT_FP32, "bf16x3": SHT_BF16X3}
 EXPORTS = ["sht_plan_create", "sht_plan_destroy", "sht_plan_set_precision", "sht_plan_set_stream",
            "sht_plan_set_nmaps", "sht_plan_set_chunk", "sht_plan_workspace_bytes", "sht_plan_table_bytes",
            "sht_plan_set_workspace", "sht_alm2map", "sht_map2alm", "sht_map2alm_iter", "sht_plan_sync",
-           "sht_last_error"]
+           "sht_last_error", "sht_plan_set_profiling", "sht_plan_get_profile"]
+
+STAGES = ["fft_fwd", "fft_inv", "residual", "m2a_spin0", "m2a_spin2", "a2m_spin0", "a2m_spin2"]
 
 _lib = None
 
@@ -58,6 +60,8 @@ def lib() -> ctypes.CDLL:
         L.sht_map2alm_iter.argtypes = [P, V, V, I, D]
         L.sht_plan_sync.argtypes = [P]
         L.sht_last_error.restype = ctypes.c_char_p
+        L.sht_plan_set_profiling.argtypes = [P, I]
+        L.sht_plan_get_profile.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), I]
         for name in EXPORTS:
             if name != "sht_plan_workspace_bytes" and name != "sht_plan_table_bytes" and name != "sht_last_error":
                 getattr(L, name).restype = I
@@ -155,6 +159,16 @@ class Plan:
                                       self._ptr(alm, self.alm_shape(), "alm"), int(niter),
                                       ctypes.cast(res, ctypes.POINTER(ctypes.c_double)) if res is not None else None))
         return list(res) if res is not None else None
+
+    def set_profiling(self, enable: bool) -> None:
+        _check(lib().sht_plan_set_profiling(self._h, 1 if enable else 0))
+
+    def profile(self, reset: bool = True) -> dict:
+        """{stage: (milliseconds, launches)} since the last reset (synchronises)."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = (ctypes.c_longlong * len(STAGES))()
+        _check(lib().sht_plan_get_profile(self._h, ms, n, 1 if reset else 0))
+        return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
 
     def sync(self) -> None:
         _check(lib().sht_plan_sync(self._h))
