@@ -66,7 +66,8 @@ enum sht_precision {
 /* Create a plan for HEALPix resolution nside, band limit lmax and spin 0 (T maps)
  * or 2 (IQU map triples), for batches of up to nmaps map sets per call.
  * Requires 1 <= nside <= 8192, 0 <= lmax <= 4*nside-1 (spin 2: lmax >= 2),
- * nmaps >= 1.  Builds the ring tables, FFT plans and Legendre seed tables on the
+ * nmaps >= 1 (SHT_ERR_ARG otherwise); this build supports nside <= 1024 and
+ * lmax <= 4094 (SHT_ERR_UNSUPPORTED beyond).  Builds the ring tables, FFT plans and Legendre seed tables on the
  * current HIP device (the paper's once-only initialisation, Sec. 3.3) and
  * allocates the workspace for one chunk of map sets (see sht_plan_set_chunk). */
 int sht_plan_create(sht_plan* out, int nside, int lmax, int spin, int nmaps);
@@ -124,7 +125,8 @@ enum sht_stage {
     SHT_STAGE_M2A_SPIN2 = 4,   /* Legendre contraction, map2alm, E/B */
     SHT_STAGE_A2M_SPIN0 = 5,   /* Legendre contraction, alm2map, T */
     SHT_STAGE_A2M_SPIN2 = 6,   /* Legendre contraction, alm2map, Q/U */
-    SHT_NSTAGE = 7
+    SHT_STAGE_ALM_LAYOUT = 7,  /* compact <-> m-major coefficient layout (with dsigma) */
+    SHT_NSTAGE = 8
 };
 
 /* Enable (1) or disable (0) per-stage timing: when enabled every stage's kernel

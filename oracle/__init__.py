@@ -278,26 +278,36 @@ def analyze_lm(nside: int, lmax: int, map1: np.ndarray, ls, ms, pol: bool = Fals
 
 
 # --------------------------------------------------------------------------- compact storage
+def _compact_index(L: int):
+    """Flat compact positions of Re a_lm (all l >= m) and Im a_lm (m >= 1), in the
+    order of the (l, m) lists returned: Re at (row l, col m), Im at
+    (row l-m, col L+1-m); flat index col*(L+1) + row (Appendix A.2)."""
+    l, m = np.tril_indices(L + 1)
+    re = m * (L + 1) + l
+    sel = m >= 1
+    im = (L + 1 - m[sel]) * (L + 1) + (l[sel] - m[sel])
+    return l, m, re, sel, im
+
+
 def to_compact(alm: np.ndarray) -> np.ndarray:
     """Complex [..., L+1, L+1] -> the paper's compact real (L+1)x(L+1) matrix
     (Appendix A.2): Re a_lm at (row l, col m); Im a_lm (m >= 1) at
     (row l - m, col L + 1 - m).  0-based, stored column-major: flat index
     col * (L+1) + row."""
     L = alm.shape[-1] - 1
+    l, m, re, sel, im = _compact_index(L)
     out = np.zeros(alm.shape[:-2] + ((L + 1) * (L + 1),))
-    for m in range(L + 1):
-        for l in range(m, L + 1):
-            out[..., m * (L + 1) + l] = alm[..., l, m].real
-            if m >= 1:
-                out[..., (L + 1 - m) * (L + 1) + (l - m)] = alm[..., l, m].imag
+    vals = alm[..., l, m]
+    out[..., re] = vals.real
+    out[..., im] = vals[..., sel].imag
     return out
 
 
 def from_compact(c: np.ndarray, lmax: int) -> np.ndarray:
     L = lmax
+    l, m, re, sel, im = _compact_index(L)
     out = np.zeros(c.shape[:-1] + (L + 1, L + 1), dtype=np.complex128)
-    for m in range(L + 1):
-        for l in range(m, L + 1):
-            im = c[..., (L + 1 - m) * (L + 1) + (l - m)] if m >= 1 else 0.0
-            out[..., l, m] = c[..., m * (L + 1) + l] + 1j * im
+    vals = c[..., re].astype(np.complex128)
+    vals[..., sel] += 1j * c[..., im]
+    out[..., l, m] = vals
     return out

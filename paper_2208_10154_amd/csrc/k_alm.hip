@@ -1,0 +1,157 @@
+// Coefficient layout changes between the paper's compact storage and the m-major
+// operand layout of the Legendre kernels (HIP, gfx950).
+//
+// The compact storage (Appendix A.2) keeps, per map and component, the real part
+// of a_lm at (row l, col m) and the imaginary part at (row l-m, col lmax+1-m) of an
+// (lmax+1)^2 column-major square, so for one m each part is a contiguous run in l.
+// The contraction wants, per m, rows of l with the maps of the batch along the
+// row: A[m][l][2k + part].  These kernels move 64 l x 32 maps tiles through LDS so
+// both sides are read and written in contiguous runs.  They also carry the scalar
+// work of the boundary: dsigma and accumulation for map2alm (the paper's GEMM
+// alpha/beta, Sec. 3.1 item 7) and the B <-> iB change of variable of Sec. 2.3.
+#include "sht_internal.h"
+
+namespace sht {
+namespace {
+
+constexpr int NT = 256;
+constexpr int TLB = 64;  // l per tile (= TL)
+constexpr int TK = 32;   // maps per tile
+
+__device__ __forceinline__ int64_t calm(int L, int l, int m, int part)
+{
+    if (part == 0) return (int64_t)m * (L + 1) + l;
+    if (m == 0) return -1;
+    return (int64_t)(L + 1 - m) * (L + 1) + (l - m);
+}
+
+__device__ __forceinline__ void decode(const int* off, int lmax, int C, int g, int& m, int& lt, int& kb)
+{
+    int lo = 0, hi = lmax + 1;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] * C <= g) lo = mid; else hi = mid;
+    }
+    m = lo;
+    int r = g - off[m] * C;
+    int nlt = off[m + 1] - off[m];
+    kb = r / nlt;
+    lt = r - kb * nlt;
+}
+
+// compact (FP64) -> m-major operand rows (T = double or float).
+// comp: component of the alm array; kind 0 = plain (T or E), 1 = B stored as B' = i a_B.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
+{
+    __shared__ double tile[TLB][2 * TK + 1];
+    const int comp = a.comp0 + blockIdx.y;
+    const int kind = (a.spin == 2 && comp == 2) ? 1 : 0;
+    int m, lt, kb;
+    decode(a.tileoff, a.lmax, a.kblocks, blockIdx.x, m, lt, kb);
+    const int L = a.lmax;
+    const int lb = lbase(a.spin, m);
+    const int l0 = lb + lt * TLB;
+    const int64_t csz = (int64_t)(L + 1) * (L + 1);
+    for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+        const int part = e / (TK * TLB);
+        const int kk = (e / TLB) % TK;
+        const int li = e % TLB;
+        const int l = l0 + li, k = kb * TK + kk;
+        double v = 0.0;
+        if (l <= L && k < a.nmaps) {
+            const double* base = a.alm_in + (int64_t)k * a.almstride + comp * csz;
+            if (kind == 0) {
+                int64_t o = calm(L, l, m, part);
+                if (o >= 0) v = base[o];
+            } else if (part == 0) {  // Re B' = -Im a_B
+                int64_t o = calm(L, l, m, 1);
+                if (o >= 0) v = -base[o];
+            } else {                 // Im B' = Re a_B
+                v = base[calm(L, l, m, 0)];
+            }
+        }
+        tile[li][2 * kk + part] = v;
+    }
+    __syncthreads();
+    T* A = static_cast<T*>(a.A) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
+    for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+        const int li = e / (2 * TK), c = e % (2 * TK);
+        if (l0 + li <= L) A[(int64_t)li * a.ldx + c] = (T)tile[li][c];
+    }
+}
+
+// m-major rows -> compact (FP64): alm = scale * A (or alm += scale * A).
+// kind 1 converts B' back: Re a_B = Im B', Im a_B = -Re B'.  Spin-2 components
+// have no l < 2 coefficients: the first tile of m < 2 clears them (store mode).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
+{
+    __shared__ double tile[TLB][2 * TK + 1];
+    const int comp = a.comp0 + blockIdx.y;
+    const int kind = (a.spin == 2 && comp == 2) ? 1 : 0;
+    int m, lt, kb;
+    decode(a.tileoff, a.lmax, a.kblocks, blockIdx.x, m, lt, kb);
+    const int L = a.lmax;
+    const int lb = lbase(a.spin, m);
+    const int l0 = lb + lt * TLB;
+    const int64_t csz = (int64_t)(L + 1) * (L + 1);
+    const T* A = static_cast<const T*>(a.A) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
+    for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+        const int li = e / (2 * TK), c = e % (2 * TK);
+        tile[li][c] = (l0 + li <= L) ? (double)A[(int64_t)li * a.ldx + c] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+        const int part = e / (TK * TLB);
+        const int kk = (e / TLB) % TK;
+        const int li = e % TLB;
+        const int l = l0 + li, k = kb * TK + kk;
+        if (l > L || k >= a.nmaps) continue;
+        double* base = a.alm_out + (int64_t)k * a.almstride + comp * csz;
+        double v;
+        int64_t o;
+        if (kind == 0) {
+            v = tile[li][2 * kk + part];
+            o = calm(L, l, m, part);
+        } else if (part == 0) {  // Re a_B = Im B'
+            v = tile[li][2 * kk + 1];
+            o = calm(L, l, m, 0);
+        } else {                 // Im a_B = -Re B'
+            v = -tile[li][2 * kk];
+            o = calm(L, l, m, 1);
+        }
+        if (o < 0) continue;
+        v *= a.scale;
+        if (a.accumulate) base[o] += v; else base[o] = v;
+    }
+    if (a.spin == 2 && !a.accumulate && m < 2 && lt == 0) {
+        for (int e = threadIdx.x; e < TK * 2 * 2; e += NT) {
+            const int kk = e / 4, part = (e >> 1) & 1, l = m + (e & 1);
+            const int k = kb * TK + kk;
+            if (l >= 2 || k >= a.nmaps) continue;
+            int64_t o = calm(L, l, m, part);
+            if (o >= 0) a.alm_out[(int64_t)k * a.almstride + comp * csz + o] = 0.0;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_alm_to_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st)
+{
+    dim3 grid(a.ntiles * a.kblocks, ncompl);
+    if (prec == 0) hipLaunchKernelGGL(k_to_mmajor<double>, grid, dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL(k_to_mmajor<float>, grid, dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_alm_from_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st)
+{
+    dim3 grid(a.ntiles * a.kblocks, ncompl);
+    if (prec == 0) hipLaunchKernelGGL(k_from_mmajor<double>, grid, dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL(k_from_mmajor<float>, grid, dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace sht

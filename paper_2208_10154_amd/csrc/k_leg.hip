@@ -2,132 +2,162 @@
 //
 // For every m the paper reduces the transform to dense products over the map
 // batch (Sec. 2.2, eq. "matrix form"):
-//     map2alm   A_m = dsigma P_m T_m      (contracts rings)
-//     alm2map   T_m = P_m^t A_m           (contracts l)
+//     map2alm   A_m = P_m T_m      (contracts rings; dsigma is applied later)
+//     alm2map   T_m = P_m^t A_m    (contracts l)
 // and, for polarisation, the real 2x2 block form of Sec. 2.3,
 //     [A^E; iA^B]_m = [[F+, F-], [F-, F+]]_m [Q; iU]_m,   F+- = -lambda+-,
 //     lambda+- = (2lambda +- -2lambda)/2 (Appendix A.2),
 // with iA^B and iU as the natural real variables (Sec. 3.1 item 1).
 //
-// Here the P_m / F+- tiles are never stored: each workgroup runs the three-term
-// recursion in FP64 registers from the plan's seed table (exponent-scaled, see
-// k_seed.hip), writes the tile to LDS in the operand precision and feeds it to
-// MFMA against tiles of T_m (map2alm) or A_m (alm2map) staged in LDS.  The two
-// hemispheres are folded with lambda_lm(-z) = (-1)^{l+m} lambda_lm(z) (and
-// lambda+-(-z) = +-(-1)^{l+m} lambda+-(z)), so only northern rings are contracted:
-// rows of even l-m pair with T_N + T_S, odd ones with T_N - T_S.  Column pairs
-// (2k, 2k+1) of the T and A tiles are the real and imaginary parts of map k
-// (Sec. 3.1 item 1, real-only arithmetic).
+// The P_m / F+- tiles are never stored in HBM: each workgroup runs the
+// three-term recursion in FP64 registers from the plan's seed table
+// (exponent-scaled, see k_seed.hip) and writes the tile to a double-buffered LDS
+// array in the operand precision; the recursion for the next tile is interleaved
+// with the MFMAs of the current one.  The other MFMA operand (ring coefficients
+// T_m for map2alm, coefficients A_m for alm2map) comes straight from HBM in the
+// m-major layouts [m][ring][column] and [m][l][column] into registers, one tile
+// ahead.  The two hemispheres are folded with lambda_lm(-z) = (-1)^{l+m}
+// lambda_lm(z) (lambda+-(-z) = +-(-1)^{l+m} lambda+-(z)): only northern rings are
+// contracted, rows of even l-m against T_N + T_S and odd ones against T_N - T_S.
+// Column pairs (2k, 2k+1) are the real and imaginary parts of map k.
 #include "leg_common.h"
 
 namespace sht {
 namespace {
 
 constexpr int NT = 256;
-constexpr int HALF = TL / 2;  // rows of one parity class per tile
+constexpr int HALF = TL / 2;   // rows of one parity class per l tile
+constexpr int KS = 8;          // MFMA K-steps per tile (32 rings or 32 l of a parity / 4)
+constexpr int STEPS_PER_KS = 4;  // recursion steps interleaved per K-step (KS*4 >= SEG-1)
+static_assert(KS * STEPS_PER_KS >= SEG - 1, "interleaved fill must finish within one tile");
 
 // ----------------------------------------------------------------------------
-// seed loading and segment fill
+// recursion state of one (ring, segment) fill item
 // ----------------------------------------------------------------------------
-struct Seed0 { double v0, v1; int k; };
-struct Seed2 { double p0, p1, q0, q1; int k; };
+struct Fill0 {
+    double v0, v1, x;
+    int k, t, cnt;
+    bool on;
+};
+struct Fill2 {
+    double p0, p1, q0, q1, x;
+    int k, t, cnt;
+    bool on;
+};
 
-__device__ __forceinline__ Seed0 load_seed0(const LegArgs& a, int m, int j, int r)
+__device__ __forceinline__ void seed_index(const LegArgs& a, int m, int j, int r, int64_t& idx)
 {
-    int64_t idx = a.seedoff[m] + (int64_t)j * a.rn + r;
-    Seed0 s;
-    s.v0 = a.mu[idx];
-    s.v1 = a.mu[a.seedstride + idx];
-    s.k = a.kk[idx];
-    return s;
-}
-__device__ __forceinline__ Seed2 load_seed2(const LegArgs& a, int m, int j, int r)
-{
-    int64_t idx = a.seedoff[m] + (int64_t)j * a.rn + r;
-    Seed2 s;
-    s.p0 = a.mu[idx];
-    s.p1 = a.mu[a.seedstride + idx];
-    s.q0 = a.mu[2 * a.seedstride + idx];
-    s.q1 = a.mu[3 * a.seedstride + idx];
-    s.k = a.kk[idx];
-    return s;
+    idx = a.seedoff[m] + (int64_t)j * a.rn + r;
 }
 
-// Fill SEG values of lambda for one (ring, segment) into the two parity classes.
-// emit(i, v) receives local row i (0..SEG-1 within the segment) and the value.
+// Starts a fill item: loads its seed (values at rows 0 and 1 of the segment).
+__device__ __forceinline__ void fill_start(Fill0& f, const LegArgs& a, int m, int j, int r, int cnt, bool on)
+{
+    f.on = on && cnt > 0;
+    f.cnt = cnt;
+    f.t = 0;
+    f.v0 = f.v1 = 0.0;
+    f.k = 1;
+    f.x = 0.0;
+    if (f.on) {
+        int64_t idx;
+        seed_index(a, m, j, r, idx);
+        f.v0 = a.mu[idx];
+        f.v1 = a.mu[a.seedstride + idx];
+        f.k = a.kk[idx];
+        f.x = a.rings[r].z;
+    }
+}
+__device__ __forceinline__ void fill_start(Fill2& f, const LegArgs& a, int m, int j, int r, int cnt, bool on)
+{
+    f.on = on && cnt > 0;
+    f.cnt = cnt;
+    f.t = 0;
+    f.p0 = f.p1 = f.q0 = f.q1 = 0.0;
+    f.k = 1;
+    f.x = 0.0;
+    if (f.on) {
+        int64_t idx;
+        seed_index(a, m, j, r, idx);
+        f.p0 = a.mu[idx];
+        f.p1 = a.mu[a.seedstride + idx];
+        f.q0 = a.mu[2 * a.seedstride + idx];
+        f.q1 = a.mu[3 * a.seedstride + idx];
+        f.k = a.kk[idx];
+        f.x = a.rings[r].z;
+    }
+}
+
+// One step: at t = 0 emits rows 0 and 1 (the seed pair), later steps emit row t.
+// Rows at or beyond cnt (past lmax) and items that are off emit zeros.
 template <typename Emit>
-__device__ __forceinline__ void fill_spin0(Seed0 s, double x, int cnt, const double* coef, Emit emit)
+__device__ __forceinline__ void fill_step(Fill0& f, const double* coef, Emit emit)
 {
-    double v0 = s.v0, v1 = s.v1;
-    int k = s.k;
-    emit(0, k == 0 ? v0 : 0.0);
-    if (cnt > 1) emit(1, k == 0 ? v1 : 0.0);
-    for (int t = 2; t < cnt; ++t) {
-        double v2 = (coef[2 * t] * x) * v1 - coef[2 * t + 1] * v0;
-        if (k > 0 && fabs(v2) > RESCALE_AT) {
-            v2 *= SCALE_DOWN;
-            v1 *= SCALE_DOWN;
-            --k;
-        }
-        emit(t, k == 0 ? v2 : 0.0);
-        v0 = v1;
-        v1 = v2;
+    if (f.t >= SEG) return;
+    if (f.t == 0) {
+        emit(0, (f.on && f.k == 0) ? f.v0 : 0.0);
+        emit(1, (f.on && f.k == 0 && f.cnt > 1) ? f.v1 : 0.0);
+        f.t = 2;
+        return;
     }
+    const int t = f.t;
+    double v2 = (coef[2 * t] * f.x) * f.v1 - coef[2 * t + 1] * f.v0;
+    if (f.k > 0 && fabs(v2) > RESCALE_AT) {
+        v2 *= SCALE_DOWN;
+        f.v1 *= SCALE_DOWN;
+        --f.k;
+    }
+    emit(t, (f.on && f.k == 0 && t < f.cnt) ? v2 : 0.0);
+    f.v0 = f.v1;
+    f.v1 = v2;
+    f.t = t + 1;
 }
 
-// emit(i, f_plus, f_minus) with F+- = -(P +- M)/2
+// emit(row, F+, F-) with F+- = -(P +- M)/2
 template <typename Emit>
-__device__ __forceinline__ void fill_spin2(Seed2 s, double x, int cnt, const double* coef, Emit emit)
+__device__ __forceinline__ void fill_step(Fill2& f, const double* coef, Emit emit)
 {
-    double p0 = s.p0, p1 = s.p1, q0 = s.q0, q1 = s.q1;
-    int k = s.k;
-    if (k == 0) emit(0, -0.5 * (p0 + q0), -0.5 * (p0 - q0)); else emit(0, 0.0, 0.0);
-    if (cnt > 1) {
-        if (k == 0) emit(1, -0.5 * (p1 + q1), -0.5 * (p1 - q1)); else emit(1, 0.0, 0.0);
+    if (f.t >= SEG) return;
+    if (f.t == 0) {
+        bool z0 = f.on && f.k == 0, z1 = z0 && f.cnt > 1;
+        emit(0, z0 ? -0.5 * (f.p0 + f.q0) : 0.0, z0 ? -0.5 * (f.p0 - f.q0) : 0.0);
+        emit(1, z1 ? -0.5 * (f.p1 + f.q1) : 0.0, z1 ? -0.5 * (f.p1 - f.q1) : 0.0);
+        f.t = 2;
+        return;
     }
-    for (int t = 2; t < cnt; ++t) {
-        double ax = coef[3 * t] * x, be = coef[3 * t + 1], ga = coef[3 * t + 2];
-        double p2 = (ax + be) * p1 - ga * p0;
-        double q2 = (ax - be) * q1 - ga * q0;
-        if (k > 0 && fmax(fabs(p2), fabs(q2)) > RESCALE_AT) {
-            p2 *= SCALE_DOWN; p1 *= SCALE_DOWN;
-            q2 *= SCALE_DOWN; q1 *= SCALE_DOWN;
-            --k;
-        }
-        if (k == 0) emit(t, -0.5 * (p2 + q2), -0.5 * (p2 - q2)); else emit(t, 0.0, 0.0);
-        p0 = p1; p1 = p2;
-        q0 = q1; q1 = q2;
+    const int t = f.t;
+    const double ax = coef[3 * t] * f.x, be = coef[3 * t + 1], ga = coef[3 * t + 2];
+    double p2 = (ax + be) * f.p1 - ga * f.p0;
+    double q2 = (ax - be) * f.q1 - ga * f.q0;
+    if (f.k > 0 && fmax(fabs(p2), fabs(q2)) > RESCALE_AT) {
+        p2 *= SCALE_DOWN; f.p1 *= SCALE_DOWN;
+        q2 *= SCALE_DOWN; f.q1 *= SCALE_DOWN;
+        --f.k;
     }
+    bool z = f.on && f.k == 0 && t < f.cnt;
+    emit(t, z ? -0.5 * (p2 + q2) : 0.0, z ? -0.5 * (p2 - q2) : 0.0);
+    f.p0 = f.p1; f.p1 = p2;
+    f.q0 = f.q1; f.q1 = q2;
+    f.t = t + 1;
 }
 
-// coefficients for the TL rows starting at l0: spin 0 -> 2 per row, spin 2 -> 3 per row
+// recursion coefficients of row i = l - l0 (i < TL): spin 0 -> 2 per row, spin 2 -> 3
 template <int SPIN>
-__device__ __forceinline__ void make_coef(double* coef, int l0, int m)
+__device__ __forceinline__ void coef_row(double* coef, int i, int l0, int m)
 {
-    if (threadIdx.x < TL) {
-        int l = l0 + threadIdx.x;
-        if (SPIN == 0) {
-            double a, ab;
-            coef_spin0(l, m, a, ab);
-            coef[2 * threadIdx.x] = a;
-            coef[2 * threadIdx.x + 1] = ab;
-        } else {
-            double al, be, ga;
-            coef_spin2(l, m, al, be, ga);
-            coef[3 * threadIdx.x] = al;
-            coef[3 * threadIdx.x + 1] = be;
-            coef[3 * threadIdx.x + 2] = ga;
-        }
+    const int l = l0 + i;
+    if (SPIN == 0) {
+        double a, ab;
+        coef_spin0(l, m, a, ab);
+        coef[2 * i] = a;
+        coef[2 * i + 1] = ab;
+    } else {
+        double al, be, ga;
+        coef_spin2(l, m, al, be, ga);
+        coef[3 * i] = al;
+        coef[3 * i + 1] = be;
+        coef[3 * i + 2] = ga;
     }
-}
-
-// compact-storage address of (l, m, part) relative to the component base;
-// part 0 = Re, 1 = Im.  Returns -1 for Im at m = 0 (not stored).
-__device__ __forceinline__ int64_t calm(int L, int l, int m, int part)
-{
-    if (part == 0) return (int64_t)m * (L + 1) + l;
-    if (m == 0) return -1;
-    return (int64_t)(L + 1 - m) * (L + 1) + (l - m);
 }
 
 template <typename T>
@@ -135,25 +165,16 @@ __device__ __forceinline__ T* xptr(const LegArgs& a, int comp)
 {
     return static_cast<T*>(a.X) + (int64_t)comp * a.xcomp;
 }
-
 template <typename T>
-__device__ __forceinline__ void ld2(const T* p, double& x, double& y)
+__device__ __forceinline__ T* aptr(const LegArgs& a, int comp)
 {
-    if constexpr (sizeof(T) == 8) {
-        double2 v = *reinterpret_cast<const double2*>(p);
-        x = v.x; y = v.y;
-    } else {
-        float2 v = *reinterpret_cast<const float2*>(p);
-        x = v.x; y = v.y;
-    }
+    return static_cast<T*>(a.A) + (int64_t)comp * a.acomp;
 }
 
-// m2a work decode: logical g -> (m, lt, ct); tileoff[m] = tiles of all m' < m.
-__device__ __forceinline__ void decode_m2a(const LegArgs& a, int g, int& m, int& lt, int& ct)
+// m2a work decode: logical g -> (m, lt, ct); tileoff[m] = l tiles of all m' < m.
+__device__ __forceinline__ void decode_tiles(const int* off, int lmax, int C, int g, int& m, int& lt, int& ct)
 {
-    const int* off = a.tiles;
-    int lo = 0, hi = a.lmax + 1;  // find m with off[m]*C <= g < off[m+1]*C
-    const int C = a.ctiles;
+    int lo = 0, hi = lmax + 1;
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
         if (off[mid] * C <= g) lo = mid; else hi = mid;
@@ -165,562 +186,617 @@ __device__ __forceinline__ void decode_m2a(const LegArgs& a, int g, int& m, int&
     lt = r - ct * nlt;
 }
 
-// ============================================================================
-// map2alm, spin 0:  A_l = scale * sum_{north rings} lambda_l (T_N +- T_S)
-// tile: TL rows of l x 64 columns, rings in chunks of 32
-// ============================================================================
-constexpr int M2A_TR = 32;
-constexpr int M2A_TC = 64;
-
-template <typename T>
-__global__ __launch_bounds__(NT) void k_m2a_spin0(LegArgs a)
+// next ring chunk >= rc whose first significant l is within [.., lend]
+__device__ __forceinline__ int next_chunk(const LegArgs& a, int m, int rc, int nchunk, int lend)
 {
-    __shared__ T lam[2][M2A_TR][HALF + 1];
-    __shared__ T xt[2][M2A_TR][M2A_TC + 2];
-    __shared__ double coef[2 * TL];
-
-    int m, lt, ct;
-    decode_m2a(a, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
-    const int L = a.lmax;
-    const int lb = lbase(0, m);
-    const int l0 = lb + lt * TL;
-    const int lend = min(L, l0 + TL - 1);
-    const int po = (lb - m) & 1;
-    const int c0 = ct * M2A_TC;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int p = wave & 1, h = wave >> 1;
-    const T* X = xptr<T>(a, 0);
-
-    make_coef<0>(coef, l0, m);
-    using MF = Mfma<T>;
-    typename MF::acc acc[2][2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) acc[t][u] = typename MF::acc{0, 0, 0, 0};
-
-    const int nchunk = (a.rn + M2A_TR - 1) / M2A_TR;
-    for (int rc = 0; rc < nchunk; ++rc) {
-        if (a.lsig[(int64_t)m * a.nrc + rc] > lend) continue;  // whole chunk negligible for this tile
-        const int r0 = rc * M2A_TR;
-        __syncthreads();  // previous chunk's MFMA reads and the coefficients are done
-        if (tid < 2 * M2A_TR) {
-            const int rl = tid & (M2A_TR - 1), s = tid / M2A_TR;
-            const int r = r0 + rl;
-            const int ls = l0 + SEG * s;
-            const int cnt = (ls <= L) ? min(SEG, L - ls + 1) : 0;
-            if (r < a.rn && cnt > 0) {
-                Seed0 sd = load_seed0(a, m, lt * 2 + s, r);
-                fill_spin0(sd, a.rings[r].z, cnt, coef + 2 * SEG * s, [&](int i, double v) {
-                    int row = SEG * s + i;
-                    lam[(row + po) & 1][rl][row >> 1] = (T)v;
-                });
-            }
-            for (int i = (r < a.rn ? cnt : 0); i < SEG; ++i) {
-                int row = SEG * s + i;
-                lam[(row + po) & 1][rl][row >> 1] = (T)0;
-            }
-        }
-        // T tiles: rows = rings r0.., S = T_N + T_S, D = T_N - T_S (equator: S = T_N, D = 0)
-        for (int e = tid; e < M2A_TR * (M2A_TC / 2); e += NT) {
-            const int rl = e / (M2A_TC / 2), cp = e - rl * (M2A_TC / 2);
-            const int r = r0 + rl;
-            double nx = 0, ny = 0, sx = 0, sy = 0;
-            if (r < a.rn) {
-                ld2(X + ((int64_t)m * a.nring + r) * a.ldx + c0 + 2 * cp, nx, ny);
-                const int rs = a.nring - 1 - r;
-                if (rs != r) ld2(X + ((int64_t)m * a.nring + rs) * a.ldx + c0 + 2 * cp, sx, sy);
-            }
-            xt[0][rl][2 * cp] = (T)(nx + sx);
-            xt[0][rl][2 * cp + 1] = (T)(ny + sy);
-            xt[1][rl][2 * cp] = (T)(nx - sx);
-            xt[1][rl][2 * cp + 1] = (T)(ny - sy);
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int ks = 0; ks < M2A_TR / 4; ++ks) {
-            const int kr = 4 * ks + (lane >> 4);
-            T av[2], bv[2];
-#pragma unroll
-            for (int t = 0; t < 2; ++t) av[t] = lam[p][kr][16 * t + (lane & 15)];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) bv[u] = xt[p][kr][32 * h + 16 * u + (lane & 15)];
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) acc[t][u] = MF::run(av[t], bv[u], acc[t][u]);
-        }
-    }
-
-    // store: row index within the parity class -> l
-    double* alm = a.alm + (int64_t)a.compT * (L + 1) * (L + 1);
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int ci = 16 * t + MF::row(lane, v);
-                const int l = l0 + 2 * ci + (p ^ po);
-                const int col = c0 + 32 * h + 16 * u + (lane & 15);
-                const int k = col >> 1;
-                if (l > L || k >= a.nmaps) continue;
-                int64_t off = calm(L, l, m, col & 1);
-                if (off < 0) continue;
-                double* dst = alm + (int64_t)k * a.almstride + off;
-                double val = a.scale * (double)acc[t][u][v];
-                if (a.accumulate) *dst += val; else *dst = val;
-            }
+    while (rc < nchunk && a.lsig[(int64_t)m * a.nrc + rc] > lend) ++rc;
+    return rc;
 }
 
 // ============================================================================
-// map2alm, spin 2 (E, B from Q, U):
-//   even l-m: A_E = F+ SX + F- DY,  iA_B = F- DX + F+ SY
-//   odd  l-m: A_E = F+ DX + F- SY,  iA_B = F- SX + F+ DY
-// X = Q-coefficients, Y = i U-coefficients; S/D = north +- south.
+// map2alm, spin 0: A_l = sum_{north rings} lambda_l (T_N +- T_S), raw sums into
+// the m-major coefficient workspace.  Tile: 64 l x 128 columns; rings in chunks
+// of 32; wave w owns columns 32w..32w+31 and all 64 rows.
 // ============================================================================
-constexpr int M2A2_TR = 32;
-constexpr int M2A2_TC = 32;
+constexpr int M0_TR = 32, M0_TC = 128;
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_m2a_spin2(LegArgs a)
+__global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
 {
-    __shared__ T fpm[2][2][M2A2_TR][HALF + 1];        // [F+ / F-][parity][ring][row/2]
-    __shared__ T xt[4][M2A2_TR][M2A2_TC + 2];         // SX, DX, SY, DY
+    __shared__ T lam[2][2][M0_TR][HALF + 1];  // [buffer][parity][ring][row/2]
+    __shared__ double coef[2 * TL];
+
+    int m, lt, ct;
+    decode_tiles(a.tiles, a.lmax, a.ctiles, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    const int L = a.lmax, lb = m;
+    const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
+    const int po = (lb - m) & 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cw = ct * M0_TC + 32 * wave;
+    const T* X = xptr<T>(a, 0);
+    const int64_t xm = (int64_t)m * a.nring * a.ldx;
+    // fill item of this lane: lanes 0..15 of each wave, 64 items = 32 rings x 2 segments
+    const int item = wave * 16 + (lane & 15);
+    const int frl = item & (M0_TR - 1), fs = item / M0_TR;
+    const bool filler = lane < 16;
+    const int fls = l0 + SEG * fs;
+    const int fcnt = (fls <= L) ? min(SEG, L - fls + 1) : 0;
+
+    if (tid < TL) coef_row<0>(coef, tid, l0, m);
+    __syncthreads();
+
+    using MF = Mfma<T>;
+    typename MF::acc acc[2][2][2];  // [parity][row tile][col tile]
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) acc[p][t][u] = typename MF::acc{0, 0, 0, 0};
+
+    const int nchunk = (a.rn + M0_TR - 1) / M0_TR;
+    int rc = next_chunk(a, m, 0, nchunk, lend);
+    if (rc < nchunk) {
+        auto emit_to = [&](int buf) {
+            return [&, buf](int i, double v) {
+                const int row = SEG * fs + i;
+                lam[buf][(row + po) & 1][frl][row >> 1] = (T)v;
+            };
+        };
+        // prologue: whole fill of the first chunk
+        Fill0 f;
+        if (filler) {
+            const int r = rc * M0_TR + frl;
+            fill_start(f, a, m, lt * 2 + fs, r, fcnt, r < a.rn);
+            auto em = emit_to(0);
+            for (int s = 0; s < SEG; ++s) fill_step(f, coef + 2 * SEG * fs, em);
+        }
+        // operand registers: N and S ring values for 8 K-steps x 2 column tiles
+        double xn[KS][2], xs[KS][2];
+        auto load_x = [&](int rcn, double (&n)[KS][2], double (&s)[KS][2]) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int r = rcn * M0_TR + 4 * ks + (lane >> 4);
+                const bool ok = r < a.rn;
+                const int rr = ok ? r : 0;
+                const int rs = a.nring - 1 - rr;
+                const T* pn = X + xm + (int64_t)rr * a.ldx + cw + (lane & 15);
+                const T* ps = X + xm + (int64_t)rs * a.ldx + cw + (lane & 15);
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    double vn = (double)pn[16 * u], vs = (double)ps[16 * u];
+                    n[ks][u] = ok ? vn : 0.0;
+                    s[ks][u] = (ok && rs != rr) ? vs : 0.0;
+                }
+            }
+        };
+        load_x(rc, xn, xs);
+        __syncthreads();
+        int buf = 0;
+        while (rc < nchunk) {
+            const int rcn = next_chunk(a, m, rc + 1, nchunk, lend);
+            const bool more = rcn < nchunk;
+            // seed loads first: waiting for them must not wait for the operand prefetch
+            if (filler && more) {
+                const int r = rcn * M0_TR + frl;
+                fill_start(f, a, m, lt * 2 + fs, r, fcnt, r < a.rn);
+            }
+            double yn[KS][2], ys[KS][2];
+            if (more) load_x(rcn, yn, ys);
+            auto em = emit_to(buf ^ 1);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int kr = 4 * ks + (lane >> 4);
+                T av[2][2];
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) av[p][t] = lam[buf][p][kr][16 * t + (lane & 15)];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const T bs = (T)(xn[ks][u] + xs[ks][u]);
+                    const T bd = (T)(xn[ks][u] - xs[ks][u]);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        acc[0][t][u] = MF::run(av[0][t], bs, acc[0][t][u]);
+                        acc[1][t][u] = MF::run(av[1][t], bd, acc[1][t][u]);
+                    }
+                }
+                if (filler && more) {
+#pragma unroll
+                    for (int q = 0; q < STEPS_PER_KS; ++q) fill_step(f, coef + 2 * SEG * fs, em);
+                }
+            }
+            if (filler && more)
+                while (f.t < SEG) fill_step(f, coef + 2 * SEG * fs, em);
+            __syncthreads();
+            if (more) {
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) { xn[ks][u] = yn[ks][u]; xs[ks][u] = ys[ks][u]; }
+            }
+            buf ^= 1;
+            rc = rcn;
+        }
+    }
+
+    // store raw sums: row index within a parity class -> l
+    T* A = aptr<T>(a, 0) + a.rowoff[m] * a.ldx;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int ci = 16 * t + MF::row(lane, v);
+                    const int l = l0 + 2 * ci + (p ^ po);
+                    if (l > L) continue;
+                    A[(int64_t)(l - lb) * a.ldx + cw + 16 * u + (lane & 15)] = (T)acc[p][t][u][v];
+                }
+}
+
+// ============================================================================
+// map2alm, spin 2 (E and iB from Q and iU):
+//   even l-m: A_E = F+ SX + F- DY,  iA_B = F+ SY + F- DX
+//   odd  l-m: A_E = F+ DX + F- SY,  iA_B = F+ DY + F- SX
+// X = Q coefficients, Y = iU; S/D = north +- south.  Tile 64 l x 64 columns,
+// rings in chunks of 32; wave w owns columns 16w..16w+15.
+// ============================================================================
+constexpr int M2_TR = 32, M2_TC = 64;
+
+template <typename T>
+__global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
+{
+    __shared__ T fpm[2][2][2][M2_TR][HALF + 1];  // [buffer][F+ / F-][parity][ring][row/2]
     __shared__ double coef[3 * TL];
 
     int m, lt, ct;
-    decode_m2a(a, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
-    const int L = a.lmax;
-    const int lb = lbase(2, m);
-    const int l0 = lb + lt * TL;
-    const int lend = min(L, l0 + TL - 1);
+    decode_tiles(a.tiles, a.lmax, a.ctiles, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    const int L = a.lmax, lb = lbase(2, m);
+    const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int po = (lb - m) & 1;
-    const int c0 = ct * M2A2_TC;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int p = wave & 1;       // parity class of the rows
-    const int q = wave >> 1;      // 0: A_E, 1: iA_B
-    // (x1, x2) tiles multiplying F+ and F- for this wave
-    const int x1 = (q == 0) ? (p == 0 ? 0 : 1) : (p == 0 ? 2 : 3);
-    const int x2 = (q == 0) ? (p == 0 ? 3 : 2) : (p == 0 ? 1 : 0);
+    const int col = ct * M2_TC + 16 * wave + (lane & 15);
+    const int pcol = col ^ 1;               // partner column: Y = iU swaps re/im
+    const double ysg = (col & 1) ? 1.0 : -1.0;  // Y_re = -U_im, Y_im = U_re
     const T* XQ = xptr<T>(a, 1);
     const T* XU = xptr<T>(a, 2);
+    const int64_t xm = (int64_t)m * a.nring * a.ldx;
+    const int item = wave * 16 + (lane & 15);
+    const int frl = item & (M2_TR - 1), fs = item / M2_TR;
+    const bool filler = lane < 16;
+    const int fls = l0 + SEG * fs;
+    const int fcnt = (fls <= L) ? min(SEG, L - fls + 1) : 0;
 
-    make_coef<2>(coef, l0, m);
+    if (tid < TL) coef_row<2>(coef, tid, l0, m);
+    __syncthreads();
+
     using MF = Mfma<T>;
-    typename MF::acc acc[2][2];
+    typename MF::acc accE[2][2], accB[2][2];  // [parity][row tile]
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int u = 0; u < 2; ++u) acc[t][u] = typename MF::acc{0, 0, 0, 0};
+        for (int t = 0; t < 2; ++t) accE[p][t] = accB[p][t] = typename MF::acc{0, 0, 0, 0};
 
-    const int nchunk = (a.rn + M2A2_TR - 1) / M2A2_TR;
-    for (int rc = 0; rc < nchunk; ++rc) {
-        if (a.lsig[(int64_t)m * a.nrc + rc] > lend) continue;
-        const int r0 = rc * M2A2_TR;
-        __syncthreads();
-        if (tid < 2 * M2A2_TR) {
-            const int rl = tid & (M2A2_TR - 1), s = tid / M2A2_TR;
-            const int r = r0 + rl;
-            const int ls = l0 + SEG * s;
-            const int cnt = (ls <= L) ? min(SEG, L - ls + 1) : 0;
-            if (r < a.rn && cnt > 0) {
-                Seed2 sd = load_seed2(a, m, lt * 2 + s, r);
-                fill_spin2(sd, a.rings[r].z, cnt, coef + 3 * SEG * s, [&](int i, double fp, double fm) {
-                    int row = SEG * s + i;
-                    int c = (row + po) & 1;
-                    fpm[0][c][rl][row >> 1] = (T)fp;
-                    fpm[1][c][rl][row >> 1] = (T)fm;
-                });
-            }
-            for (int i = (r < a.rn ? cnt : 0); i < SEG; ++i) {
-                int row = SEG * s + i;
-                int c = (row + po) & 1;
-                fpm[0][c][rl][row >> 1] = (T)0;
-                fpm[1][c][rl][row >> 1] = (T)0;
-            }
+    const int nchunk = (a.rn + M2_TR - 1) / M2_TR;
+    int rc = next_chunk(a, m, 0, nchunk, lend);
+    if (rc < nchunk) {
+        auto emit_to = [&](int buf) {
+            return [&, buf](int i, double fp, double fm) {
+                const int row = SEG * fs + i;
+                const int c = (row + po) & 1;
+                fpm[buf][0][c][frl][row >> 1] = (T)fp;
+                fpm[buf][1][c][frl][row >> 1] = (T)fm;
+            };
+        };
+        Fill2 f;
+        if (filler) {
+            const int r = rc * M2_TR + frl;
+            fill_start(f, a, m, lt * 2 + fs, r, fcnt, r < a.rn);
+            auto em = emit_to(0);
+            for (int s = 0; s < SEG; ++s) fill_step(f, coef + 3 * SEG * fs, em);
         }
-        for (int e = tid; e < M2A2_TR * (M2A2_TC / 2); e += NT) {
-            const int rl = e / (M2A2_TC / 2), cp = e - rl * (M2A2_TC / 2);
-            const int r = r0 + rl;
-            double qn = 0, qni = 0, qs = 0, qsi = 0, un = 0, uni = 0, us = 0, usi = 0;
-            if (r < a.rn) {
-                const int64_t on = ((int64_t)m * a.nring + r) * a.ldx + c0 + 2 * cp;
-                ld2(XQ + on, qn, qni);
-                ld2(XU + on, un, uni);
-                const int rs = a.nring - 1 - r;
-                if (rs != r) {
-                    const int64_t os = ((int64_t)m * a.nring + rs) * a.ldx + c0 + 2 * cp;
-                    ld2(XQ + os, qs, qsi);
-                    ld2(XU + os, us, usi);
+        // operand registers: Q_N, Q_S, Y_N, Y_S per K-step
+        double qn[KS], qs[KS], yn[KS], ys[KS];
+        auto load_x = [&](int rcn, double (&a1)[KS], double (&a2)[KS], double (&b1)[KS], double (&b2)[KS]) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int r = rcn * M2_TR + 4 * ks + (lane >> 4);
+                const bool ok = r < a.rn;
+                const int rr = ok ? r : 0;
+                const int rs = a.nring - 1 - rr;
+                const bool south = ok && rs != rr;
+                const int64_t on = xm + (int64_t)rr * a.ldx, os = xm + (int64_t)rs * a.ldx;
+                double v1 = (double)XQ[on + col], v2 = (double)XQ[os + col];
+                double v3 = (double)XU[on + pcol], v4 = (double)XU[os + pcol];
+                a1[ks] = ok ? v1 : 0.0;
+                a2[ks] = south ? v2 : 0.0;
+                b1[ks] = ok ? ysg * v3 : 0.0;
+                b2[ks] = south ? ysg * v4 : 0.0;
+            }
+        };
+        load_x(rc, qn, qs, yn, ys);
+        __syncthreads();
+        int buf = 0;
+        while (rc < nchunk) {
+            const int rcn = next_chunk(a, m, rc + 1, nchunk, lend);
+            const bool more = rcn < nchunk;
+            if (filler && more) {
+                const int r = rcn * M2_TR + frl;
+                fill_start(f, a, m, lt * 2 + fs, r, fcnt, r < a.rn);
+            }
+            double qn2[KS], qs2[KS], yn2[KS], ys2[KS];
+            if (more) load_x(rcn, qn2, qs2, yn2, ys2);
+            auto em = emit_to(buf ^ 1);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int kr = 4 * ks + (lane >> 4);
+                const T sx = (T)(qn[ks] + qs[ks]), dx = (T)(qn[ks] - qs[ks]);
+                const T sy = (T)(yn[ks] + ys[ks]), dy = (T)(yn[ks] - ys[ks]);
+                T fp[2][2], fm[2][2];  // [parity][row tile]
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        fp[p][t] = fpm[buf][0][p][kr][16 * t + (lane & 15)];
+                        fm[p][t] = fpm[buf][1][p][kr][16 * t + (lane & 15)];
+                    }
+                // first terms of all eight accumulators, then the second terms, so
+                // that dependent MFMAs are eight instructions apart
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    accE[0][t] = MF::run(fp[0][t], sx, accE[0][t]);
+                    accB[0][t] = MF::run(fp[0][t], sy, accB[0][t]);
+                    accE[1][t] = MF::run(fp[1][t], dx, accE[1][t]);
+                    accB[1][t] = MF::run(fp[1][t], dy, accB[1][t]);
+                }
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    accE[0][t] = MF::run(fm[0][t], dy, accE[0][t]);
+                    accB[0][t] = MF::run(fm[0][t], dx, accB[0][t]);
+                    accE[1][t] = MF::run(fm[1][t], sy, accE[1][t]);
+                    accB[1][t] = MF::run(fm[1][t], sx, accB[1][t]);
+                }
+                if (filler && more) {
+#pragma unroll
+                    for (int q = 0; q < STEPS_PER_KS; ++q) fill_step(f, coef + 3 * SEG * fs, em);
                 }
             }
-            // Y = i U: (re, im) = (-U_im, U_re)
-            double yn = -uni, yni = un, ys = -usi, ysi = us;
-            xt[0][rl][2 * cp] = (T)(qn + qs);  xt[0][rl][2 * cp + 1] = (T)(qni + qsi);
-            xt[1][rl][2 * cp] = (T)(qn - qs);  xt[1][rl][2 * cp + 1] = (T)(qni - qsi);
-            xt[2][rl][2 * cp] = (T)(yn + ys);  xt[2][rl][2 * cp + 1] = (T)(yni + ysi);
-            xt[3][rl][2 * cp] = (T)(yn - ys);  xt[3][rl][2 * cp + 1] = (T)(yni - ysi);
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int ks = 0; ks < M2A2_TR / 4; ++ks) {
-            const int kr = 4 * ks + (lane >> 4);
-            T ap[2], am[2], b1[2], b2[2];
+            if (filler && more)
+                while (f.t < SEG) fill_step(f, coef + 3 * SEG * fs, em);
+            __syncthreads();
+            if (more) {
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                ap[t] = fpm[0][p][kr][16 * t + (lane & 15)];
-                am[t] = fpm[1][p][kr][16 * t + (lane & 15)];
+                for (int ks = 0; ks < KS; ++ks) { qn[ks] = qn2[ks]; qs[ks] = qs2[ks]; yn[ks] = yn2[ks]; ys[ks] = ys2[ks]; }
             }
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                b1[u] = xt[x1][kr][16 * u + (lane & 15)];
-                b2[u] = xt[x2][kr][16 * u + (lane & 15)];
-            }
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    acc[t][u] = MF::run(ap[t], b1[u], acc[t][u]);
-                    acc[t][u] = MF::run(am[t], b2[u], acc[t][u]);
-                }
+            buf ^= 1;
+            rc = rcn;
         }
     }
 
-    const int64_t csz = (int64_t)(L + 1) * (L + 1);
+    T* AE = aptr<T>(a, 1) + a.rowoff[m] * a.ldx;
+    T* AB = aptr<T>(a, 2) + a.rowoff[m] * a.ldx;
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int ci = 16 * t + MF::row(lane, v);
                 const int l = l0 + 2 * ci + (p ^ po);
-                const int col = c0 + 16 * u + (lane & 15);
-                const int k = col >> 1;
-                if (l > L || k >= a.nmaps) continue;
-                double val = a.scale * (double)acc[t][u][v];
-                int64_t off;
-                double* base;
-                if (q == 0) {  // A_E: column parity is the part
-                    base = a.alm + (int64_t)k * a.almstride + 1 * csz;
-                    off = calm(L, l, m, col & 1);
-                } else {       // iA_B: Re(iA_B) = -Im(a_B), Im(iA_B) = Re(a_B)
-                    base = a.alm + (int64_t)k * a.almstride + 2 * csz;
-                    if (col & 1) off = calm(L, l, m, 0);
-                    else { off = calm(L, l, m, 1); val = -val; }
-                }
-                if (off < 0) continue;
-                if (a.accumulate) base[off] += val; else base[off] = val;
+                if (l > L) continue;
+                const int64_t o = (int64_t)(l - lb) * a.ldx + col;
+                AE[o] = (T)accE[p][t][v];
+                AB[o] = (T)accB[p][t][v];
             }
-    // E and B have no l < 2 coefficients: clear them once (first l tile of m < 2)
-    if (!a.accumulate && m < 2 && lt == 0) {
-        for (int e = tid; e < 2 * M2A2_TC * 2; e += NT) {
-            const int comp = 1 + (e / (2 * M2A2_TC));
-            const int rem = e % (2 * M2A2_TC);
-            const int l = m + (rem >> 5 & 1);
-            const int col = c0 + (rem & 31);
-            const int k = col >> 1;
-            if (l >= 2 || k >= a.nmaps) continue;
-            int64_t off = calm(L, l, m, col & 1);
-            if (off >= 0) a.alm[(int64_t)k * a.almstride + comp * csz + off] = 0.0;
-        }
-    }
 }
 
 // ============================================================================
-// alm2map, spin 0:  E = sum_{even l-m} lambda A, O = sum_{odd} lambda A,
-// T_N = E + O, T_S = E - O.   tile: 64 rings x 64 columns, l in chunks of TL.
+// alm2map, spin 0: E = sum_{even l-m} lambda A, O = sum_{odd} lambda A,
+// T_N = E + O, T_S = E - O.  Tile: 64 rings x 64 columns, l in chunks of 64;
+// wave w owns columns 16w..16w+15 and all 64 rings.
 // ============================================================================
-constexpr int A2M_TR = 64;
-constexpr int A2M_TC = 64;
+constexpr int A0_TR = 64, A0_TC = 64;
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_a2m_spin0(LegArgs a)
+__global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
 {
-    __shared__ T lam[2][HALF][A2M_TR + 1];   // [parity][row/2][ring]
-    __shared__ T at[2][HALF][A2M_TC + 1];    // [parity][row/2][col]
-    __shared__ double coef[2 * TL];
+    __shared__ T lam[2][2][HALF][A0_TR + 1];   // [buffer][parity][row/2][ring]
+    __shared__ double coef[3][2 * TL];         // coefficients of three consecutive l chunks
 
-    const int nrt = (a.rn + A2M_TR - 1) / A2M_TR;
+    const int nrt = (a.rn + A0_TR - 1) / A0_TR;
     const int g = xcd_remap(blockIdx.x, gridDim.x);
     const int m = g / (a.ctiles * nrt);
     const int rem = g - m * a.ctiles * nrt;
     const int ct = rem / nrt, rt = rem - ct * nrt;
-    const int L = a.lmax;
-    const int lb = lbase(0, m);
+    const int L = a.lmax, lb = m;
     const int po = (lb - m) & 1;
-    const int r0 = rt * A2M_TR, c0 = ct * A2M_TC;
+    const int r0 = rt * A0_TR;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int rh = wave & 1, ch = wave >> 1;
-    const double* alm = a.alm + (int64_t)a.compT * (L + 1) * (L + 1);
+    const int col = ct * A0_TC + 16 * wave + (lane & 15);
+    // fill items: lanes 0..31 of each wave, 128 items = 64 rings x 2 segments
+    const int item = wave * 32 + (lane & 31);
+    const int frl = item & (A0_TR - 1), fs = item / A0_TR;
+    const bool filler = lane < 32;
+    const int fr = r0 + frl;
+    // lanes 32..63 of waves 0 and 1 compute coefficients of the chunk after next
+    const bool coefer = lane >= 32 && wave < 2;
+    const int crow = (wave * 32) + (lane - 32);
 
     int lsig = L + 1;
-    for (int c = r0 / RCHUNK; c < min(a.nrc, (r0 + A2M_TR + RCHUNK - 1) / RCHUNK); ++c)
+    for (int c = r0 / RCHUNK; c < min(a.nrc, (r0 + A0_TR + RCHUNK - 1) / RCHUNK); ++c)
         lsig = min(lsig, a.lsig[(int64_t)m * a.nrc + c]);
-    const int jstart = (lsig > L) ? 0 : (lsig - lb) / SEG;
-    const int lfirst = (lsig > L) ? L + 1 : lb + SEG * (jstart & ~1);
+    const int lfirst = (lsig > L) ? L + 1 : lb + SEG * (((lsig - lb) / SEG) & ~1);
+    const int nch = (lfirst > L) ? 0 : (L - lfirst) / TL + 1;
 
     using MF = Mfma<T>;
-    typename MF::acc accE[2][2], accO[2][2];
+    typename MF::acc accE[4], accO[4];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) accE[t][u] = accO[t][u] = typename MF::acc{0, 0, 0, 0};
+    for (int t = 0; t < 4; ++t) accE[t] = accO[t] = typename MF::acc{0, 0, 0, 0};
 
-    for (int lc = lfirst; lc <= L; lc += TL) {
-        const int jc = (lc - lb) / SEG;
+    const T* Am = aptr<T>(a, 0) + a.rowoff[m] * a.ldx;
+    if (nch > 0) {
+        if (tid < TL) coef_row<0>(coef[0], tid, lfirst, m);
+        if (tid >= TL && tid < 2 * TL && nch > 1) coef_row<0>(coef[1], tid - TL, lfirst + TL, m);
         __syncthreads();
-        make_coef<0>(coef, lc, m);
-        __syncthreads();
-        if (tid < 2 * A2M_TR) {
-            const int rl = tid & (A2M_TR - 1), s = tid / A2M_TR;
-            const int r = r0 + rl;
-            const int ls = lc + SEG * s;
-            const int cnt = (ls <= L) ? min(SEG, L - ls + 1) : 0;
-            if (r < a.rn && cnt > 0) {
-                Seed0 sd = load_seed0(a, m, jc + s, r);
-                fill_spin0(sd, a.rings[r].z, cnt, coef + 2 * SEG * s, [&](int i, double v) {
-                    int row = SEG * s + i;
-                    lam[(row + po) & 1][row >> 1][rl] = (T)v;
-                });
-            }
-            for (int i = (r < a.rn ? cnt : 0); i < SEG; ++i) {
-                int row = SEG * s + i;
-                lam[(row + po) & 1][row >> 1][rl] = (T)0;
-            }
+        auto emit_to = [&](int buf) {
+            return [&, buf](int i, double v) {
+                const int row = SEG * fs + i;
+                lam[buf][(row + po) & 1][row >> 1][frl] = (T)v;
+            };
+        };
+        auto seg_of = [&](int c) { return (lfirst - lb) / SEG + 2 * c + fs; };
+        auto cnt_of = [&](int c) {
+            const int ls = lfirst + TL * c + SEG * fs;
+            return (ls <= L) ? min(SEG, L - ls + 1) : 0;
+        };
+        Fill0 f;
+        if (filler) {
+            fill_start(f, a, m, seg_of(0), fr < a.rn ? fr : 0, cnt_of(0), fr < a.rn);
+            auto em = emit_to(0);
+            for (int s = 0; s < SEG; ++s) fill_step(f, coef[0] + 2 * SEG * fs, em);
         }
-        // A tile: wave w loads columns w, w+4, ...; lane = row
-        for (int cc = wave; cc < A2M_TC; cc += 4) {
-            const int col = c0 + cc, k = col >> 1;
-            const int l = lc + lane;
-            double v = 0.0;
-            if (l <= L && k < a.nmaps) {
-                int64_t off = calm(L, l, m, col & 1);
-                if (off >= 0) v = alm[(int64_t)k * a.almstride + off];
+        // operand registers: A rows of even / odd class for 8 K-steps
+        double be[KS], bo[KS];
+        auto load_a = [&](int c, double (&e)[KS], double (&o)[KS]) {
+            const int lc = lfirst + TL * c;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int kl = 4 * ks + (lane >> 4);
+                // class 0 rows are local rows i with (i + po) even
+                const int le = lc + 2 * kl + po, lo = lc + 2 * kl + (po ^ 1);
+                const int lec = min(le, L), loc = min(lo, L);
+                double ve = (double)Am[(int64_t)(lec - lb) * a.ldx + col];
+                double vo = (double)Am[(int64_t)(loc - lb) * a.ldx + col];
+                e[ks] = (le <= L) ? ve : 0.0;
+                o[ks] = (lo <= L) ? vo : 0.0;
             }
-            at[(lane + po) & 1][lane >> 1][cc] = (T)v;
-        }
+        };
+        load_a(0, be, bo);
         __syncthreads();
-#pragma unroll 2
-        for (int ks = 0; ks < HALF / 4; ++ks) {
-            const int kl = 4 * ks + (lane >> 4);
-            T aE[2], aO[2], bE[2], bO[2];
+        int buf = 0;
+        for (int c = 0; c < nch; ++c) {
+            const bool more = c + 1 < nch;
+            if (filler && more) fill_start(f, a, m, seg_of(c + 1), fr < a.rn ? fr : 0, cnt_of(c + 1), fr < a.rn);
+            double be2[KS], bo2[KS];
+            if (more) load_a(c + 1, be2, bo2);
+            if (coefer && c + 2 < nch) coef_row<0>(coef[(c + 2) % 3], crow, lfirst + TL * (c + 2), m);
+            const double* cf = coef[(c + 1) % 3] + 2 * SEG * fs;
+            auto em = emit_to(buf ^ 1);
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                aE[t] = lam[0][kl][32 * rh + 16 * t + (lane & 15)];
-                aO[t] = lam[1][kl][32 * rh + 16 * t + (lane & 15)];
-            }
+            for (int ks = 0; ks < KS; ++ks) {
+                const int kl = 4 * ks + (lane >> 4);
+                const T bE = (T)be[ks], bO = (T)bo[ks];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                bE[u] = at[0][kl][32 * ch + 16 * u + (lane & 15)];
-                bO[u] = at[1][kl][32 * ch + 16 * u + (lane & 15)];
-            }
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    accE[t][u] = MF::run(aE[t], bE[u], accE[t][u]);
-                    accO[t][u] = MF::run(aO[t], bO[u], accO[t][u]);
+                for (int t = 0; t < 4; ++t) {
+                    const T aE = lam[buf][0][kl][16 * t + (lane & 15)];
+                    const T aO = lam[buf][1][kl][16 * t + (lane & 15)];
+                    accE[t] = MF::run(aE, bE, accE[t]);
+                    accO[t] = MF::run(aO, bO, accO[t]);
                 }
+                if (filler && more) {
+#pragma unroll
+                    for (int q = 0; q < STEPS_PER_KS; ++q) fill_step(f, cf, em);
+                }
+            }
+            if (filler && more)
+                while (f.t < SEG) fill_step(f, cf, em);
+            __syncthreads();
+            if (more) {
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) { be[ks] = be2[ks]; bo[ks] = bo2[ks]; }
+            }
+            buf ^= 1;
         }
     }
 
     T* X = xptr<T>(a, 0);
+    const int64_t xm = (int64_t)m * a.nring * a.ldx;
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = r0 + 32 * rh + 16 * t + MF::row(lane, v);
-                const int col = c0 + 32 * ch + 16 * u + (lane & 15);
-                if (r >= a.rn) continue;
-                const double e = (double)accE[t][u][v], o = (double)accO[t][u][v];
-                X[((int64_t)m * a.nring + r) * a.ldx + col] = (T)(e + o);
-                const int rs = a.nring - 1 - r;
-                if (rs != r) X[((int64_t)m * a.nring + rs) * a.ldx + col] = (T)(e - o);
-            }
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * t + MF::row(lane, v);
+            if (r >= a.rn) continue;
+            const double e = (double)accE[t][v], o = (double)accO[t][v];
+            X[xm + (int64_t)r * a.ldx + col] = (T)(e + o);
+            const int rs = a.nring - 1 - r;
+            if (rs != r) X[xm + (int64_t)rs * a.ldx + col] = (T)(e - o);
+        }
 }
 
 // ============================================================================
-// alm2map, spin 2:
+// alm2map, spin 2, with B' = i a_B:
 //   U1 = sum_even F+ E + sum_odd F- B',  U2 = sum_odd F+ E + sum_even F- B'
 //   V1 = sum_even F+ B' + sum_odd F- E,  V2 = sum_odd F+ B' + sum_even F- E
-//   X_N = U1 + U2, X_S = U1 - U2 (Q);  Y_N = V1 + V2, Y_S = V1 - V2 (i U)
-// with B' = i a_B.  tile: 32 rings x 32 columns; wave w owns U1, U2, V1, V2.
+//   Q_N = U1 + U2, Q_S = U1 - U2;  (iU)_N = V1 + V2, (iU)_S = V1 - V2.
+// Tile: 32 rings x 64 columns; wave w owns columns 16w..16w+15.
 // ============================================================================
-constexpr int A2M2_TR = 32;
-constexpr int A2M2_TC = 32;
+constexpr int A2_TR = 32, A2_TC = 64;
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_a2m_spin2(LegArgs a)
+__global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
 {
-    __shared__ T fpm[2][2][HALF][A2M2_TR + 1];   // [F+/F-][parity][row/2][ring]
-    __shared__ T at[2][2][HALF][A2M2_TC + 1];    // [E/B'][parity][row/2][col]
-    __shared__ double coef[3 * TL];
+    __shared__ T fpm[2][2][2][HALF][A2_TR + 1];   // [buffer][F+/F-][parity][row/2][ring]
+    __shared__ double coef[3][3 * TL];
 
-    const int nrt = (a.rn + A2M2_TR - 1) / A2M2_TR;
+    const int nrt = (a.rn + A2_TR - 1) / A2_TR;
     const int g = xcd_remap(blockIdx.x, gridDim.x);
     const int m = g / (a.ctiles * nrt);
     const int rem = g - m * a.ctiles * nrt;
     const int ct = rem / nrt, rt = rem - ct * nrt;
-    const int L = a.lmax;
-    const int lb = lbase(2, m);
+    const int L = a.lmax, lb = lbase(2, m);
     const int po = (lb - m) & 1;
-    const int r0 = rt * A2M2_TR, c0 = ct * A2M2_TC;
+    const int r0 = rt * A2_TR;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t csz = (int64_t)(L + 1) * (L + 1);
-    // per wave: first (parity, F, alm) term and second term
-    // U1: (0,+,E)(1,-,B')  U2: (1,+,E)(0,-,B')  V1: (0,+,B')(1,-,E)  V2: (1,+,B')(0,-,E)
-    const int pa = (wave == 0 || wave == 2) ? 0 : 1;  // parity of the F+ term
-    const int aa = (wave < 2) ? 0 : 1;                // alm of the F+ term (0: E, 1: B')
+    const int col = ct * A2_TC + 16 * wave + (lane & 15);
+    const int item = wave * 16 + (lane & 15);
+    const int frl = item & (A2_TR - 1), fs = item / A2_TR;
+    const bool filler = lane < 16;
+    const int fr = r0 + frl;
+    const bool coefer = lane >= 32 && wave < 2;
+    const int crow = (wave * 32) + (lane - 32);
 
     int lsig = L + 1;
     if (lb <= L) lsig = a.lsig[(int64_t)m * a.nrc + r0 / RCHUNK];
-    const int jstart = (lsig > L) ? 0 : (lsig - lb) / SEG;
-    const int lfirst = (lsig > L) ? L + 1 : lb + SEG * (jstart & ~1);
+    const int lfirst = (lsig > L) ? L + 1 : lb + SEG * (((lsig - lb) / SEG) & ~1);
+    const int nch = (lfirst > L) ? 0 : (L - lfirst) / TL + 1;
 
     using MF = Mfma<T>;
-    typename MF::acc acc[2][2];
+    typename MF::acc u1[2], u2[2], v1[2], v2[2];  // per row tile
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) acc[t][u] = typename MF::acc{0, 0, 0, 0};
+    for (int t = 0; t < 2; ++t) u1[t] = u2[t] = v1[t] = v2[t] = typename MF::acc{0, 0, 0, 0};
 
-    for (int lc = lfirst; lc <= L; lc += TL) {
-        const int jc = (lc - lb) / SEG;
+    const T* AE = aptr<T>(a, 1) + a.rowoff[m] * a.ldx;
+    const T* AB = aptr<T>(a, 2) + a.rowoff[m] * a.ldx;
+    if (nch > 0) {
+        if (tid < TL) coef_row<2>(coef[0], tid, lfirst, m);
+        if (tid >= TL && tid < 2 * TL && nch > 1) coef_row<2>(coef[1], tid - TL, lfirst + TL, m);
         __syncthreads();
-        make_coef<2>(coef, lc, m);
-        __syncthreads();
-        if (tid < 2 * A2M2_TR) {
-            const int rl = tid & (A2M2_TR - 1), s = tid / A2M2_TR;
-            const int r = r0 + rl;
-            const int ls = lc + SEG * s;
-            const int cnt = (ls <= L) ? min(SEG, L - ls + 1) : 0;
-            if (r < a.rn && cnt > 0) {
-                Seed2 sd = load_seed2(a, m, jc + s, r);
-                fill_spin2(sd, a.rings[r].z, cnt, coef + 3 * SEG * s, [&](int i, double fp, double fm) {
-                    int row = SEG * s + i;
-                    int c = (row + po) & 1;
-                    fpm[0][c][row >> 1][rl] = (T)fp;
-                    fpm[1][c][row >> 1][rl] = (T)fm;
-                });
-            }
-            for (int i = (r < a.rn ? cnt : 0); i < SEG; ++i) {
-                int row = SEG * s + i;
-                int c = (row + po) & 1;
-                fpm[0][c][row >> 1][rl] = (T)0;
-                fpm[1][c][row >> 1][rl] = (T)0;
-            }
+        auto emit_to = [&](int buf) {
+            return [&, buf](int i, double fp, double fm) {
+                const int row = SEG * fs + i;
+                const int c = (row + po) & 1;
+                fpm[buf][0][c][row >> 1][frl] = (T)fp;
+                fpm[buf][1][c][row >> 1][frl] = (T)fm;
+            };
+        };
+        auto seg_of = [&](int c) { return (lfirst - lb) / SEG + 2 * c + fs; };
+        auto cnt_of = [&](int c) {
+            const int ls = lfirst + TL * c + SEG * fs;
+            return (ls <= L) ? min(SEG, L - ls + 1) : 0;
+        };
+        Fill2 f;
+        if (filler) {
+            fill_start(f, a, m, seg_of(0), fr < a.rn ? fr : 0, cnt_of(0), fr < a.rn);
+            auto em = emit_to(0);
+            for (int s = 0; s < SEG; ++s) fill_step(f, coef[0] + 3 * SEG * fs, em);
         }
-        // alm tiles: E and B' = i a_B (Re B' = -Im a_B, Im B' = Re a_B)
-        for (int cc = wave; cc < 2 * A2M2_TC; cc += 4) {
-            const int which = cc / A2M2_TC;   // 0: E, 1: B'
-            const int cl = cc - which * A2M2_TC;
-            const int col = c0 + cl, k = col >> 1;
-            const int l = lc + lane;
-            double v = 0.0;
-            if (l <= L && k < a.nmaps) {
-                const double* base = a.alm + (int64_t)k * a.almstride + (1 + which) * csz;
-                if (which == 0) {
-                    int64_t off = calm(L, l, m, col & 1);
-                    if (off >= 0) v = base[off];
-                } else if (col & 1) {
-                    v = base[calm(L, l, m, 0)];
-                } else {
-                    int64_t off = calm(L, l, m, 1);
-                    if (off >= 0) v = -base[off];
+        double ee[KS], eo[KS], he[KS], ho[KS];   // E and B' rows of both parity classes
+        auto load_a = [&](int c, double (&e0)[KS], double (&e1)[KS], double (&h0)[KS], double (&h1)[KS]) {
+            const int lc = lfirst + TL * c;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int kl = 4 * ks + (lane >> 4);
+                const int le = lc + 2 * kl + po, lo = lc + 2 * kl + (po ^ 1);
+                const int64_t oe = (int64_t)(min(le, L) - lb) * a.ldx + col;
+                const int64_t oo = (int64_t)(min(lo, L) - lb) * a.ldx + col;
+                double w1 = (double)AE[oe], w2 = (double)AE[oo], w3 = (double)AB[oe], w4 = (double)AB[oo];
+                e0[ks] = (le <= L) ? w1 : 0.0;
+                e1[ks] = (lo <= L) ? w2 : 0.0;
+                h0[ks] = (le <= L) ? w3 : 0.0;
+                h1[ks] = (lo <= L) ? w4 : 0.0;
+            }
+        };
+        load_a(0, ee, eo, he, ho);
+        __syncthreads();
+        int buf = 0;
+        for (int c = 0; c < nch; ++c) {
+            const bool more = c + 1 < nch;
+            if (filler && more) fill_start(f, a, m, seg_of(c + 1), fr < a.rn ? fr : 0, cnt_of(c + 1), fr < a.rn);
+            double ee2[KS], eo2[KS], he2[KS], ho2[KS];
+            if (more) load_a(c + 1, ee2, eo2, he2, ho2);
+            if (coefer && c + 2 < nch) coef_row<2>(coef[(c + 2) % 3], crow, lfirst + TL * (c + 2), m);
+            const double* cf = coef[(c + 1) % 3] + 3 * SEG * fs;
+            auto em = emit_to(buf ^ 1);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int kl = 4 * ks + (lane >> 4);
+                const T bEe = (T)ee[ks], bEo = (T)eo[ks], bBe = (T)he[ks], bBo = (T)ho[ks];
+                T pe[2], pd[2], me[2], mo[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    pe[t] = fpm[buf][0][0][kl][16 * t + (lane & 15)];
+                    pd[t] = fpm[buf][0][1][kl][16 * t + (lane & 15)];
+                    me[t] = fpm[buf][1][0][kl][16 * t + (lane & 15)];
+                    mo[t] = fpm[buf][1][1][kl][16 * t + (lane & 15)];
+                }
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    u1[t] = MF::run(pe[t], bEe, u1[t]);
+                    u2[t] = MF::run(pd[t], bEo, u2[t]);
+                    v1[t] = MF::run(pe[t], bBe, v1[t]);
+                    v2[t] = MF::run(pd[t], bBo, v2[t]);
+                }
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    u1[t] = MF::run(mo[t], bBo, u1[t]);
+                    u2[t] = MF::run(me[t], bBe, u2[t]);
+                    v1[t] = MF::run(mo[t], bEo, v1[t]);
+                    v2[t] = MF::run(me[t], bEe, v2[t]);
+                }
+                if (filler && more) {
+#pragma unroll
+                    for (int q = 0; q < STEPS_PER_KS; ++q) fill_step(f, cf, em);
                 }
             }
-            at[which][(lane + po) & 1][lane >> 1][cl] = (T)v;
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int ks = 0; ks < HALF / 4; ++ks) {
-            const int kl = 4 * ks + (lane >> 4);
-            T a1[2], a2[2], b1[2], b2[2];
+            if (filler && more)
+                while (f.t < SEG) fill_step(f, cf, em);
+            __syncthreads();
+            if (more) {
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                a1[t] = fpm[0][pa][kl][16 * t + (lane & 15)];
-                a2[t] = fpm[1][pa ^ 1][kl][16 * t + (lane & 15)];
+                for (int ks = 0; ks < KS; ++ks) { ee[ks] = ee2[ks]; eo[ks] = eo2[ks]; he[ks] = he2[ks]; ho[ks] = ho2[ks]; }
             }
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                b1[u] = at[aa][pa][kl][16 * u + (lane & 15)];
-                b2[u] = at[aa ^ 1][pa ^ 1][kl][16 * u + (lane & 15)];
-            }
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    acc[t][u] = MF::run(a1[t], b1[u], acc[t][u]);
-                    acc[t][u] = MF::run(a2[t], b2[u], acc[t][u]);
-                }
+            buf ^= 1;
         }
     }
 
-    // combine U1/U2 and V1/V2 across waves through LDS (reuses the alm tile space)
-    __syncthreads();
-    double* ex = reinterpret_cast<double*>(&at[0][0][0][0]);  // 4 x 32 x 32 doubles needed
-    static_assert(sizeof(at) >= 4 * A2M2_TR * A2M2_TC * sizeof(float), "exchange space");
-    constexpr bool fits = sizeof(at) >= 4 * A2M2_TR * A2M2_TC * sizeof(double);
-    float* exf = reinterpret_cast<float*>(&at[0][0][0][0]);
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int rl = 16 * t + MF::row(lane, v);
-                const int cl = 16 * u + (lane & 15);
-                const int idx = (wave * A2M2_TR + rl) * A2M2_TC + cl;
-                if constexpr (fits) ex[idx] = (double)acc[t][u][v];
-                else exf[idx] = (float)acc[t][u][v];
-            }
-    __syncthreads();
+    // Q = X; U = -i Y: U_re = Y_im, U_im = -Y_re -> this lane's Y value goes to the partner column
     T* XQ = xptr<T>(a, 1);
     T* XU = xptr<T>(a, 2);
-    for (int e = tid; e < A2M2_TR * (A2M2_TC / 2); e += NT) {
-        const int rl = e / (A2M2_TC / 2), cp = e - rl * (A2M2_TC / 2);
-        const int r = r0 + rl;
-        if (r >= a.rn) continue;
-        double w[4][2];
+    const int64_t xm = (int64_t)m * a.nring * a.ldx;
+    const int pcol = col ^ 1;
+    const double usg = (col & 1) ? 1.0 : -1.0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int z = 0; z < 2; ++z) {
-                const int idx = (s * A2M2_TR + rl) * A2M2_TC + 2 * cp + z;
-                if constexpr (fits) w[s][z] = ex[idx];
-                else w[s][z] = (double)exf[idx];
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * t + MF::row(lane, v);
+            if (r >= a.rn) continue;
+            const double U1 = (double)u1[t][v], U2 = (double)u2[t][v];
+            const double V1 = (double)v1[t][v], V2 = (double)v2[t][v];
+            XQ[xm + (int64_t)r * a.ldx + col] = (T)(U1 + U2);
+            XU[xm + (int64_t)r * a.ldx + pcol] = (T)(usg * (V1 + V2));
+            const int rs = a.nring - 1 - r;
+            if (rs != r) {
+                XQ[xm + (int64_t)rs * a.ldx + col] = (T)(U1 - U2);
+                XU[xm + (int64_t)rs * a.ldx + pcol] = (T)(usg * (V1 - V2));
             }
-        // Q = X, U = -i Y: (U_re, U_im) = (Y_im, -Y_re)
-        const int64_t on = ((int64_t)m * a.nring + r) * a.ldx + c0 + 2 * cp;
-        XQ[on] = (T)(w[0][0] + w[1][0]);
-        XQ[on + 1] = (T)(w[0][1] + w[1][1]);
-        XU[on] = (T)(w[2][1] + w[3][1]);
-        XU[on + 1] = (T)(-(w[2][0] + w[3][0]));
-        const int rs = a.nring - 1 - r;
-        if (rs != r) {
-            const int64_t os = ((int64_t)m * a.nring + rs) * a.ldx + c0 + 2 * cp;
-            XQ[os] = (T)(w[0][0] - w[1][0]);
-            XQ[os + 1] = (T)(w[0][1] - w[1][1]);
-            XU[os] = (T)(w[2][1] - w[3][1]);
-            XU[os + 1] = (T)(-(w[2][0] - w[3][0]));
         }
-    }
 }
 
 template <typename T>
 hipError_t launch_m2a_t(const LegArgs& a, hipStream_t st)
 {
+    LegArgs b = a;
     if (a.spin == 0) {
-        LegArgs b = a;
-        b.ctiles = (int)((a.ldx + M2A_TC - 1) / M2A_TC);
+        b.ctiles = (int)((a.ldx + M0_TC - 1) / M0_TC);
         hipLaunchKernelGGL(k_m2a_spin0<T>, dim3(b.ntiles * b.ctiles), dim3(NT), 0, st, b);
     } else {
-        LegArgs b = a;
-        b.ctiles = (int)((a.ldx + M2A2_TC - 1) / M2A2_TC);
+        b.ctiles = (int)((a.ldx + M2_TC - 1) / M2_TC);
         hipLaunchKernelGGL(k_m2a_spin2<T>, dim3(b.ntiles * b.ctiles), dim3(NT), 0, st, b);
     }
     return hipGetLastError();
@@ -731,12 +807,12 @@ hipError_t launch_a2m_t(const LegArgs& a, hipStream_t st)
 {
     LegArgs b = a;
     if (a.spin == 0) {
-        b.ctiles = (int)((a.ldx + A2M_TC - 1) / A2M_TC);
-        int nrt = (a.rn + A2M_TR - 1) / A2M_TR;
+        b.ctiles = (int)((a.ldx + A0_TC - 1) / A0_TC);
+        int nrt = (a.rn + A0_TR - 1) / A0_TR;
         hipLaunchKernelGGL(k_a2m_spin0<T>, dim3((a.lmax + 1) * b.ctiles * nrt), dim3(NT), 0, st, b);
     } else {
-        b.ctiles = (int)((a.ldx + A2M2_TC - 1) / A2M2_TC);
-        int nrt = (a.rn + A2M2_TR - 1) / A2M2_TR;
+        b.ctiles = (int)((a.ldx + A2_TC - 1) / A2_TC);
+        int nrt = (a.rn + A2_TR - 1) / A2_TR;
         hipLaunchKernelGGL(k_a2m_spin2<T>, dim3((a.lmax + 1) * b.ctiles * nrt), dim3(NT), 0, st, b);
     }
     return hipGetLastError();

@@ -43,9 +43,10 @@ struct Dev {
 
 struct SeedSet {
     int spin = -1;
-    Dev mu, kk, seedoff, lsig, tileoff;
+    Dev mu, kk, seedoff, lsig, tileoff, rowoff;
     int64_t stride = 0;  // seeds per SoA array
-    int ntiles = 0;      // map2alm l tiles over all m
+    int ntiles = 0;      // l tiles of TL over all m
+    int64_t rows = 0;    // m-major coefficient rows over all m
 };
 
 }  // namespace
@@ -355,27 +356,32 @@ int build_seeds(sht_plan p, SeedSet& S, int spin)
             }
         }
     }
-    std::vector<int64_t> seedoff(L + 2);
+    std::vector<int64_t> seedoff(L + 2), rowoff(L + 2);
     std::vector<int> tileoff(L + 2);
-    int64_t tot = 0;
+    int64_t tot = 0, rows = 0;
     int tt = 0;
     for (int m = 0; m <= L; ++m) {
         seedoff[m] = tot;
         tileoff[m] = tt;
+        rowoff[m] = rows;
         int ns = nsegs(spin, L, m);
         tot += (int64_t)ns * rn;
         tt += (ns + 1) / 2;  // TL = 2 SEG
+        rows += std::max(0, L + 1 - lbase(spin, m));
     }
     seedoff[L + 1] = tot;
     tileoff[L + 1] = tt;
+    rowoff[L + 1] = rows;
     S.stride = tot;
     S.ntiles = tt;
+    S.rows = rows;
     int rc;
     const int nmu = (spin == 0) ? 2 : 4;
     if ((rc = dev_alloc(p, S.mu, (size_t)std::max<int64_t>(1, tot) * nmu * sizeof(double)))) return rc;
     if ((rc = dev_alloc(p, S.kk, (size_t)std::max<int64_t>(1, tot) * sizeof(int)))) return rc;
     if ((rc = upload(p, S.seedoff, seedoff))) return rc;
     if ((rc = upload(p, S.tileoff, tileoff))) return rc;
+    if ((rc = upload(p, S.rowoff, rowoff))) return rc;
     if ((rc = dev_alloc(p, S.lsig, (size_t)(L + 1) * p->nrc * sizeof(int)))) return rc;
     HIPCHK(hipMemsetD32Async((hipDeviceptr_t)S.lsig.p, L + 1, (size_t)(L + 1) * p->nrc, p->stream));
     void* d_start = nullptr;
@@ -411,18 +417,31 @@ int build_seeds(sht_plan p, SeedSet& S, int spin)
 // --------------------------------------------------------------------------
 size_t esize(int prec) { return prec == SHT_FP64 ? sizeof(double) : sizeof(float); }
 
-int64_t ldx_for(int chunk) { return 2 * (int64_t)((chunk + 31) / 32 * 32); }
+// columns of the m-major operand arrays: 2 * map sets padded to a multiple of 64
+int64_t ldx_for(int chunk) { return 2 * (int64_t)((chunk + 63) / 64 * 64); }
 
 int64_t xcomp_elems(sht_plan p) { return (int64_t)(p->lmax + 1) * p->nring * ldx_for(p->chunk); }
 
-size_t ws_need(sht_plan p) { return (size_t)p->ncomp * (size_t)xcomp_elems(p) * esize(p->prec); }
+// rows of the m-major coefficient arrays (spin-0 count bounds the spin-2 one)
+int64_t acomp_elems(sht_plan p)
+{
+    int64_t L = p->lmax;
+    return (L + 1) * (L + 2) / 2 * ldx_for(p->chunk);
+}
+
+size_t ws_need(sht_plan p)
+{
+    return (size_t)p->ncomp * (size_t)(xcomp_elems(p) + acomp_elems(p)) * esize(p->prec);
+}
+
+void* ws_A(sht_plan p) { return (char*)p->ws + (size_t)p->ncomp * xcomp_elems(p) * esize(p->prec); }
 
 int default_chunk(sht_plan p)
 {
     const double budget = 8.0e9;
-    double per = (double)p->ncomp * (p->lmax + 1) * p->nring * 2.0 * esize(p->prec);
+    double per = (double)p->ncomp * (p->lmax + 1) * (p->nring + (p->lmax + 2) / 2.0) * 2.0 * esize(p->prec);
     int c = (int)std::max(1.0, std::floor(budget / per));
-    if (c >= 32) c = c / 32 * 32;
+    if (c >= 64) c = c / 64 * 64;
     return std::min(c, p->cap);
 }
 
@@ -482,7 +501,7 @@ FftArgs fft_args(sht_plan p, int nmaps_chunk)
     return a;
 }
 
-LegArgs leg_args(sht_plan p, const SeedSet& S, double* alm, int nmaps_chunk)
+LegArgs leg_args(sht_plan p, const SeedSet& S)
 {
     LegArgs a{};
     a.rings = p->d_rings;
@@ -496,17 +515,33 @@ LegArgs leg_args(sht_plan p, const SeedSet& S, double* alm, int nmaps_chunk)
     a.ntiles = S.ntiles;
     a.X = p->ws;
     a.xcomp = xcomp_elems(p);
-    a.alm = alm;
-    a.almstride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
-    a.compT = 0;
-    a.nmaps = nmaps_chunk;
+    a.A = ws_A(p);
+    a.acomp = acomp_elems(p);
+    a.rowoff = (const int64_t*)S.rowoff.p;
     a.ldx = ldx_for(p->chunk);
     a.lmax = p->lmax;
     a.rn = p->rn;
     a.nring = p->nring;
     a.spin = S.spin;
+    return a;
+}
+
+AlmArgs alm_args(sht_plan p, const SeedSet& S, int nmaps_chunk)
+{
+    AlmArgs a{};
+    a.A = ws_A(p);
+    a.acomp = acomp_elems(p);
+    a.rowoff = (const int64_t*)S.rowoff.p;
+    a.tileoff = (const int*)S.tileoff.p;
+    a.ntiles = S.ntiles;
+    a.ldx = ldx_for(p->chunk);
+    a.kblocks = (int)(a.ldx / 64);
+    a.almstride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
+    a.lmax = p->lmax;
+    a.spin = S.spin;
+    a.nmaps = nmaps_chunk;
+    a.comp0 = (S.spin == 0) ? 0 : 1;
     a.scale = 1.0;
-    a.accumulate = 0;
     return a;
 }
 
@@ -519,15 +554,24 @@ int prep(sht_plan p)
 
 int run_a2m(sht_plan p, const double* alm, int nm)
 {
-    LegArgs a = leg_args(p, p->s0, const_cast<double*>(alm), nm);
+    {
+        StageTimer t(p, SHT_STAGE_ALM_LAYOUT);
+        AlmArgs t0 = alm_args(p, p->s0, nm);
+        t0.alm_in = alm;
+        HIPCHK(launch_alm_to_mmajor(t0, 1, p->prec, p->stream));
+        if (p->spin == 2) {
+            AlmArgs t2 = alm_args(p, p->s2, nm);
+            t2.alm_in = alm;
+            HIPCHK(launch_alm_to_mmajor(t2, 2, p->prec, p->stream));
+        }
+    }
     {
         StageTimer t(p, SHT_STAGE_A2M_SPIN0);
-        HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
+        HIPCHK(launch_leg_a2m(leg_args(p, p->s0), p->prec, p->stream));
     }
     if (p->spin == 2) {
-        LegArgs b = leg_args(p, p->s2, const_cast<double*>(alm), nm);
         StageTimer t(p, SHT_STAGE_A2M_SPIN2);
-        HIPCHK(launch_leg_a2m(b, p->prec, p->stream));
+        HIPCHK(launch_leg_a2m(leg_args(p, p->s2), p->prec, p->stream));
     }
     return SHT_OK;
 }
@@ -535,19 +579,26 @@ int run_a2m(sht_plan p, const double* alm, int nm)
 int run_m2a(sht_plan p, double* alm, int nm, int accumulate)
 {
     const double dsig = 4.0 * M_PI / (double)p->npix;
-    LegArgs a = leg_args(p, p->s0, alm, nm);
-    a.scale = dsig;
-    a.accumulate = accumulate;
     {
         StageTimer t(p, SHT_STAGE_M2A_SPIN0);
-        HIPCHK(launch_leg_m2a(a, p->prec, p->stream));
+        HIPCHK(launch_leg_m2a(leg_args(p, p->s0), p->prec, p->stream));
     }
     if (p->spin == 2) {
-        LegArgs b = leg_args(p, p->s2, alm, nm);
-        b.scale = dsig;
-        b.accumulate = accumulate;
         StageTimer t(p, SHT_STAGE_M2A_SPIN2);
-        HIPCHK(launch_leg_m2a(b, p->prec, p->stream));
+        HIPCHK(launch_leg_m2a(leg_args(p, p->s2), p->prec, p->stream));
+    }
+    StageTimer t(p, SHT_STAGE_ALM_LAYOUT);
+    AlmArgs t0 = alm_args(p, p->s0, nm);
+    t0.alm_out = alm;
+    t0.scale = dsig;
+    t0.accumulate = accumulate;
+    HIPCHK(launch_alm_from_mmajor(t0, 1, p->prec, p->stream));
+    if (p->spin == 2) {
+        AlmArgs t2 = alm_args(p, p->s2, nm);
+        t2.alm_out = alm;
+        t2.scale = dsig;
+        t2.accumulate = accumulate;
+        HIPCHK(launch_alm_from_mmajor(t2, 2, p->prec, p->stream));
     }
     return SHT_OK;
 }

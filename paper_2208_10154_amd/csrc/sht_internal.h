@@ -94,16 +94,33 @@ struct LegArgs {
     int ntiles;             // map2alm: total l tiles (tileoff[lmax+1])
     void* X;                // [m][ring][ldx], component arrays xcomp apart (T | Q | U)
     int64_t xcomp;
-    double* alm;            // compact alm of the chunk's first map set
-    int64_t almstride;      // doubles between consecutive map sets (= ncomp*(lmax+1)^2)
-    int compT;              // component index of T / the spin-0 field in the alm array
-    int nmaps;              // valid map sets (columns beyond 2*nmaps are padding)
-    int64_t ldx;
+    void* A;                // m-major coefficients [rowoff[m] + l - lb(m)][ldx], arrays acomp apart (T | E | iB)
+    int64_t acomp;
+    const int64_t* rowoff;  // first row of each m in A for this spin
+    int64_t ldx;            // columns of X and A (2 * padded map sets, multiple of 128)
     int lmax, rn, nring, spin;
     int ctiles;             // column tiles
-    double scale;           // dsigma for map2alm, 1 for alm2map
-    int accumulate;         // map2alm: alm += scale * result instead of =
 };
+
+// Layout change compact alm <-> m-major rows (one spin's components per launch).
+struct AlmArgs {
+    const double* alm_in;   // compact alm of the chunk (to m-major)
+    double* alm_out;        // compact alm of the chunk (from m-major)
+    void* A;
+    int64_t acomp;
+    const int64_t* rowoff;
+    const int* tileoff;     // l tiles of 64 per m for this spin
+    int ntiles;
+    int kblocks;            // blocks of 32 map sets (ldx / 64)
+    int64_t ldx;
+    int64_t almstride;      // doubles between consecutive map sets
+    int lmax, spin, nmaps;
+    int comp0;              // first component of the launch (blockIdx.y adds)
+    double scale;           // from m-major: alm = scale * A
+    int accumulate;         // from m-major: alm += scale * A
+};
+hipError_t launch_alm_to_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
+hipError_t launch_alm_from_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
 
 // first l of the recursion for (spin, m)
 __host__ __device__ inline int lbase(int spin, int m) { return spin == 2 ? (m > 2 ? m : 2) : m; }

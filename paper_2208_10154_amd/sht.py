@@ -25,7 +25,7 @@ EXPORTS = ["sht_plan_create", "sht_plan_destroy", "sht_plan_set_precision", "sht
            "sht_plan_set_workspace", "sht_alm2map", "sht_map2alm", "sht_map2alm_iter", "sht_plan_sync",
            "sht_last_error", "sht_plan_set_profiling", "sht_plan_get_profile"]
 
-STAGES = ["fft_fwd", "fft_inv", "residual", "m2a_spin0", "m2a_spin2", "a2m_spin0", "a2m_spin2"]
+STAGES = ["fft_fwd", "fft_inv", "residual", "m2a_spin0", "m2a_spin2", "a2m_spin0", "a2m_spin2", "alm_layout"]
 
 _lib = None
 

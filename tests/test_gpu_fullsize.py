@@ -1,0 +1,89 @@
+"""Full-size parity at nside 512, lmax 1535 (IQU), in the launch configuration the
+benchmark times (chunks of 125 map triples), checked on outputs the oracle
+computes one by one: sampled pixels of alm2map, sampled a_lm of map2alm.
+
+Two of the batch's map sets (slots 0 and 137) carry seeded inputs the oracle
+also receives; the other slots hold device-generated noise so the batch and the
+chunking are those of the benchmark.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_10154_amd import synth
+
+from .gpu_util import from_dev, note, to_dev
+
+pytestmark = pytest.mark.gpu
+
+NSIDE, LMAX, NMAPS, CHUNK = 512, 1535, 250, 125
+SLOTS = (0, 137)
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+def rel(got, ref):
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+@pytest.fixture(scope="module")
+def batch():
+    import torch
+    assert torch.cuda.is_available()
+    alm_c = synth.gaussian_alm(LMAX, len(SLOTS), True, workload=11)
+    alm_np = oracle.to_compact(alm_c)
+    maps_np = synth.white_maps(12 * NSIDE ** 2, len(SLOTS), 3, workload=11)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    alm = torch.randn((NMAPS, 3, (LMAX + 1) ** 2), generator=g, device="cuda", dtype=torch.float64) * 1e-2
+    maps = torch.randn((NMAPS, 3, 12 * NSIDE ** 2), generator=g, device="cuda", dtype=torch.float64)
+    for i, s in enumerate(SLOTS):
+        alm[s] = to_dev(alm_np[i])
+        maps[s] = to_dev(maps_np[i])
+    return alm_c, alm, maps_np, maps
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_alm2map_sampled_pixels(batch, prec):
+    import torch
+    from paper_2208_10154_amd import sht
+    alm_c, alm, _, _ = batch
+    note(f"full-size alm2map nside={NSIDE} lmax={LMAX} nmaps={NMAPS} chunk={CHUNK} {prec}")
+    p = sht.Plan(NSIDE, LMAX, 2, NMAPS, precision=prec, chunk=CHUNK)
+    out = torch.empty(p.map_shape(), dtype=torch.float64, device="cuda")
+    p.alm2map(alm, out)
+    p.sync()
+    rng = np.random.default_rng(5)
+    pix = np.concatenate([[0, 1, 2, 3, 12 * NSIDE ** 2 - 1, 6 * NSIDE ** 2],
+                          rng.integers(0, 12 * NSIDE ** 2, 18)])
+    for i, s in enumerate(SLOTS):
+        got = from_dev(out[s][:, pix])
+        ref = oracle.synth_pixels(NSIDE, LMAX, alm_c[i], pix, pol=True)
+        for c in range(3):
+            e = rel(got[c], ref[c])
+            assert e <= TOL[prec], (s, c, e)
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_map2alm_sampled_coefficients(batch, prec):
+    import torch
+    from paper_2208_10154_amd import sht
+    _, _, maps_np, maps = batch
+    note(f"full-size map2alm nside={NSIDE} lmax={LMAX} nmaps={NMAPS} chunk={CHUNK} {prec}")
+    p = sht.Plan(NSIDE, LMAX, 2, NMAPS, precision=prec, chunk=CHUNK)
+    out = torch.empty(p.alm_shape(), dtype=torch.float64, device="cuda")
+    p.map2alm(maps, out)
+    p.sync()
+    ls = np.array([2, 3, 100, 767, 1024, 1535, 1535, 700, 1200, 40])
+    ms = np.array([0, 1, 57, 3, 1024, 0, 1535, 699, 300, 40])
+    L1 = LMAX + 1
+    for i, s in enumerate(SLOTS):
+        comp = from_dev(out[s])
+        ref = oracle.analyze_lm(NSIDE, LMAX, maps_np[i], ls, ms, pol=True)
+        for c in range(3):
+            re = comp[c][ms * L1 + ls]
+            msafe = np.maximum(ms, 1)
+            im = np.where(ms > 0, comp[c][(L1 - msafe) * L1 + (ls - msafe)], 0.0)
+            e = rel(re + 1j * im, ref[c])
+            assert e <= TOL[prec], (s, c, e)
+    p.close()
