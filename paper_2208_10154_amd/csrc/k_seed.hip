@@ -98,7 +98,32 @@ __global__ __launch_bounds__(128) void k_seeds(SeedArgs a)
     atomicMin(a.lsig + (int64_t)m * a.nrc + r / RCHUNK, lsig);
 }
 
+// One row per (m, l >= lb): the coefficients the recursion uses to produce
+// lambda_l, from the same formulas the seed recursion above evaluates.
+__global__ __launch_bounds__(256) void k_coefs(double* coef, const int64_t* rowoff, int lmax, int spin)
+{
+    const int m = blockIdx.y;
+    const int lb = lbase(spin, m);
+    const int l = lb + blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > lmax) return;
+    if (spin == 0) {
+        double* c = coef + (rowoff[m] + (l - lb)) * 2;
+        coef_spin0(l, m, c[0], c[1]);
+    } else {
+        double* c = coef + (rowoff[m] + (l - lb)) * 4;
+        coef_spin2(l, m, c[0], c[1], c[2]);
+        c[3] = 0.0;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_coefs(double* coef, const int64_t* rowoff, int lmax, int spin, hipStream_t st)
+{
+    dim3 grid((lmax + 1 + 255) / 256, lmax + 1);
+    hipLaunchKernelGGL(k_coefs, grid, dim3(256), 0, st, coef, rowoff, lmax, spin);
+    return hipGetLastError();
+}
 
 hipError_t launch_seeds(const SeedArgs& a, hipStream_t st)
 {

@@ -43,7 +43,7 @@ struct Dev {
 
 struct SeedSet {
     int spin = -1;
-    Dev mu, kk, seedoff, lsig, tileoff, rowoff;
+    Dev mu, kk, seedoff, lsig, tileoff, ftileoff, rowoff, coef;
     int64_t stride = 0;  // seeds per SoA array
     int ntiles = 0;      // l tiles of TL over all m
     int64_t rows = 0;    // m-major coefficient rows over all m
@@ -372,6 +372,13 @@ int build_seeds(sht_plan p, SeedSet& S, int spin)
     seedoff[L + 1] = tot;
     tileoff[L + 1] = tt;
     rowoff[L + 1] = rows;
+    // the same l tiles listed in folded m order (work list of the map2alm kernels)
+    std::vector<int> ftileoff(L + 2);
+    ftileoff[0] = 0;
+    for (int i = 0; i <= L; ++i) {
+        const int m = mfold(i, L);
+        ftileoff[i + 1] = ftileoff[i] + (tileoff[m + 1] - tileoff[m]);
+    }
     S.stride = tot;
     S.ntiles = tt;
     S.rows = rows;
@@ -381,7 +388,13 @@ int build_seeds(sht_plan p, SeedSet& S, int spin)
     if ((rc = dev_alloc(p, S.kk, (size_t)std::max<int64_t>(1, tot) * sizeof(int)))) return rc;
     if ((rc = upload(p, S.seedoff, seedoff))) return rc;
     if ((rc = upload(p, S.tileoff, tileoff))) return rc;
+    if ((rc = upload(p, S.ftileoff, ftileoff))) return rc;
     if ((rc = upload(p, S.rowoff, rowoff))) return rc;
+    const int cstr = (spin == 0) ? 2 : 4;
+    const size_t coef_bytes = (size_t)(rows + TL) * cstr * sizeof(double);
+    if ((rc = dev_alloc(p, S.coef, coef_bytes))) return rc;
+    HIPCHK(hipMemsetAsync(S.coef.p, 0, coef_bytes, p->stream));
+    HIPCHK(launch_coefs((double*)S.coef.p, (const int64_t*)S.rowoff.p, L, spin, p->stream));
     if ((rc = dev_alloc(p, S.lsig, (size_t)(L + 1) * p->nrc * sizeof(int)))) return rc;
     HIPCHK(hipMemsetD32Async((hipDeviceptr_t)S.lsig.p, L + 1, (size_t)(L + 1) * p->nrc, p->stream));
     void* d_start = nullptr;
@@ -511,13 +524,14 @@ LegArgs leg_args(sht_plan p, const SeedSet& S)
     a.seedstride = S.stride;
     a.lsig = (const int*)S.lsig.p;
     a.nrc = p->nrc;
-    a.tiles = (const int*)S.tileoff.p;
+    a.tiles = (const int*)S.ftileoff.p;
     a.ntiles = S.ntiles;
     a.X = p->ws;
     a.xcomp = xcomp_elems(p);
     a.A = ws_A(p);
     a.acomp = acomp_elems(p);
     a.rowoff = (const int64_t*)S.rowoff.p;
+    a.coef = (const double*)S.coef.p;
     a.ldx = ldx_for(p->chunk);
     a.lmax = p->lmax;
     a.rn = p->rn;

@@ -90,13 +90,19 @@ struct LegArgs {
     int64_t seedstride;     // distance between SoA arrays of mu
     const int* lsig;        // [m][ring chunk of RCHUNK]: first l with a significant value (or lmax+1)
     int nrc;                // ring chunks of RCHUNK per m
-    const int* tiles;       // map2alm: tileoff[m] = l tiles of all m' < m (lmax+2 entries)
-    int ntiles;             // map2alm: total l tiles (tileoff[lmax+1])
+    // map2alm work list: l tiles of the m in folded order (see mfold), prefix sums:
+    // tiles[i] = l tiles of mfold(0..i-1) (lmax+2 entries)
+    const int* tiles;
+    int ntiles;             // map2alm: total l tiles (tiles[lmax+1])
     void* X;                // [m][ring][ldx], component arrays xcomp apart (T | Q | U)
     int64_t xcomp;
     void* A;                // m-major coefficients [rowoff[m] + l - lb(m)][ldx], arrays acomp apart (T | E | iB)
     int64_t acomp;
     const int64_t* rowoff;  // first row of each m in A for this spin
+    // recursion coefficients per (m, l), row rowoff[m] + l - lb(m): spin 0 {a, ab}
+    // (2 doubles a row), spin 2 {alpha, beta, gamma, 0} (4 doubles); TL zero rows
+    // follow the last m so that a segment may run past lmax
+    const double* coef;
     int64_t ldx;            // columns of X and A (2 * padded map sets, multiple of 128)
     int lmax, rn, nring, spin;
     int ctiles;             // column tiles
@@ -121,6 +127,12 @@ struct AlmArgs {
 };
 hipError_t launch_alm_to_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
 hipError_t launch_alm_from_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
+
+// Folded m order 0, lmax, 1, lmax-1, ...: work per m falls linearly with m, so any
+// run of consecutive folded indices carries about the same work per index.  Each
+// XCD takes a contiguous run of workgroups, which keeps the XCDs balanced while
+// the workgroups of one m stay on one XCD (and its L2).
+__host__ __device__ inline int mfold(int i, int lmax) { return (i & 1) ? lmax - (i >> 1) : (i >> 1); }
 
 // first l of the recursion for (spin, m)
 __host__ __device__ inline int lbase(int spin, int m) { return spin == 2 ? (m > 2 ? m : 2) : m; }
@@ -162,6 +174,8 @@ struct SeedArgs {
     int lmax, rn, spin;
 };
 hipError_t launch_seeds(const SeedArgs& a, hipStream_t st);
+// recursion coefficient table (layout of LegArgs::coef); rows must be zeroed first
+hipError_t launch_coefs(double* coef, const int64_t* rowoff, int lmax, int spin, hipStream_t st);
 
 // prec: 0 FP64, 1 FP32, 2 BF16x3
 hipError_t launch_leg_m2a(const LegArgs& a, int prec, hipStream_t st);
