@@ -15,6 +15,14 @@
 // back to pixels.  The residual kernel (iterative map2alm, Algorithm 2) performs
 // the same fold, subtracts N times it from the stored data spectrum in FP64 and
 // unfolds the difference, never leaving the Fourier domain (Sec. 3.1 item 8).
+//
+// Index arithmetic is kept off the critical path: ring lengths are runtime
+// values, so divisions inside LDS index ranges use an exact multiply-high form,
+// and the (un)folding walks m with incrementally updated bin and phase indices
+// (one thread per map pair and m, all four output columns at once).  LDS holds
+// sequence sq, element i at sq * lstride + i + i / 16: the pad slot every 16
+// values and the sequence stride (congruent to 16/nseq modulo 16) spread
+// power-of-two strides over the banks.
 #include "sht_internal.h"
 
 namespace sht {
@@ -29,6 +37,18 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
+
+// exact x / d for 0 <= x < 2^16 and 1 <= d < 2^16: with mul = ceil(2^32 / d),
+// x * mul / 2^32 exceeds x / d by less than 2^-16 < 1/d, so the floor is exact
+struct FastDiv {
+    int d;
+    unsigned mul;
+    __device__ __forceinline__ explicit FastDiv(int dd) : d(dd), mul(dd > 1 ? 0xFFFFFFFFu / (unsigned)dd + 1u : 0u) {}
+    __device__ __forceinline__ int div(int x) const { return d == 1 ? x : (int)__umulhi((unsigned)x, mul); }
+};
+
+// LDS slot of element i of sequence sq
+__device__ __forceinline__ int P(int sq, int i, int ls) { return sq * ls + i + (i >> 4); }
 
 // R-point forward DFT (odd R) in registers with W[t] = e^{-2 pi i t/R}, using
 // the conjugate symmetry W^{(R-r)q} = conj(W^{rq}): with s_r = v_r + v_{R-r},
@@ -85,162 +105,204 @@ __device__ __forceinline__ void dft<4>(double2* v, const double2*)
 // place: every thread first reads all of its butterfly inputs, then (after a
 // barrier) writes all outputs.  Ns = product of the radices already applied.
 template <int R, int ELEMS>
-__device__ __forceinline__ void stockham_step(double2* buf, int nseq, int n, int len, int Ns, const double2* tw)
+__device__ __forceinline__ void stockham_step(double2* buf, int nseq, int n, int ls, int Ns, const double2* tw)
 {
     constexpr int MAXB = (ELEMS + R - 1) / R;
     const int nb = n / R;
     const int tot = nseq * nb;
     const int unit = 2 * (n / (Ns * R));
+    const FastDiv dnb(nb), dns(Ns);
     double2 W[R];
     if (R != 2 && R != 4) {
 #pragma unroll
         for (int t = 0; t < R; ++t) W[t] = tw[(2 * n / R) * t];
     }
     double2 v[MAXB][R];
+    int sqs[MAXB], js[MAXB];
 #pragma unroll
     for (int q = 0; q < MAXB; ++q) {
-        int w = threadIdx.x + q * NT;
+        const int w = threadIdx.x + q * NT;
         if (w < tot) {
-            int sq = w / nb, j = w - sq * nb;
+            const int sq = dnb.div(w), j = w - sq * nb;
+            sqs[q] = sq;
+            js[q] = j;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[sq * len + j + r * nb];
+            for (int r = 0; r < R; ++r) v[q][r] = buf[P(sq, j + r * nb, ls)];
         }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MAXB; ++q) {
-        int w = threadIdx.x + q * NT;
+        const int w = threadIdx.x + q * NT;
         if (w < tot) {
-            int sq = w / nb, j = w - sq * nb;
-            int k = j % Ns;
+            const int sq = sqs[q], j = js[q];
+            const int k = j - dns.div(j) * Ns;
 #pragma unroll
             for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * unit]);
             dft<R>(v[q], W);
-            int base = (j / Ns) * Ns * R + k;
+            const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[sq * len + base + r * Ns] = v[q][r];
+            for (int r = 0; r < R; ++r) buf[P(sq, base + r * Ns, ls)] = v[q][r];
         }
     }
     __syncthreads();
 }
 
-// Forward DFT (e^{-2 pi i jk/n}) of nseq sequences (stride len) in LDS.
+// Forward DFT (e^{-2 pi i jk/n}) of nseq sequences in LDS.
 template <int ELEMS>
-__device__ __forceinline__ void fft_lds(double2* buf, int nseq, int n, int len, int nstage, const int* radix, const double2* tw)
+__device__ __forceinline__ void fft_lds(double2* buf, int nseq, int n, int ls, int nstage, const int* radix, const double2* tw)
 {
     int Ns = 1;
     for (int s = 0; s < nstage; ++s) {
         int R = radix[s];
         switch (R) {
-            case 4: stockham_step<4, ELEMS>(buf, nseq, n, len, Ns, tw); break;
-            case 2: stockham_step<2, ELEMS>(buf, nseq, n, len, Ns, tw); break;
-            case 3: stockham_step<3, ELEMS>(buf, nseq, n, len, Ns, tw); break;
-            case 5: stockham_step<5, ELEMS>(buf, nseq, n, len, Ns, tw); break;
-            default: stockham_step<7, ELEMS>(buf, nseq, n, len, Ns, tw); break;
+            case 4: stockham_step<4, ELEMS>(buf, nseq, n, ls, Ns, tw); break;
+            case 2: stockham_step<2, ELEMS>(buf, nseq, n, ls, Ns, tw); break;
+            case 3: stockham_step<3, ELEMS>(buf, nseq, n, ls, Ns, tw); break;
+            case 5: stockham_step<5, ELEMS>(buf, nseq, n, ls, Ns, tw); break;
+            default: stockham_step<7, ELEMS>(buf, nseq, n, ls, Ns, tw); break;
         }
         Ns *= R;
     }
 }
 
-// Ring DFT of length n of the sequences already loaded in buf[sq*len + i], i < n.
+// Ring DFT of length n of the sequences already loaded in LDS (elements i < n).
 // Direct: Stockham over n.  Bluestein: y_j = w_j sum_i (x_i w_i) conj(w_{j-i}),
 // w_i = e^{-i pi i^2/n}, the convolution done through length m with the
 // precomputed kernel spectrum (which carries the 1/m of the inverse).
 template <int ELEMS>
-__device__ __forceinline__ void ring_dft(double2* buf, int nseq, const FftLen* L, const double2* tw_n, const double2* tw_m,
-                         const double2* bhat)
+__device__ __forceinline__ void ring_dft(double2* buf, int nseq, const FftLen* L, const double2* tw_m, const double2* chirp,
+                                         const double2* bhat)
 {
-    const int n = L->n;
+    const int n = L->n, ls = L->lstride;
     if (!L->blue) {
-        fft_lds<ELEMS>(buf, nseq, n, n, L->nstage, L->radix, tw_n);
+        fft_lds<ELEMS>(buf, nseq, n, ls, L->nstage, L->radix, tw_m);
         return;
     }
     const int m = L->m;
-    const int two_n = 2 * n;
+    const FastDiv dm(m), dn(n);
     for (int e = threadIdx.x; e < nseq * m; e += NT) {
-        int sq = e / m, i = e - sq * m;
+        const int sq = dm.div(e), i = e - sq * m;
         double2 v = make_double2(0.0, 0.0);
-        if (i < n) v = cmul(buf[sq * m + i], tw_n[(int)(((unsigned)(i * i)) % (unsigned)two_n)]);
-        buf[sq * m + i] = v;
+        if (i < n) v = cmul(buf[P(sq, i, ls)], chirp[i]);
+        buf[P(sq, i, ls)] = v;
     }
     __syncthreads();
-    fft_lds<ELEMS>(buf, nseq, m, m, L->nstage, L->radix, tw_m);
+    fft_lds<ELEMS>(buf, nseq, m, ls, L->nstage, L->radix, tw_m);
     for (int e = threadIdx.x; e < nseq * m; e += NT) {
-        int i = e % m;
-        buf[e] = conjd(cmul(buf[e], bhat[i]));
+        const int sq = dm.div(e), i = e - sq * m;
+        buf[P(sq, i, ls)] = conjd(cmul(buf[P(sq, i, ls)], bhat[i]));
     }
     __syncthreads();
-    fft_lds<ELEMS>(buf, nseq, m, m, L->nstage, L->radix, tw_m);
+    fft_lds<ELEMS>(buf, nseq, m, ls, L->nstage, L->radix, tw_m);
     for (int e = threadIdx.x; e < nseq * n; e += NT) {
-        int sq = e / n, j = e - sq * n;
-        buf[sq * m + j] = cmul(tw_n[(int)(((unsigned)(j * j)) % (unsigned)two_n)], conjd(buf[sq * m + j]));
+        const int sq = dn.div(e), j = e - sq * n;
+        buf[P(sq, j, ls)] = cmul(chirp[j], conjd(buf[P(sq, j, ls)]));
     }
     __syncthreads();
 }
+
+// Walks m = m0, m0 + dm, ... for one thread, keeping j = m mod n and
+// ph = (m s) mod 2n (the phase e^{-i m phi0} = tw_n[ph]) up to date.
+struct MWalk {
+    int j, ph, dj, dph, n, two_n;
+    __device__ __forceinline__ MWalk(int m0, int dm, int n_, int s)
+    {
+        n = n_;
+        two_n = 2 * n_;
+        j = m0 % n;
+        ph = (int)(((int64_t)m0 * s) % two_n);
+        dj = dm % n;
+        dph = (int)(((int64_t)dm * s) % two_n);
+    }
+    __device__ __forceinline__ void next()
+    {
+        j += dj;
+        if (j >= n) j -= n;
+        ph += dph;
+        if (ph >= two_n) ph -= two_n;
+    }
+};
 
 __device__ __forceinline__ int64_t xidx(const FftArgs& a, int comp, int m, int ring, int col)
 {
     return (int64_t)comp * a.xcomp + ((int64_t)m * a.nring + ring) * a.ldx + col;
 }
 
-__device__ __forceinline__ double2 load_x2(const FftArgs& a, int64_t idx)
+// the four columns (re a, im a, re b, im b) of one map pair at one (m, ring)
+__device__ __forceinline__ void store_x4(const FftArgs& a, int64_t idx, double2 ta, double2 tb)
 {
     if (a.x32) {
-        float2 f = *reinterpret_cast<const float2*>(static_cast<const float*>(a.X) + idx);
-        return make_double2(f.x, f.y);
+        *reinterpret_cast<float4*>(static_cast<float*>(a.X) + idx) =
+            make_float4((float)ta.x, (float)ta.y, (float)tb.x, (float)tb.y);
+    } else {
+        double2* p = reinterpret_cast<double2*>(static_cast<double*>(a.X) + idx);
+        p[0] = ta;
+        p[1] = tb;
     }
-    return *reinterpret_cast<const double2*>(static_cast<const double*>(a.X) + idx);
+}
+__device__ __forceinline__ void load_x4(const FftArgs& a, int64_t idx, double2& ta, double2& tb)
+{
+    if (a.x32) {
+        const float4 f = *reinterpret_cast<const float4*>(static_cast<const float*>(a.X) + idx);
+        ta = make_double2(f.x, f.y);
+        tb = make_double2(f.z, f.w);
+    } else {
+        const double2* p = reinterpret_cast<const double2*>(static_cast<const double*>(a.X) + idx);
+        ta = p[0];
+        tb = p[1];
+    }
 }
 
 // Unfold the packed spectrum Z = A + i B (both Hermitian) of each sequence onto
 // T_m = e^{-i m phi0} F_{m mod n} for m = 0..lmax and store m-major.
-__device__ __forceinline__ void unfold_store(const FftArgs& a, const double2* buf, int len, int nseq, int n, int s, int ring,
-                             int pair0, int comp, const double2* tw_n)
+__device__ __forceinline__ void unfold_store(const FftArgs& a, const double2* buf, const FftLen* L, int s, int ring, int pair0,
+                                             int comp, const double2* tw_n)
 {
-    const int per_m = 4 * nseq;
-    const int tot = (a.lmax + 1) * per_m;
-    const int two_n = 2 * n;
-    for (int e = threadIdx.x; e < tot; e += NT) {
-        int mm = e / per_m, q = e - mm * per_m;
-        int sq = q >> 2, w = q & 3;
-        int j = mm % n, jn = (n - j) % n;
-        double2 z = buf[sq * len + j], y = buf[sq * len + jn];
-        double2 F = (w < 2) ? make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y))
-                            : make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
-        double2 T = cmul(tw_n[(int)(((unsigned)(mm * s)) % (unsigned)two_n)], F);
-        double val = (w & 1) ? T.y : T.x;
-        int64_t idx = xidx(a, comp, mm, ring, 4 * (pair0 + sq) + w);
-        if (a.x32) static_cast<float*>(a.X)[idx] = (float)val;
-        else static_cast<double*>(a.X)[idx] = val;
+    const int n = L->n, ls = L->lstride;
+    const int sq = threadIdx.x & (L->nseq - 1);
+    const int m0 = threadIdx.x >> L->lgseq, dm = NT >> L->lgseq;
+    const int col = 4 * (pair0 + sq);
+    MWalk w(m0, dm, n, s);
+    for (int mm = m0; mm <= a.lmax; mm += dm) {
+        const int jn = w.j ? n - w.j : 0;
+        const double2 z = buf[P(sq, w.j, ls)], y = buf[P(sq, jn, ls)];
+        const double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
+        const double2 Fb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
+        const double2 t = tw_n[w.ph];
+        store_x4(a, xidx(a, comp, mm, ring, col), cmul(t, Fa), cmul(t, Fb));
+        w.next();
     }
 }
 
 // Fold the m-major coefficients of each sequence's two maps onto the ring bins:
 // Z_j = C^a_j + i C^b_j with C_j = sum_{m = j} c_m + sum_{m >= 1, -m = j} conj(c_m),
 // c_m = e^{i m phi0} T_m.
-__device__ __forceinline__ void fold_load(const FftArgs& a, double2* buf, int len, int nseq, int n, int s, int ring, int pair0,
-                          int comp, const double2* tw_n)
+__device__ __forceinline__ void fold_load(const FftArgs& a, double2* buf, const FftLen* L, int s, int ring, int pair0, int comp,
+                                          const double2* tw_n)
 {
-    for (int e = threadIdx.x; e < nseq * len; e += NT) buf[e] = make_double2(0.0, 0.0);
+    const int n = L->n, ls = L->lstride;
+    for (int e = threadIdx.x; e < L->nseq * ls; e += NT) buf[e] = make_double2(0.0, 0.0);
     __syncthreads();
-    const int two_n = 2 * n;
-    const int tot = (a.lmax + 1) * nseq;
-    for (int e = threadIdx.x; e < tot; e += NT) {
-        int mm = e / nseq, sq = e - mm * nseq;
-        int64_t idx = xidx(a, comp, mm, ring, 4 * (pair0 + sq));
-        double2 ta = load_x2(a, idx), tb = load_x2(a, idx + 2);
-        double2 ph = conjd(tw_n[(int)(((unsigned)(mm * s)) % (unsigned)two_n)]);
-        double2 ca = cmul(ph, ta), cb = cmul(ph, tb);
-        int j1 = mm % n;
-        double* p1 = reinterpret_cast<double*>(buf + sq * len + j1);
+    const int sq = threadIdx.x & (L->nseq - 1);
+    const int m0 = threadIdx.x >> L->lgseq, dm = NT >> L->lgseq;
+    const int col = 4 * (pair0 + sq);
+    MWalk w(m0, dm, n, s);
+    for (int mm = m0; mm <= a.lmax; mm += dm) {
+        double2 ta, tb;
+        load_x4(a, xidx(a, comp, mm, ring, col), ta, tb);
+        const double2 ph = conjd(tw_n[w.ph]);
+        const double2 ca = cmul(ph, ta), cb = cmul(ph, tb);
+        double* p1 = reinterpret_cast<double*>(buf + P(sq, w.j, ls));
         atomicAdd(p1, ca.x - cb.y);
         atomicAdd(p1 + 1, ca.y + cb.x);
         if (mm >= 1) {
-            int j2 = (n - j1) % n;
-            double* p2 = reinterpret_cast<double*>(buf + sq * len + j2);
+            const int jn = w.j ? n - w.j : 0;
+            double* p2 = reinterpret_cast<double*>(buf + P(sq, jn, ls));
             atomicAdd(p2, ca.x + cb.y);
             atomicAdd(p2 + 1, cb.x - ca.y);
         }
+        w.next();
     }
     __syncthreads();
 }
@@ -258,74 +320,88 @@ __device__ __forceinline__ double2 hc_get(const double* f, int n, int j)
     return make_double2(re, conj ? -im : im);
 }
 
+struct RingCtx {
+    FftItem it;
+    int comp;
+    RingDev rg;
+    const FftLen* L;
+    const double2* tw_n;   // e^{-i pi j / n}
+    const double2* tw_m;   // twiddles of the transform length actually run
+    const double2* chirp;
+    const double2* bhat;
+};
+__device__ __forceinline__ RingCtx ring_ctx(const FftArgs& a, const FftItem* items)
+{
+    RingCtx c;
+    c.it = items[blockIdx.x];
+    c.comp = a.comp0 + blockIdx.y;
+    c.rg = a.rings[c.it.ring];
+    c.L = a.lens + c.rg.len;
+    c.tw_n = a.tw + c.L->tw;
+    c.tw_m = c.L->blue ? a.tw + c.L->twm : c.tw_n;
+    c.chirp = a.tw + c.L->chirp;
+    c.bhat = a.bhat + c.L->bhat;
+    return c;
+}
+
 template <int ELEMS>
 __global__ __launch_bounds__(NT) void k_fft_fwd(FftArgs a, const FftItem* items)
 {
     extern __shared__ double2 lds[];
-    const FftItem it = items[blockIdx.x];
-    const int comp = a.comp0 + blockIdx.y;
-    const RingDev rg = a.rings[it.ring];
-    const FftLen* L = a.lens + rg.len;
-    const int n = rg.n;
-    const int nseq = min(L->nseq, a.npairs - it.pair0);
-    const int len = L->blue ? L->m : n;
-    const double2* tw_n = a.tw + L->tw;
+    const RingCtx c = ring_ctx(a, items);
+    const int n = c.rg.n, nseq = c.L->nseq, ls = c.L->lstride;
+    const FastDiv dn(n);
 
     for (int e = threadIdx.x; e < nseq * n; e += NT) {
-        int sq = e / n, i = e - sq * n;
-        int k = 2 * (it.pair0 + sq);
+        const int sq = dn.div(e), i = e - sq * n;
+        const int k = 2 * (c.it.pair0 + sq);
         double re = 0.0, im = 0.0;
-        if (k < a.nmaps) re = a.maps_in[((int64_t)k * a.ncomp + comp) * a.npix + rg.first + i];
-        if (k + 1 < a.nmaps) im = a.maps_in[((int64_t)(k + 1) * a.ncomp + comp) * a.npix + rg.first + i];
-        lds[sq * len + i] = make_double2(re, im);
+        if (k < a.nmaps) re = a.maps_in[((int64_t)k * a.ncomp + c.comp) * a.npix + c.rg.first + i];
+        if (k + 1 < a.nmaps) im = a.maps_in[((int64_t)(k + 1) * a.ncomp + c.comp) * a.npix + c.rg.first + i];
+        lds[P(sq, i, ls)] = make_double2(re, im);
     }
     __syncthreads();
-    ring_dft<ELEMS>(lds, nseq, L, tw_n, a.tw + L->twm, a.bhat + L->bhat);
+    ring_dft<ELEMS>(lds, nseq, c.L, c.tw_m, c.chirp, c.bhat);
 
     if (a.F) {  // keep the data spectra of both maps (iterative map2alm)
         for (int e = threadIdx.x; e < nseq * n; e += NT) {
-            int sq = e / n, pos = e - sq * n;
-            int j = (pos == 0) ? 0 : (pos == n - 1 ? n / 2 : (pos + 1) / 2);
-            int jn = (n - j) % n;
-            double2 z = lds[sq * len + j], y = lds[sq * len + jn];
-            double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
-            double2 Fb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
-            bool im = (pos != 0) && (pos != n - 1) && ((pos & 1) == 0);
-            int k = 2 * (it.pair0 + sq);
-            if (k < a.nmaps) a.F[((int64_t)k * a.ncomp + comp) * a.npix + rg.first + pos] = im ? Fa.y : Fa.x;
-            if (k + 1 < a.nmaps) a.F[((int64_t)(k + 1) * a.ncomp + comp) * a.npix + rg.first + pos] = im ? Fb.y : Fb.x;
+            const int sq = dn.div(e), pos = e - sq * n;
+            const int j = (pos == 0) ? 0 : (pos == n - 1 ? n / 2 : (pos + 1) / 2);
+            const int jn = j ? n - j : 0;
+            const double2 z = lds[P(sq, j, ls)], y = lds[P(sq, jn, ls)];
+            const double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
+            const double2 Fb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
+            const bool im = (pos != 0) && (pos != n - 1) && ((pos & 1) == 0);
+            const int k = 2 * (c.it.pair0 + sq);
+            if (k < a.nmaps) a.F[((int64_t)k * a.ncomp + c.comp) * a.npix + c.rg.first + pos] = im ? Fa.y : Fa.x;
+            if (k + 1 < a.nmaps) a.F[((int64_t)(k + 1) * a.ncomp + c.comp) * a.npix + c.rg.first + pos] = im ? Fb.y : Fb.x;
         }
     }
-    unfold_store(a, lds, len, nseq, n, rg.s, it.ring, it.pair0, comp, tw_n);
+    unfold_store(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
 }
 
 template <int ELEMS>
 __global__ __launch_bounds__(NT) void k_fft_inv(FftArgs a, const FftItem* items)
 {
     extern __shared__ double2 lds[];
-    const FftItem it = items[blockIdx.x];
-    const int comp = a.comp0 + blockIdx.y;
-    const RingDev rg = a.rings[it.ring];
-    const FftLen* L = a.lens + rg.len;
-    const int n = rg.n;
-    const int nseq = min(L->nseq, a.npairs - it.pair0);
-    const int len = L->blue ? L->m : n;
-    const double2* tw_n = a.tw + L->tw;
+    const RingCtx c = ring_ctx(a, items);
+    const int n = c.rg.n, nseq = c.L->nseq, ls = c.L->lstride;
+    const FastDiv dn(n);
 
-    fold_load(a, lds, len, nseq, n, rg.s, it.ring, it.pair0, comp, tw_n);
+    fold_load(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
     // inverse DFT as conj(DFT(conj(Z)))
     for (int e = threadIdx.x; e < nseq * n; e += NT) {
-        int sq = e / n, j = e - sq * n;
-        lds[sq * len + j] = conjd(lds[sq * len + j]);
+        const int sq = dn.div(e), j = e - sq * n;
+        lds[P(sq, j, ls)] = conjd(lds[P(sq, j, ls)]);
     }
     __syncthreads();
-    ring_dft<ELEMS>(lds, nseq, L, tw_n, a.tw + L->twm, a.bhat + L->bhat);
+    ring_dft<ELEMS>(lds, nseq, c.L, c.tw_m, c.chirp, c.bhat);
     for (int e = threadIdx.x; e < nseq * n; e += NT) {
-        int sq = e / n, i = e - sq * n;
-        int k = 2 * (it.pair0 + sq);
-        double2 z = lds[sq * len + i];
-        if (k < a.nmaps) a.maps_out[((int64_t)k * a.ncomp + comp) * a.npix + rg.first + i] = z.x;
-        if (k + 1 < a.nmaps) a.maps_out[((int64_t)(k + 1) * a.ncomp + comp) * a.npix + rg.first + i] = -z.y;
+        const int sq = dn.div(e), i = e - sq * n;
+        const int k = 2 * (c.it.pair0 + sq);
+        const double2 z = lds[P(sq, i, ls)];
+        if (k < a.nmaps) a.maps_out[((int64_t)k * a.ncomp + c.comp) * a.npix + c.rg.first + i] = z.x;
+        if (k + 1 < a.nmaps) a.maps_out[((int64_t)(k + 1) * a.ncomp + c.comp) * a.npix + c.rg.first + i] = -z.y;
     }
 }
 
@@ -337,59 +413,53 @@ template <int ELEMS>
 __global__ __launch_bounds__(NT) void k_residual(FftArgs a, const FftItem* items)
 {
     extern __shared__ double2 lds[];
-    const FftItem it = items[blockIdx.x];
-    const int comp = a.comp0 + blockIdx.y;
-    const RingDev rg = a.rings[it.ring];
-    const FftLen* L = a.lens + rg.len;
-    const int n = rg.n;
-    const int nseq = min(L->nseq, a.npairs - it.pair0);
-    const int len = L->blue ? L->m : n;
-    const double2* tw_n = a.tw + L->tw;
+    const RingCtx c = ring_ctx(a, items);
+    const int n = c.rg.n, nseq = c.L->nseq, ls = c.L->lstride;
+    const FastDiv dn(n);
 
-    fold_load(a, lds, len, nseq, n, rg.s, it.ring, it.pair0, comp, tw_n);
-    constexpr int PER = (ELEMS + 0);
-    double2 res[PER];
-    double ssa[PER], ssb[PER];
-    const double dn = (double)n;
+    fold_load(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
+    double2 res[ELEMS];
+    double ssa[ELEMS], ssb[ELEMS];
+    const double dnn = (double)n;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        int e = threadIdx.x + q * NT;
+    for (int q = 0; q < ELEMS; ++q) {
+        const int e = threadIdx.x + q * NT;
         ssa[q] = ssb[q] = 0.0;
         if (e < nseq * n) {
-            int sq = e / n, j = e - sq * n;
-            int jn = (n - j) % n;
-            double2 z = lds[sq * len + j], y = lds[sq * len + jn];
-            double2 Ca = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
-            double2 Cb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
-            int k = 2 * (it.pair0 + sq);
+            const int sq = dn.div(e), j = e - sq * n;
+            const int jn = j ? n - j : 0;
+            const double2 z = lds[P(sq, j, ls)], y = lds[P(sq, jn, ls)];
+            const double2 Ca = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
+            const double2 Cb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
+            const int k = 2 * (c.it.pair0 + sq);
             double2 Fa = make_double2(0.0, 0.0), Fb = make_double2(0.0, 0.0);
-            if (k < a.nmaps) Fa = hc_get(a.F + ((int64_t)k * a.ncomp + comp) * a.npix + rg.first, n, j);
-            if (k + 1 < a.nmaps) Fb = hc_get(a.F + ((int64_t)(k + 1) * a.ncomp + comp) * a.npix + rg.first, n, j);
-            double2 Ra = make_double2(Fa.x - dn * Ca.x, Fa.y - dn * Ca.y);
-            double2 Rb = make_double2(Fb.x - dn * Cb.x, Fb.y - dn * Cb.y);
+            if (k < a.nmaps) Fa = hc_get(a.F + ((int64_t)k * a.ncomp + c.comp) * a.npix + c.rg.first, n, j);
+            if (k + 1 < a.nmaps) Fb = hc_get(a.F + ((int64_t)(k + 1) * a.ncomp + c.comp) * a.npix + c.rg.first, n, j);
+            double2 Ra = make_double2(Fa.x - dnn * Ca.x, Fa.y - dnn * Ca.y);
+            double2 Rb = make_double2(Fb.x - dnn * Cb.x, Fb.y - dnn * Cb.y);
             if (k >= a.nmaps) Ra = make_double2(0.0, 0.0);
             if (k + 1 >= a.nmaps) Rb = make_double2(0.0, 0.0);
-            ssa[q] = (Ra.x * Ra.x + Ra.y * Ra.y) / dn;
-            ssb[q] = (Rb.x * Rb.x + Rb.y * Rb.y) / dn;
+            ssa[q] = (Ra.x * Ra.x + Ra.y * Ra.y) / dnn;
+            ssb[q] = (Rb.x * Rb.x + Rb.y * Rb.y) / dnn;
             res[q] = make_double2(Ra.x - Rb.y, Ra.y + Rb.x);  // pack as Ra + i Rb
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        int e = threadIdx.x + q * NT;
+    for (int q = 0; q < ELEMS; ++q) {
+        const int e = threadIdx.x + q * NT;
         if (e < nseq * n) {
-            int sq = e / n, j = e - sq * n;
-            lds[sq * len + j] = res[q];
-            int k = 2 * (it.pair0 + sq);
+            const int sq = dn.div(e), j = e - sq * n;
+            lds[P(sq, j, ls)] = res[q];
+            const int k = 2 * (c.it.pair0 + sq);
             if (a.norms) {
-                if (ssa[q] != 0.0) atomicAdd(a.norms + (int64_t)k * a.ncomp + comp, ssa[q]);
-                if (ssb[q] != 0.0) atomicAdd(a.norms + (int64_t)(k + 1) * a.ncomp + comp, ssb[q]);
+                if (ssa[q] != 0.0) atomicAdd(a.norms + (int64_t)k * a.ncomp + c.comp, ssa[q]);
+                if (ssb[q] != 0.0) atomicAdd(a.norms + (int64_t)(k + 1) * a.ncomp + c.comp, ssb[q]);
             }
         }
     }
     __syncthreads();
-    if (a.iteration_sub) unfold_store(a, lds, len, nseq, n, rg.s, it.ring, it.pair0, comp, tw_n);
+    if (a.iteration_sub) unfold_store(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
 }
 
 // Bluestein kernel spectra: b_k = e^{+i pi k^2/n} for |k| < n placed circularly
@@ -400,18 +470,21 @@ __global__ __launch_bounds__(NT) void k_bluestein_init(const FftLen* lens, const
 {
     extern __shared__ double2 lds[];
     const FftLen* L = lens + blue_lens[blockIdx.x];
-    const int n = L->n, m = L->m;
-    const double2* tw_n = tw + L->tw;
+    const int n = L->n, m = L->m, ls = L->lstride;
+    const double2* chirp = tw + L->chirp;
     for (int i = threadIdx.x; i < m; i += NT) {
-        int k = (i < n) ? i : (i > m - n ? m - i : -1);
+        const int k = (i < n) ? i : (i > m - n ? m - i : -1);
         double2 v = make_double2(0.0, 0.0);
-        if (k >= 0) v = conjd(tw_n[(int)(((unsigned)(k * k)) % (unsigned)(2 * n))]);
-        lds[i] = v;
+        if (k >= 0) v = conjd(chirp[k]);
+        lds[P(0, i, ls)] = v;
     }
     __syncthreads();
-    fft_lds<ELEMS>(lds, 1, m, m, L->nstage, L->radix, tw + L->twm);
+    fft_lds<ELEMS>(lds, 1, m, ls, L->nstage, L->radix, tw + L->twm);
     const double inv = 1.0 / (double)m;
-    for (int i = threadIdx.x; i < m; i += NT) bhat[L->bhat + i] = make_double2(lds[i].x * inv, lds[i].y * inv);
+    for (int i = threadIdx.x; i < m; i += NT) {
+        const double2 v = lds[P(0, i, ls)];
+        bhat[L->bhat + i] = make_double2(v.x * inv, v.y * inv);
+    }
 }
 
 enum class Kind { Fwd, Inv, Res };

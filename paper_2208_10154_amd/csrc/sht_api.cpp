@@ -220,6 +220,13 @@ int build_fft(sht_plan p)
         int len = r.n;
         if (!direct) {
             L.blue = 1;
+            // chirp e^{-i pi j^2 / n}: the angle is reduced exactly (j^2 mod 2n) before the long-double sincos
+            L.chirp = (int64_t)pool.size();
+            for (int j = 0; j < r.n; ++j) {
+                const int64_t q = ((int64_t)j * j) % (2 * (int64_t)r.n);
+                const ld ang = PI_L * (ld)q / (ld)r.n;
+                pool.push_back(make_double2((double)cosl(ang), (double)(-sinl(ang))));
+            }
             L.m = smooth_at_least(2 * r.n - 1);
             factor_radices(L.m, rad);
             if (!tw_of.count(L.m)) { tw_of[L.m] = (int64_t)pool.size(); push_twiddles(pool, L.m); }
@@ -235,8 +242,17 @@ int build_fft(sht_plan p)
         if (len > 16 * FFT_THREADS) return fail(SHT_ERR_UNSUPPORTED, "ring FFT length beyond the LDS plan");
         // map pairs per workgroup: fill up to 1024 complex values when small, else 4096
         int cap = (len <= 1024) ? 1024 : (len <= 4096 ? 4096 : 8192);
-        L.nseq = std::max(1, std::min(16, cap / len));
+        L.lgseq = 0;
+        while (L.lgseq < 4 && (2 << L.lgseq) * len <= cap) ++L.lgseq;
+        L.nseq = 1 << L.lgseq;
         L.ldsc = L.nseq * len;
+        // padded sequence stride, congruent to 16/nseq complex values modulo 16, so
+        // that the nseq sequences interleaved across a wave start on distinct banks
+        {
+            const int base = len + len / 16, want = (16 / L.nseq) % 16;
+            L.lstride = base + (((want - base) % 16) + 16) % 16;
+        }
+        L.lds = L.nseq * L.lstride;
         r.len = (int)p->lens.size();
         len_index[r.n] = r.len;
         if (L.blue) blue.push_back(r.len);
@@ -255,7 +271,7 @@ int build_fft(sht_plan p)
     if (!blue.empty()) {
         if ((rc = upload(p, dblue, blue))) return rc;
         HIPCHK(launch_bluestein_init(p->d_lens, (const int*)dblue.p, (int)blue.size(), p->d_tw, p->d_bhat,
-                                     max_blue_m, p->stream));
+                                     max_blue_m + max_blue_m / 16 + 1, p->stream));
     }
     return SHT_OK;
 }
@@ -269,7 +285,8 @@ int build_items(sht_plan p, int npairs)
     for (int r = 0; r < p->nring; ++r) {
         const FftLen& L = p->lens[p->rings[r].len];
         int c = (L.ldsc <= 2 * FFT_THREADS) ? 0 : (L.ldsc <= 8 * FFT_THREADS ? 1 : 2);
-        lds[c] = std::max(lds[c], L.ldsc);
+        lds[c] = std::max(lds[c], L.lds);
+        if (npairs % L.nseq) return fail(SHT_ERR_UNSUPPORTED, "map pairs per chunk not a multiple of the ring batch");
         for (int q = 0; q < npairs; q += L.nseq) cls_items[c].push_back(FftItem{r, q});
     }
     std::vector<FftItem> all;

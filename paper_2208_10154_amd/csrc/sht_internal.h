@@ -35,8 +35,12 @@ struct FftLen {
     int64_t tw;             // offset of e^{-i pi j / n}, j < 2n
     int64_t twm;            // offset of e^{-i pi j / m}, j < 2m (Bluestein)
     int64_t bhat;           // offset of the Bluestein kernel spectrum (m entries, scaled by 1/m)
-    int nseq;               // map pairs per workgroup
-    int ldsc;               // complex LDS elements per workgroup = nseq * (blue ? m : n)
+    int64_t chirp;          // offset of the Bluestein chirp e^{-i pi j^2 / n}, j < n (in the twiddle pool)
+    int nseq;               // map pairs per workgroup (a power of two)
+    int lgseq;              // log2(nseq)
+    int ldsc;               // complex values per workgroup = nseq * (blue ? m : n)
+    int lstride;            // LDS stride between sequences: >= len + len/16, = 16/nseq mod 16 (see k_fft.hip)
+    int lds;                // complex LDS slots per workgroup = nseq * lstride
 };
 
 struct RingDev {
