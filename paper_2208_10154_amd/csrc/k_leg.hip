@@ -35,7 +35,7 @@
 //    rings past the equator read clamped, finite data and meet exact zeros in
 //    the recursion tile; the equator ring, whose north and south rows coincide,
 //    enters the map2alm fold with its seeds halved.
-#include "leg_common.h"
+#include "leg_rec.h"
 
 namespace sht {
 namespace {
@@ -47,244 +47,6 @@ constexpr int RPK = SEG / KS;  // recursion rows emitted per K-step
 static_assert(RPK == 4, "the fill of one segment is spread over the K-steps of a tile");
 constexpr int M_TR = 32;       // map2alm: rings per chunk (= RCHUNK, the skip granularity)
 static_assert(M_TR == RCHUNK, "ring chunks and skip-table entries coincide");
-
-template <int I>
-struct IC {
-    static constexpr int v = I;
-};
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F&& f)
-{
-    if constexpr (I < N) {
-        f(IC<I>{});
-        static_for<I + 1, N>(f);
-    }
-}
-
-// Read-only table pointer in the constant address space: with a wave-uniform
-// address its loads become scalar loads (one per wave, into SGPRs).
-using cptr = const __attribute__((address_space(4))) double*;
-__device__ __forceinline__ cptr to_const(const double* p)
-{
-#pragma clang diagnostic push
-#pragma clang diagnostic ignored "-Wold-style-cast"
-    return (cptr)(p);
-#pragma clang diagnostic pop
-}
-
-// wave index as a scalar (wave-uniform) value
-__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
-
-// sign flip by mask on the top bit (integer op: keeps the FP64 pipe free)
-__device__ __forceinline__ double flip(double v, unsigned s)
-{
-    unsigned long long b = (unsigned long long)__double_as_longlong(v) ^ ((unsigned long long)s << 32);
-    return __longlong_as_double((long long)b);
-}
-__device__ __forceinline__ float flip(float v, unsigned s) { return __uint_as_float(__float_as_uint(v) ^ s); }
-
-// ----------------------------------------------------------------------------
-// seeds and recursion state of one fill item (one ring, one SEG-row segment)
-// ----------------------------------------------------------------------------
-template <int SPIN>
-struct Seed;
-template <>
-struct Seed<0> {
-    double v0, v1, x;
-    int k;
-};
-template <>
-struct Seed<2> {
-    double p0, p1, q0, q1, x;
-    int k;
-};
-
-__device__ __forceinline__ void seed_load(Seed<0>& s, const LegArgs& a, int64_t idx, int r)
-{
-    s.v0 = a.mu[idx];
-    s.v1 = a.mu[a.seedstride + idx];
-    s.k = a.kk[idx];
-    s.x = a.rings[r].z;
-}
-__device__ __forceinline__ void seed_load(Seed<2>& s, const LegArgs& a, int64_t idx, int r)
-{
-    s.p0 = a.mu[idx];
-    s.p1 = a.mu[a.seedstride + idx];
-    s.q0 = a.mu[2 * a.seedstride + idx];
-    s.q1 = a.mu[3 * a.seedstride + idx];
-    s.k = a.kk[idx];
-    s.x = a.rings[r].z;
-}
-
-template <int SPIN>
-struct Rec;
-template <>
-struct Rec<0> {
-    double v0, v1, x;  // lambda at rows t-2, t-1 (scaled by 2^(600k))
-    int k;
-    // w: 1, 0.5 (equator ring in the map2alm fold) or 0 (no ring)
-    __device__ __forceinline__ void start(const Seed<0>& s, double w)
-    {
-        v0 = w * s.v0;
-        v1 = w * s.v1;
-        x = s.x;
-        k = s.k;
-    }
-};
-template <>
-struct Rec<2> {
-    double a0, a1, b0, b1, x;  // F+ and F- at rows t-2, t-1
-    int k;
-    // F+- = -(P +- M)/2 from the seed pair (P = lambda_{+2}, M = lambda_{-2})
-    __device__ __forceinline__ void start(const Seed<2>& s, double w)
-    {
-        const double h = -0.5 * w;
-        a0 = h * (s.p0 + s.q0);
-        a1 = h * (s.p1 + s.q1);
-        b0 = h * (s.p0 - s.q0);
-        b1 = h * (s.p1 - s.q1);
-        x = s.x;
-        k = s.k;
-    }
-};
-
-// Destination of the rows of one fill item: even rows t go to e0, odd ones to e1
-// (the two parity classes of l - m), (t >> 1) * STEP further on; the F- row of
-// spin 2 sits FOFF after the F+ row.
-template <typename T, int STEP, int FOFF>
-struct Emit {
-    T* e0;
-    T* e1;
-    template <int R>
-    __device__ __forceinline__ void put(double v)
-    {
-        (R & 1 ? e1 : e0)[(R >> 1) * STEP] = (T)v;
-    }
-    template <int R>
-    __device__ __forceinline__ void put(double p, double q)
-    {
-        T* d = (R & 1 ? e1 : e0) + (R >> 1) * STEP;
-        d[0] = (T)p;
-        d[FOFF] = (T)q;
-    }
-};
-
-// Row R of a segment: rows 0 and 1 are the seed pair, later rows come from the
-// recursion with coefficient row R of the segment (cp: wave-uniform pointer).
-// Rows at or past cnt (beyond lmax) and values still carrying an exponent
-// (k > 0: below 2^-100) are emitted as zeros.
-template <int R, typename E>
-__device__ __forceinline__ void rec_row(Rec<0>& f, cptr cp, int cnt, E& em)
-{
-    double v;
-    if constexpr (R == 0) {
-        v = f.v0;
-    } else if constexpr (R == 1) {
-        v = f.v1;
-    } else {
-        // lambda_l = (a_l x) lambda_{l-1} - (a_l b_l) lambda_{l-2}
-        v = (cp[2 * R] * f.x) * f.v1 - cp[2 * R + 1] * f.v0;
-        if (__any(f.k > 0)) {
-            if (f.k > 0 && fabs(v) > RESCALE_AT) {
-                v *= SCALE_DOWN;
-                f.v1 *= SCALE_DOWN;
-                --f.k;
-            }
-        }
-        f.v0 = f.v1;
-        f.v1 = v;
-    }
-    em.template put<R>((f.k == 0 && R < cnt) ? v : 0.0);
-}
-
-template <int R, typename E>
-__device__ __forceinline__ void rec_row(Rec<2>& f, cptr cp, int cnt, E& em)
-{
-    double fp, fm;
-    if constexpr (R == 0) {
-        fp = f.a0;
-        fm = f.b0;
-    } else if constexpr (R == 1) {
-        fp = f.a1;
-        fm = f.b1;
-    } else {
-        // P_l = (al x + be) P_{l-1} - ga P_{l-2}, M_l = (al x - be) M_{l-1} - ga M_{l-2}
-        // in the F+- basis: F+_l = al x F+_{l-1} + be F-_{l-1} - ga F+_{l-2} (and + <-> -)
-        const double ax = cp[4 * R] * f.x, be = cp[4 * R + 1], ga = cp[4 * R + 2];
-        fp = fma(ax, f.a1, fma(be, f.b1, -ga * f.a0));
-        fm = fma(ax, f.b1, fma(be, f.a1, -ga * f.b0));
-        if (__any(f.k > 0)) {
-            if (f.k > 0 && fmax(fabs(fp), fabs(fm)) > RESCALE_AT) {
-                fp *= SCALE_DOWN;
-                fm *= SCALE_DOWN;
-                f.a1 *= SCALE_DOWN;
-                f.b1 *= SCALE_DOWN;
-                --f.k;
-            }
-        }
-        f.a0 = f.a1;
-        f.a1 = fp;
-        f.b0 = f.b1;
-        f.b1 = fm;
-    }
-    const bool z = f.k == 0 && R < cnt;
-    em.template put<R>(z ? fp : 0.0, z ? fm : 0.0);
-}
-
-// the RPK rows emitted during K-step KI
-template <int KI, int SPIN, typename E>
-__device__ __forceinline__ void rec_group(Rec<SPIN>& f, cptr cp, int cnt, E& em)
-{
-    static_for<0, RPK>([&](auto q) { rec_row<RPK * KI + decltype(q)::v>(f, cp, cnt, em); });
-}
-
-// a whole segment (prologue)
-template <int SPIN, typename E>
-__device__ __forceinline__ void rec_all(Rec<SPIN>& f, cptr cp, int cnt, E& em)
-{
-    static_for<0, KS>([&](auto ki) { rec_group<decltype(ki)::v>(f, cp, cnt, em); });
-}
-
-template <typename T>
-__device__ __forceinline__ T* xptr(const LegArgs& a, int comp)
-{
-    return static_cast<T*>(a.X) + (int64_t)comp * a.xcomp;
-}
-template <typename T>
-__device__ __forceinline__ T* aptr(const LegArgs& a, int comp)
-{
-    return static_cast<T*>(a.A) + (int64_t)comp * a.acomp;
-}
-
-// m2a work decode: logical g -> (m, lt, ct); off[i] = l tiles of the first i m in
-// folded order.
-__device__ __forceinline__ void decode_tiles(const int* off, int lmax, int C, int g, int& m, int& lt, int& ct)
-{
-    int lo = 0, hi = lmax + 1;
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (off[mid] * C <= g) lo = mid; else hi = mid;
-    }
-    m = mfold(lo, lmax);
-    int r = g - off[lo] * C;
-    int nlt = off[lo + 1] - off[lo];
-    ct = r / nlt;
-    lt = r - ct * nlt;
-}
-
-// first ring chunk whose significance bound reaches an l <= lend
-__device__ __forceinline__ int first_chunk(const LegArgs& a, int m, int nchunk, int lend)
-{
-    int rc = 0;
-    while (rc < nchunk && a.lsig[(int64_t)m * a.nrc + rc] > lend) ++rc;
-    return __builtin_amdgcn_readfirstlane(rc);
-}
-
-// fill weight of north ring r in the map2alm fold
-__device__ __forceinline__ double m2a_weight(const LegArgs& a, int r)
-{
-    return (r >= a.rn) ? 0.0 : (2 * r + 1 == a.nring ? 0.5 : 1.0);
-}
 
 // ============================================================================
 // map2alm, spin 0: A_l = sum_{north rings} lambda_l (T_N +- T_S), raw sums into
@@ -311,7 +73,10 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
     const int ls = l0 + SEG * fs;
     const int cnt = min(SEG, L - ls + 1);
     const int64_t row0 = a.rowoff[m];
-    const cptr cp = to_const(a.coef) + (row0 + (ls - lb)) * 2;
+    __shared__ double ctile[CoefTile<2>::N];
+    CoefTile<2>::put(ctile, CoefTile<2>::fetch(a, row0 + (l0 - lb)));
+    __syncthreads();
+    const double* cp = ctile + SEG * fs * 2;
     const int jseg = min(2 * lt + fs, (L - lb) / SEG);
     const int64_t sbase = a.seedoff[m] + (int64_t)jseg * a.rn;
 
@@ -391,7 +156,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
                         acc[1][t][u] = MF::run(av[1][t], bd, acc[1][t][u]);
                     }
                 }
-                if (filler) rec_group<ks>(f, cp, cnt, em);
+                if (filler) rec_group<ks, RPK>(f, cp, cnt, em);
             });
             __syncthreads();
         }
@@ -442,7 +207,10 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
     const int ls = l0 + SEG * fs;
     const int cnt = min(SEG, L - ls + 1);
     const int64_t row0 = a.rowoff[m];
-    const cptr cp = to_const(a.coef) + (row0 + (ls - lb)) * 4;
+    __shared__ double ctile[CoefTile<4>::N];
+    CoefTile<4>::put(ctile, CoefTile<4>::fetch(a, row0 + (l0 - lb)));
+    __syncthreads();
+    const double* cp = ctile + SEG * fs * 4;
     const int jseg = min(2 * lt + fs, (L - lb) / SEG);
     const int64_t sbase = a.seedoff[m] + (int64_t)jseg * a.rn;
 
@@ -537,7 +305,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
                         accB[1][t][u] = MF::run(fm[1][t], sx, accB[1][t][u]);
                     }
                 }
-                if (filler) rec_group<ks>(f, cp, cnt, em);
+                if (filler) rec_group<ks, RPK>(f, cp, cnt, em);
             });
             __syncthreads();
         }
@@ -563,22 +331,6 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
             }
 }
 
-// alm2map tile bounds shared by both spins: first l tile start (an even number of
-// segments past lb, at or below the first significant l of the ring tile) and
-// the number of l tiles.
-__device__ __forceinline__ void a2m_range(const LegArgs& a, int m, int lb, int r0, int tr, int& lfirst, int& nch)
-{
-    const int L = a.lmax;
-    int lsig = L + 1;
-    if (lb <= L)
-        for (int c = r0 / RCHUNK; c < min(a.nrc, (r0 + tr + RCHUNK - 1) / RCHUNK); ++c)
-            lsig = min(lsig, a.lsig[(int64_t)m * a.nrc + c]);
-    // the table loads make these look lane-dependent to the compiler; they are
-    // wave-uniform, and the coefficient addresses built from them must be too
-    lfirst = __builtin_amdgcn_readfirstlane((lsig > L) ? L + 1 : lb + SEG * (((lsig - lb) / SEG) & ~1));
-    nch = __builtin_amdgcn_readfirstlane((lfirst > L) ? 0 : (L - lfirst) / TL + 1);
-}
-
 // ============================================================================
 // alm2map, spin 0: E = sum_{even l-m} lambda A, O = sum_{odd} lambda A,
 // T_N = E + O, T_S = E - O.  Tile: 64 rings x 64*NU columns, l in chunks of 64;
@@ -592,6 +344,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
     constexpr int RS = A0_TR + 1;       // [row/2][ring]
     constexpr int CLS = HALF * RS, BUF = 2 * CLS;
     __shared__ T lam[2 * BUF];          // [buffer][parity class][row/2][ring]
+    __shared__ double ctile[2][CoefTile<2>::N];
 
     const int nrt = (a.rn + A0_TR - 1) / A0_TR;
     const int g = xcd_remap(blockIdx.x, gridDim.x);
@@ -624,7 +377,6 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
     if (nch > 0) {
         const int64_t row0 = a.rowoff[m];
         const T* Am = aptr<T>(a, 0) + row0 * a.ldx + col;
-        const cptr cm = to_const(a.coef) + row0 * 2;
         const int64_t sb = a.seedoff[m] + frc;
         const int j0 = (lfirst - lb) / SEG + fs;
         const int jmax = (L - lb) / SEG;  // last segment of this m
@@ -650,11 +402,17 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
 
         Seed<0> sd;
         Rec<0> f;
+        using CT = CoefTile<2>;
+        auto tile_row = [&](int c) { return row0 + (lfirst + TL * c - lb); };
+        CT::put(ctile[0], CT::fetch(a, tile_row(0)));
+        CT::put(ctile[1], CT::fetch(a, tile_row(min(1, nch - 1))));
+        double cnext = CT::fetch(a, tile_row(min(2, nch - 1)));
+        __syncthreads();
         seed_of(sd, 0);
         if (filler) {
             f.start(sd, w);
             auto em = emit_to(0);
-            rec_all(f, cm + (int64_t)__builtin_amdgcn_readfirstlane(ls_of(0) - lb) * 2, min(SEG, L - ls_of(0) + 1), em);
+            rec_all(f, ctile[0] + SEG * fs * 2, min(SEG, L - ls_of(0) + 1), em);
         }
         seed_of(sd, min(1, nch - 1));
         load_a(0, 0, bb[0]);
@@ -662,7 +420,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
         for (int c = 0; c < nch; ++c) {
             const int b = c & 1;
             const int cn = min(c + 1, nch - 1);
-            const cptr cp = cm + (int64_t)__builtin_amdgcn_readfirstlane(ls_of(cn) - lb) * 2;
+            const double* cp = ctile[(c + 1) & 1] + SEG * fs * 2;
             const int cnt = min(SEG, L - ls_of(cn) + 1);
             if (filler) f.start(sd, w);
             auto em = emit_to(b ^ 1);
@@ -685,8 +443,10 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
                         accO[t][u] = MF::run(aO, bb[ks & 1][1][u], accO[t][u]);
                     }
                 }
-                if (filler) rec_group<ks>(f, cp, cnt, em);
+                if (filler) rec_group<ks, RPK>(f, cp, cnt, em);
             });
+            CT::put(ctile[c & 1], cnext);  // tile of chunk c + 2
+            cnext = CT::fetch(a, tile_row(min(c + 3, nch - 1)));
             __syncthreads();
         }
     }
@@ -723,6 +483,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
     constexpr int RS = A2_TR + 1;
     constexpr int CLS = HALF * RS, FOFF = 2 * CLS, BUF = 4 * CLS;
     __shared__ T fpm[2 * BUF];  // [buffer][F+ / F-][parity class][row/2][ring]
+    __shared__ double ctile[2][CoefTile<4>::N];
 
     const int nrt = (a.rn + A2_TR - 1) / A2_TR;
     const int g = xcd_remap(blockIdx.x, gridDim.x);
@@ -756,7 +517,6 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
         const int64_t row0 = a.rowoff[m];
         const T* AE = aptr<T>(a, 1) + row0 * a.ldx + col;
         const T* AB = aptr<T>(a, 2) + row0 * a.ldx + col;
-        const cptr cm = to_const(a.coef) + row0 * 4;
         const int64_t sb = a.seedoff[m] + frc;
         const int j0 = (lfirst - lb) / SEG + fs;
         const int jmax = (L - lb) / SEG;  // last segment of this m
@@ -784,11 +544,17 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
 
         Seed<2> sd;
         Rec<2> f;
+        using CT = CoefTile<4>;
+        auto tile_row = [&](int c) { return row0 + (lfirst + TL * c - lb); };
+        CT::put(ctile[0], CT::fetch(a, tile_row(0)));
+        CT::put(ctile[1], CT::fetch(a, tile_row(min(1, nch - 1))));
+        double cnext = CT::fetch(a, tile_row(min(2, nch - 1)));
+        __syncthreads();
         seed_of(sd, 0);
         if (filler) {
             f.start(sd, w);
             auto em = emit_to(0);
-            rec_all(f, cm + (int64_t)__builtin_amdgcn_readfirstlane(ls_of(0) - lb) * 4, min(SEG, L - ls_of(0) + 1), em);
+            rec_all(f, ctile[0] + SEG * fs * 4, min(SEG, L - ls_of(0) + 1), em);
         }
         seed_of(sd, min(1, nch - 1));
         load_a(0, 0, bb[0]);
@@ -796,7 +562,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
         for (int c = 0; c < nch; ++c) {
             const int b = c & 1;
             const int cn = min(c + 1, nch - 1);
-            const cptr cp = cm + (int64_t)__builtin_amdgcn_readfirstlane(ls_of(cn) - lb) * 4;
+            const double* cp = ctile[(c + 1) & 1] + SEG * fs * 4;
             const int cnt = min(SEG, L - ls_of(cn) + 1);
             if (filler) f.start(sd, w);
             auto em = emit_to(b ^ 1);
@@ -830,8 +596,10 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
                         v2[t][u] = MF::run(me, d[0][u], v2[t][u]);
                     }
                 }
-                if (filler) rec_group<ks>(f, cp, cnt, em);
+                if (filler) rec_group<ks, RPK>(f, cp, cnt, em);
             });
+            CT::put(ctile[c & 1], cnext);  // tile of chunk c + 2
+            cnext = CT::fetch(a, tile_row(min(c + 3, nch - 1)));
             __syncthreads();
         }
     }
@@ -919,12 +687,14 @@ hipError_t launch_a2m_t(const LegArgs& a, hipStream_t st)
 
 hipError_t launch_leg_m2a(const LegArgs& a, int prec, hipStream_t st)
 {
+    if (prec == 2) return launch_leg_m2a_bf16(a, st);
     if (prec == 0) return launch_m2a_t<double>(a, st);
     return launch_m2a_t<float>(a, st);
 }
 
 hipError_t launch_leg_a2m(const LegArgs& a, int prec, hipStream_t st)
 {
+    if (prec == 2) return launch_leg_a2m_bf16(a, st);
     if (prec == 0) return launch_a2m_t<double>(a, st);
     return launch_a2m_t<float>(a, st);
 }

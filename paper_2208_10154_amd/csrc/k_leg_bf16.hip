@@ -1,0 +1,704 @@
+// Legendre contraction in split-BF16 precision (HIP, gfx950).
+//
+// The same products as k_leg.hip (the paper's per-m GEMMs, Sec. 2.2 and the 2x2
+// block of Sec. 2.3), with the operands held as pairs of bfloat16 numbers
+// x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) and every product formed as
+// hi*hi + hi*lo + lo*hi on the BF16 matrix cores with FP32 accumulation; the
+// dropped lo*lo term and the two roundings leave about 2^-17 relative error per
+// product.  The recursion, its exponent handling and the data in HBM are the
+// same as in the FP32 path (recursion FP64, workspace FP32), so only the MFMA
+// step changes precision.
+//
+// One v_mfma_f32_16x16x32_bf16 covers the whole K extent of a tile (32 rings,
+// or the 32 rows of one parity class of a 64-row l tile), so a tile is one burst
+// of MFMAs per (class, row tile, column tile).  The bursts are spread over eight
+// phases with four recursion rows of the next tile after each, as in the FP64 /
+// FP32 kernels.  Operand layouts (measured): A[i][k] from lane i + 16 (k / 8),
+// element k % 8 of the lane's 8-vector; B[k][j] likewise with j for i; result
+// row 4 (lane / 16) + v, column lane % 16.  The recursion tiles are stored
+// K-contiguous in LDS (rows of 32 values padded to 40), so each operand vector
+// is one 16-byte LDS read.
+#include "leg_rec.h"
+
+namespace sht {
+namespace {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int NT = 256;
+constexpr int HALF = TL / 2;
+constexpr int KP = HALF + 8;   // padded K row in LDS (bf16 elements, 80 bytes)
+constexpr int NPH = 8;         // phases per tile
+constexpr int RPP = SEG / NPH; // recursion rows per phase
+static_assert(RPP == 4, "four recursion rows per phase");
+constexpr int M_TR = 32;
+
+__device__ __forceinline__ v4f mfma3(v8bf ah, v8bf al, v8bf bh, v8bf bl, v4f c)
+{
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+}
+
+// x = hi + lo for eight FP32 values
+__device__ __forceinline__ void split8(const float (&x)[8], v8bf& hi, v8bf& lo)
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 h = (__bf16)x[e];
+        hi[e] = h;
+        lo[e] = (__bf16)(x[e] - (float)h);
+    }
+}
+
+__device__ __forceinline__ v8bf lds8(const __bf16* p) { return *reinterpret_cast<const v8bf*>(p); }
+
+// Emitter for the split tiles: hi at d, lo LOFF further on, F- FOFF after F+.
+template <int STEP, int FOFF, int LOFF>
+struct EmitBF {
+    __bf16* e0;
+    __bf16* e1;
+    __device__ __forceinline__ static void put1(__bf16* d, double v)
+    {
+        const float f = (float)v;
+        const __bf16 h = (__bf16)f;
+        d[0] = h;
+        d[LOFF] = (__bf16)(f - (float)h);
+    }
+    template <int R>
+    __device__ __forceinline__ void put(double v)
+    {
+        put1((R & 1 ? e1 : e0) + (R >> 1) * STEP, v);
+    }
+    template <int R>
+    __device__ __forceinline__ void put(double p, double q)
+    {
+        __bf16* d = (R & 1 ? e1 : e0) + (R >> 1) * STEP;
+        put1(d, p);
+        put1(d + FOFF, q);
+    }
+};
+
+__device__ __forceinline__ const float* fptr(const void* base, int64_t comp, int64_t stride)
+{
+    return static_cast<const float*>(base) + comp * stride;
+}
+
+// ============================================================================
+// map2alm, spin 0.  Tile 64 l x 64*NU columns, rings in chunks of 32.
+// LDS: [buffer][hi, lo][parity class][class row][ring (K)].
+// ============================================================================
+template <int NU>
+__global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
+{
+    constexpr int CLS = HALF * KP, HL = 2 * CLS, BUF = 2 * HL;
+    __shared__ __attribute__((aligned(16))) __bf16 lam[2 * BUF];
+
+    int m, lt, ct;
+    decode_tiles(a.tiles, a.lmax, a.ctiles, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    const int L = a.lmax, lb = m;
+    const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
+    const int lane = threadIdx.x & 63, wave = wave_index();
+    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    const int k0 = 8 * (lane >> 4);
+    const bool filler = lane < 16;
+    const int frl = 16 * (wave & 1) + (lane & 15);
+    const int fs = wave >> 1;
+    const int ls = l0 + SEG * fs;
+    const int cnt = min(SEG, L - ls + 1);
+    const int64_t row0 = a.rowoff[m];
+    __shared__ double ctile[CoefTile<2>::N];
+    CoefTile<2>::put(ctile, CoefTile<2>::fetch(a, row0 + (l0 - lb)));
+    __syncthreads();
+    const double* cp = ctile + SEG * fs * 2;
+    const int jseg = min(2 * lt + fs, (L - lb) / SEG);
+    const int64_t sbase = a.seedoff[m] + (int64_t)jseg * a.rn;
+
+    v4f acc[2][2][NU];  // [class][row tile][column tile]
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < NU; ++u) acc[p][t][u] = v4f{0, 0, 0, 0};
+
+    const int nchunk = (a.rn + M_TR - 1) / M_TR;
+    const int rc0 = first_chunk(a, m, nchunk, lend);
+    if (rc0 < nchunk) {
+        const float* Xm = fptr(a.X, 0, a.xcomp) + (int64_t)m * a.nring * a.ldx + col;
+        auto seed_of = [&](Seed<0>& s, int rc) {
+            const int r = min(rc * M_TR + frl, a.rn - 1);
+            seed_load(s, a, sbase + r, r);
+        };
+        auto emit_to = [&](int b) {
+            EmitBF<KP, 0, HL> e;
+            e.e0 = lam + b * BUF + 16 * fs * KP + frl;
+            e.e1 = e.e0 + CLS;
+            return e;
+        };
+        float xr[2][NU][8];  // [north, south][column tile][ring k0 + e] of the next chunk
+        auto load_x = [&](int rc) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int r = min(rc * M_TR + k0 + e, a.rn - 1);
+                const float* pn = Xm + (int64_t)r * a.ldx;
+                const float* ps = Xm + (int64_t)(a.nring - 1 - r) * a.ldx;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    xr[0][u][e] = pn[16 * u];
+                    xr[1][u][e] = ps[16 * u];
+                }
+            }
+        };
+
+        Seed<0> sd;
+        Rec<0> f;
+        seed_of(sd, rc0);
+        if (filler) {
+            f.start(sd, m2a_weight(a, rc0 * M_TR + frl));
+            auto em = emit_to(0);
+            rec_all(f, cp, cnt, em);
+        }
+        seed_of(sd, min(rc0 + 1, nchunk - 1));
+        load_x(rc0);
+        __syncthreads();
+        for (int rc = rc0; rc < nchunk; ++rc) {
+            const int b = (rc - rc0) & 1;
+            const int rcn = min(rc + 1, nchunk - 1);
+            if (filler) f.start(sd, m2a_weight(a, rcn * M_TR + frl));
+            // operands of this chunk: north + south and north - south, split
+            v8bf bh[2][NU], bl[2][NU];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                float s8[8], d8[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    s8[e] = xr[0][u][e] + xr[1][u][e];
+                    d8[e] = xr[0][u][e] - xr[1][u][e];
+                }
+                split8(s8, bh[0][u], bl[0][u]);
+                split8(d8, bh[1][u], bl[1][u]);
+            }
+            load_x(rcn);
+            seed_of(sd, min(rc + 2, nchunk - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            auto em = emit_to(b ^ 1);
+            const __bf16* lb_ = lam + b * BUF;
+            static_for<0, NPH>([&](auto ph) {
+                constexpr int P = decltype(ph)::v;
+                if constexpr ((P & 1) == 0) {
+                    constexpr int cls = (P >> 2) & 1, t = (P >> 1) & 1;
+                    const __bf16* q = lb_ + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
+                    const v8bf ah = lds8(q), al = lds8(q + HL);
+#pragma unroll
+                    for (int u = 0; u < NU; ++u) acc[cls][t][u] = mfma3(ah, al, bh[cls][u], bl[cls][u], acc[cls][t][u]);
+                }
+                if (filler) rec_group<P, RPP>(f, cp, cnt, em);
+            });
+            __syncthreads();
+        }
+    }
+
+    float* A = static_cast<float*>(a.A) + row0 * a.ldx;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ci = 16 * t + 4 * (lane >> 4) + v;
+                const int l = l0 + 2 * ci + p;
+                if (l > L) continue;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) A[(int64_t)(l - lb) * a.ldx + col + 16 * u] = acc[p][t][u][v];
+            }
+}
+
+// ============================================================================
+// map2alm, spin 2 (see k_m2a_spin2 in k_leg.hip for the block form).
+// LDS: [buffer][hi, lo][F+, F-][parity class][class row][ring (K)].
+// ============================================================================
+template <int NU>
+__global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
+{
+    constexpr int CLS = HALF * KP, FOFF = 2 * CLS, HL = 2 * FOFF, BUF = 2 * HL;
+    __shared__ __attribute__((aligned(16))) __bf16 fpm[2 * BUF];
+
+    int m, lt, ct;
+    decode_tiles(a.tiles, a.lmax, a.ctiles, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    const int L = a.lmax, lb = lbase(2, m);
+    const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
+    const int po = (lb - m) & 1;
+    const int lane = threadIdx.x & 63, wave = wave_index();
+    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    const int pcol = col ^ 1;
+    const unsigned ysg = (col & 1) ? 0u : 0x80000000u;
+    const int k0 = 8 * (lane >> 4);
+    const bool filler = lane < 16;
+    const int frl = 16 * (wave & 1) + (lane & 15);
+    const int fs = wave >> 1;
+    const int ls = l0 + SEG * fs;
+    const int cnt = min(SEG, L - ls + 1);
+    const int64_t row0 = a.rowoff[m];
+    __shared__ double ctile[CoefTile<4>::N];
+    CoefTile<4>::put(ctile, CoefTile<4>::fetch(a, row0 + (l0 - lb)));
+    __syncthreads();
+    const double* cp = ctile + SEG * fs * 4;
+    const int jseg = min(2 * lt + fs, (L - lb) / SEG);
+    const int64_t sbase = a.seedoff[m] + (int64_t)jseg * a.rn;
+
+    v4f accE[2][2][NU], accB[2][2][NU];  // [class][row tile][column tile]
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < NU; ++u) accE[p][t][u] = accB[p][t][u] = v4f{0, 0, 0, 0};
+
+    const int nchunk = (a.rn + M_TR - 1) / M_TR;
+    const int rc0 = first_chunk(a, m, nchunk, lend);
+    if (rc0 < nchunk) {
+        const int64_t xm = (int64_t)m * a.nring * a.ldx;
+        const float* XQ = fptr(a.X, 1, a.xcomp) + xm + col;
+        const float* XU = fptr(a.X, 2, a.xcomp) + xm + pcol;
+        auto seed_of = [&](Seed<2>& s, int rc) {
+            const int r = min(rc * M_TR + frl, a.rn - 1);
+            seed_load(s, a, sbase + r, r);
+        };
+        auto emit_to = [&](int b) {
+            EmitBF<KP, FOFF, HL> e;
+            e.e0 = fpm + b * BUF + po * CLS + 16 * fs * KP + frl;
+            e.e1 = fpm + b * BUF + (po ^ 1) * CLS + 16 * fs * KP + frl;
+            return e;
+        };
+        float xr[4][NU][8];  // [Q_N, Q_S, U_N, U_S][column tile][ring k0 + e]
+        auto load_x = [&](int rc) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int r = min(rc * M_TR + k0 + e, a.rn - 1);
+                const int64_t on = (int64_t)r * a.ldx, os = (int64_t)(a.nring - 1 - r) * a.ldx;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    xr[0][u][e] = XQ[on + 16 * u];
+                    xr[1][u][e] = XQ[os + 16 * u];
+                    xr[2][u][e] = XU[on + 16 * u];
+                    xr[3][u][e] = XU[os + 16 * u];
+                }
+            }
+        };
+
+        Seed<2> sd;
+        Rec<2> f;
+        seed_of(sd, rc0);
+        if (filler) {
+            f.start(sd, m2a_weight(a, rc0 * M_TR + frl));
+            auto em = emit_to(0);
+            rec_all(f, cp, cnt, em);
+        }
+        seed_of(sd, min(rc0 + 1, nchunk - 1));
+        load_x(rc0);
+        __syncthreads();
+        for (int rc = rc0; rc < nchunk; ++rc) {
+            const int b = (rc - rc0) & 1;
+            const int rcn = min(rc + 1, nchunk - 1);
+            if (filler) f.start(sd, m2a_weight(a, rcn * M_TR + frl));
+            // SX, DX, SY, DY split
+            v8bf bh[4][NU], bl[4][NU];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                float o[4][8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    o[0][e] = xr[0][u][e] + xr[1][u][e];
+                    o[1][e] = xr[0][u][e] - xr[1][u][e];
+                    o[2][e] = flip(xr[2][u][e] + xr[3][u][e], ysg);
+                    o[3][e] = flip(xr[2][u][e] - xr[3][u][e], ysg);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) split8(o[i], bh[i][u], bl[i][u]);
+            }
+            load_x(rcn);
+            seed_of(sd, min(rc + 2, nchunk - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            auto em = emit_to(b ^ 1);
+            const __bf16* fb = fpm + b * BUF;
+            static_for<0, NPH>([&](auto ph) {
+                constexpr int P = decltype(ph)::v;
+                if constexpr ((P & 1) == 0) {
+                    constexpr int cls = (P >> 2) & 1, t = (P >> 1) & 1;
+                    const __bf16* q = fb + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
+                    const v8bf ph_ = lds8(q), pl = lds8(q + HL);               // F+
+                    const v8bf mh = lds8(q + FOFF), ml = lds8(q + FOFF + HL);  // F-
+                    // even class: E = F+ SX + F- DY, B' = F+ SY + F- DX; odd: S <-> D
+                    constexpr int X1 = cls ? 1 : 0, Y1 = cls ? 3 : 2, X2 = cls ? 0 : 1, Y2 = cls ? 2 : 3;
+#pragma unroll
+                    for (int u = 0; u < NU; ++u) {
+                        accE[cls][t][u] = mfma3(ph_, pl, bh[X1][u], bl[X1][u], accE[cls][t][u]);
+                        accB[cls][t][u] = mfma3(ph_, pl, bh[Y1][u], bl[Y1][u], accB[cls][t][u]);
+                        accE[cls][t][u] = mfma3(mh, ml, bh[Y2][u], bl[Y2][u], accE[cls][t][u]);
+                        accB[cls][t][u] = mfma3(mh, ml, bh[X2][u], bl[X2][u], accB[cls][t][u]);
+                    }
+                }
+                if (filler) rec_group<P, RPP>(f, cp, cnt, em);
+            });
+            __syncthreads();
+        }
+    }
+
+    float* AE = static_cast<float*>(a.A) + a.acomp + row0 * a.ldx;
+    float* AB = static_cast<float*>(a.A) + 2 * a.acomp + row0 * a.ldx;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ci = 16 * t + 4 * (lane >> 4) + v;
+                const int l = l0 + 2 * ci + (p ^ po);
+                if (l > L) continue;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    const int64_t o = (int64_t)(l - lb) * a.ldx + col + 16 * u;
+                    AE[o] = accE[p][t][u][v];
+                    AB[o] = accB[p][t][u][v];
+                }
+            }
+}
+
+// ============================================================================
+// alm2map, spin 0.  Tile 64 rings x 64*NU columns, l in chunks of 64.
+// LDS: [buffer][hi, lo][parity class][ring][class row (K)].
+// ============================================================================
+constexpr int A0_TR = 64;
+
+template <int NU>
+__global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
+{
+    constexpr int CLS = A0_TR * KP, HL = 2 * CLS, BUF = 2 * HL;
+    __shared__ __attribute__((aligned(16))) __bf16 lam[2 * BUF];
+    __shared__ double ctile[2][CoefTile<2>::N];
+
+    const int nrt = (a.rn + A0_TR - 1) / A0_TR;
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    const int mi = g / (a.ctiles * nrt);
+    const int m = mfold(mi, a.lmax);
+    const int rem = g - mi * a.ctiles * nrt;
+    const int ct = rem / nrt, rt = rem - ct * nrt;
+    const int L = a.lmax, lb = m;
+    const int r0 = rt * A0_TR;
+    const int lane = threadIdx.x & 63, wave = wave_index();
+    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    const int k0 = 8 * (lane >> 4);
+    const bool filler = lane < 32;
+    const int frl = 32 * (wave & 1) + (lane & 31);
+    const int fs = wave >> 1;
+    const int fr = r0 + frl;
+    const int frc = min(fr, a.rn - 1);
+    const double w = fr < a.rn ? 1.0 : 0.0;
+
+    int lfirst, nch;
+    a2m_range(a, m, lb, r0, A0_TR, lfirst, nch);
+
+    v4f accE[4][NU], accO[4][NU];  // [ring tile][column tile]
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < NU; ++u) accE[t][u] = accO[t][u] = v4f{0, 0, 0, 0};
+
+    if (nch > 0) {
+        const int64_t row0 = a.rowoff[m];
+        const float* Am = static_cast<const float*>(a.A) + row0 * a.ldx + col;
+        const int64_t sb = a.seedoff[m] + frc;
+        const int j0 = (lfirst - lb) / SEG + fs;
+        const int jmax = (L - lb) / SEG;
+        auto seed_of = [&](Seed<0>& s, int c) { seed_load(s, a, sb + (int64_t)min(j0 + 2 * c, jmax) * a.rn, frc); };
+        auto ls_of = [&](int c) { return lfirst + TL * c + SEG * fs; };
+        auto emit_to = [&](int b) {
+            EmitBF<1, 0, HL> e;
+            e.e0 = lam + b * BUF + frl * KP + 16 * fs;
+            e.e1 = e.e0 + CLS;
+            return e;
+        };
+        float ar[2][NU][8];  // [even, odd class][column tile][class row k0 + e] of the next chunk
+        auto load_a = [&](int c) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int le = lfirst + TL * c + 2 * (k0 + e);
+                const float* pe = Am + (int64_t)(min(le, L) - lb) * a.ldx;
+                const float* pq = Am + (int64_t)(min(le + 1, L) - lb) * a.ldx;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    ar[0][u][e] = pe[16 * u];
+                    ar[1][u][e] = pq[16 * u];
+                }
+            }
+        };
+
+        Seed<0> sd;
+        Rec<0> f;
+        using CT = CoefTile<2>;
+        auto tile_row = [&](int c) { return row0 + (lfirst + TL * c - lb); };
+        CT::put(ctile[0], CT::fetch(a, tile_row(0)));
+        CT::put(ctile[1], CT::fetch(a, tile_row(min(1, nch - 1))));
+        double cnext = CT::fetch(a, tile_row(min(2, nch - 1)));
+        __syncthreads();
+        seed_of(sd, 0);
+        if (filler) {
+            f.start(sd, w);
+            auto em = emit_to(0);
+            rec_all(f, ctile[0] + SEG * fs * 2, min(SEG, L - ls_of(0) + 1), em);
+        }
+        seed_of(sd, min(1, nch - 1));
+        load_a(0);
+        __syncthreads();
+        for (int c = 0; c < nch; ++c) {
+            const int b = c & 1;
+            const int cn = min(c + 1, nch - 1);
+            const double* cp = ctile[(c + 1) & 1] + SEG * fs * 2;
+            const int cnt = min(SEG, L - ls_of(cn) + 1);
+            if (filler) f.start(sd, w);
+            v8bf bh[2][NU], bl[2][NU];
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int u = 0; u < NU; ++u) split8(ar[p][u], bh[p][u], bl[p][u]);
+            load_a(cn);
+            seed_of(sd, min(c + 2, nch - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            auto em = emit_to(b ^ 1);
+            const __bf16* lb_ = lam + b * BUF;
+            static_for<0, NPH>([&](auto ph) {
+                constexpr int P = decltype(ph)::v;
+                constexpr int cls = P >> 2, t = P & 3;
+                const __bf16* q = lb_ + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
+                const v8bf ah = lds8(q), al = lds8(q + HL);
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    if constexpr (cls == 0) accE[t][u] = mfma3(ah, al, bh[0][u], bl[0][u], accE[t][u]);
+                    else accO[t][u] = mfma3(ah, al, bh[1][u], bl[1][u], accO[t][u]);
+                }
+                if (filler) rec_group<P, RPP>(f, cp, cnt, em);
+            });
+            CT::put(ctile[c & 1], cnext);  // tile of chunk c + 2
+            cnext = CT::fetch(a, tile_row(min(c + 3, nch - 1)));
+            __syncthreads();
+        }
+    }
+
+    float* X = static_cast<float*>(a.X) + (int64_t)m * a.nring * a.ldx + col;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * t + 4 * (lane >> 4) + v;
+            if (r >= a.rn) continue;
+            const int rs = a.nring - 1 - r;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const float e = accE[t][u][v], o = accO[t][u][v];
+                X[(int64_t)r * a.ldx + 16 * u] = e + o;
+                if (rs != r) X[(int64_t)rs * a.ldx + 16 * u] = e - o;
+            }
+        }
+}
+
+// ============================================================================
+// alm2map, spin 2 (see k_a2m_spin2 in k_leg.hip for the block form).
+// LDS: [buffer][hi, lo][F+, F-][parity class][ring][class row (K)].
+// ============================================================================
+constexpr int A2_TR = 32;
+
+template <int NU>
+__global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
+{
+    constexpr int CLS = A2_TR * KP, FOFF = 2 * CLS, HL = 2 * FOFF, BUF = 2 * HL;
+    __shared__ __attribute__((aligned(16))) __bf16 fpm[2 * BUF];
+    __shared__ double ctile[2][CoefTile<4>::N];
+
+    const int nrt = (a.rn + A2_TR - 1) / A2_TR;
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    const int mi = g / (a.ctiles * nrt);
+    const int m = mfold(mi, a.lmax);
+    const int rem = g - mi * a.ctiles * nrt;
+    const int ct = rem / nrt, rt = rem - ct * nrt;
+    const int L = a.lmax, lb = lbase(2, m);
+    const int po = (lb - m) & 1;
+    const int r0 = rt * A2_TR;
+    const int lane = threadIdx.x & 63, wave = wave_index();
+    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    const int k0 = 8 * (lane >> 4);
+    const bool filler = lane < 16;
+    const int frl = 16 * (wave & 1) + (lane & 15);
+    const int fs = wave >> 1;
+    const int fr = r0 + frl;
+    const int frc = min(fr, a.rn - 1);
+    const double w = fr < a.rn ? 1.0 : 0.0;
+
+    int lfirst, nch;
+    a2m_range(a, m, lb, r0, A2_TR, lfirst, nch);
+
+    v4f u1[2][NU], u2[2][NU], v1[2][NU], v2[2][NU];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < NU; ++u) u1[t][u] = u2[t][u] = v1[t][u] = v2[t][u] = v4f{0, 0, 0, 0};
+
+    if (nch > 0) {
+        const int64_t row0 = a.rowoff[m];
+        const float* AE = static_cast<const float*>(a.A) + a.acomp + row0 * a.ldx + col;
+        const float* AB = static_cast<const float*>(a.A) + 2 * a.acomp + row0 * a.ldx + col;
+        const int64_t sb = a.seedoff[m] + frc;
+        const int j0 = (lfirst - lb) / SEG + fs;
+        const int jmax = (L - lb) / SEG;
+        auto seed_of = [&](Seed<2>& s, int c) { seed_load(s, a, sb + (int64_t)min(j0 + 2 * c, jmax) * a.rn, frc); };
+        auto ls_of = [&](int c) { return lfirst + TL * c + SEG * fs; };
+        auto emit_to = [&](int b) {
+            EmitBF<1, FOFF, HL> e;
+            e.e0 = fpm + b * BUF + po * CLS + frl * KP + 16 * fs;
+            e.e1 = fpm + b * BUF + (po ^ 1) * CLS + frl * KP + 16 * fs;
+            return e;
+        };
+        float ar[4][NU][8];  // [E even, E odd, B' even, B' odd][column tile][class row k0 + e]
+        auto load_a_tile = [&](int c, int u) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int lc = lfirst + TL * c + 2 * (k0 + e);
+                const int64_t oe = (int64_t)(min(lc + po, L) - lb) * a.ldx + 16 * u;
+                const int64_t oo = (int64_t)(min(lc + (po ^ 1), L) - lb) * a.ldx + 16 * u;
+                ar[0][u][e] = AE[oe];
+                ar[1][u][e] = AE[oo];
+                ar[2][u][e] = AB[oe];
+                ar[3][u][e] = AB[oo];
+            }
+        };
+
+        Seed<2> sd;
+        Rec<2> f;
+        using CT = CoefTile<4>;
+        auto tile_row = [&](int c) { return row0 + (lfirst + TL * c - lb); };
+        CT::put(ctile[0], CT::fetch(a, tile_row(0)));
+        CT::put(ctile[1], CT::fetch(a, tile_row(min(1, nch - 1))));
+        double cnext = CT::fetch(a, tile_row(min(2, nch - 1)));
+        __syncthreads();
+        seed_of(sd, 0);
+        if (filler) {
+            f.start(sd, w);
+            auto em = emit_to(0);
+            rec_all(f, ctile[0] + SEG * fs * 4, min(SEG, L - ls_of(0) + 1), em);
+        }
+        seed_of(sd, min(1, nch - 1));
+#pragma unroll
+        for (int u = 0; u < NU; ++u) load_a_tile(0, u);
+        __syncthreads();
+        for (int c = 0; c < nch; ++c) {
+            const int b = c & 1;
+            const int cn = min(c + 1, nch - 1);
+            const double* cp = ctile[(c + 1) & 1] + SEG * fs * 4;
+            const int cnt = min(SEG, L - ls_of(cn) + 1);
+            if (filler) f.start(sd, w);
+            // Phases run column tile by column tile (u = P / (NPH / NU)): a tile's
+            // operands are split when its first phase starts and its loads for the
+            // next chunk issued right after, so only one tile's split operands and
+            // one tile's raw prefetch are live besides the accumulators.
+            static_assert(NPH % NU == 0 && NPH / NU >= 4, "four MFMA phases per column tile");
+            constexpr int PPU = NPH / NU;  // phases per column tile
+            v8bf bh[4], bl[4];
+            auto em = emit_to(b ^ 1);
+            const __bf16* fb = fpm + b * BUF;
+            static_for<0, NPH>([&](auto ph) {
+                constexpr int P = decltype(ph)::v;
+                constexpr int u = P / PPU, pu = P % PPU;
+                if constexpr (pu == 0) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) split8(ar[i][u], bh[i], bl[i]);
+                    load_a_tile(cn, u);
+                    if constexpr (u == 0) seed_of(sd, min(c + 2, nch - 1));
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if constexpr (pu < 4) {
+                    constexpr int t = pu & 1, second = pu >> 1;
+                    const __bf16* q = fb + (16 * t + (lane & 15)) * KP + k0;
+                    if constexpr (!second) {
+                        // F+ terms: U1 += F+e E_e, U2 += F+o E_o, V1 += F+e B'_e, V2 += F+o B'_o
+                        const v8bf eh = lds8(q), el = lds8(q + HL);
+                        const v8bf oh = lds8(q + CLS), ol = lds8(q + CLS + HL);
+                        u1[t][u] = mfma3(eh, el, bh[0], bl[0], u1[t][u]);
+                        u2[t][u] = mfma3(oh, ol, bh[1], bl[1], u2[t][u]);
+                        v1[t][u] = mfma3(eh, el, bh[2], bl[2], v1[t][u]);
+                        v2[t][u] = mfma3(oh, ol, bh[3], bl[3], v2[t][u]);
+                    } else {
+                        // F- terms: U1 += F-o B'_o, U2 += F-e B'_e, V1 += F-o E_o, V2 += F-e E_e
+                        const v8bf eh = lds8(q + FOFF), el = lds8(q + FOFF + HL);
+                        const v8bf oh = lds8(q + FOFF + CLS), ol = lds8(q + FOFF + CLS + HL);
+                        u1[t][u] = mfma3(oh, ol, bh[3], bl[3], u1[t][u]);
+                        u2[t][u] = mfma3(eh, el, bh[2], bl[2], u2[t][u]);
+                        v1[t][u] = mfma3(oh, ol, bh[1], bl[1], v1[t][u]);
+                        v2[t][u] = mfma3(eh, el, bh[0], bl[0], v2[t][u]);
+                    }
+                }
+                if (filler) rec_group<P, RPP>(f, cp, cnt, em);
+            });
+            CT::put(ctile[c & 1], cnext);  // tile of chunk c + 2
+            cnext = CT::fetch(a, tile_row(min(c + 3, nch - 1)));
+            __syncthreads();
+        }
+    }
+
+    const int64_t xm = (int64_t)m * a.nring * a.ldx;
+    float* XQ = static_cast<float*>(a.X) + a.xcomp + xm + col;
+    float* XU = static_cast<float*>(a.X) + 2 * a.xcomp + xm + (col ^ 1);
+    const unsigned usg = (col & 1) ? 0u : 0x80000000u;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * t + 4 * (lane >> 4) + v;
+            if (r >= a.rn) continue;
+            const int rs = a.nring - 1 - r;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const float U1 = u1[t][u][v], U2 = u2[t][u][v];
+                const float V1 = v1[t][u][v], V2 = v2[t][u][v];
+                XQ[(int64_t)r * a.ldx + 16 * u] = U1 + U2;
+                XU[(int64_t)r * a.ldx + 16 * u] = flip(V1 + V2, usg);
+                if (rs != r) {
+                    XQ[(int64_t)rs * a.ldx + 16 * u] = U1 - U2;
+                    XU[(int64_t)rs * a.ldx + 16 * u] = flip(V1 - V2, usg);
+                }
+            }
+        }
+}
+
+}  // namespace
+
+hipError_t launch_leg_m2a_bf16(const LegArgs& a, hipStream_t st)
+{
+    LegArgs b = a;
+    const dim3 blk(NT);
+    if (a.spin == 0) {
+        b.ctiles = (int)(a.ldx / 128);
+        hipLaunchKernelGGL((k_m2a_spin0_bf<2>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
+    } else {
+        b.ctiles = (int)(a.ldx / 64);
+        hipLaunchKernelGGL((k_m2a_spin2_bf<1>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_leg_a2m_bf16(const LegArgs& a, hipStream_t st)
+{
+    LegArgs b = a;
+    const dim3 blk(NT);
+    if (a.spin == 0) {
+        b.ctiles = (int)(a.ldx / 128);
+        const dim3 grid((a.lmax + 1) * b.ctiles * ((a.rn + A0_TR - 1) / A0_TR));
+        hipLaunchKernelGGL((k_a2m_spin0_bf<2>), grid, blk, 0, st, b);
+    } else {
+        b.ctiles = (int)(a.ldx / 64);
+        const dim3 grid((a.lmax + 1) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR));
+        hipLaunchKernelGGL((k_a2m_spin2_bf<1>), grid, blk, 0, st, b);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sht

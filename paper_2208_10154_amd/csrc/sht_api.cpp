@@ -727,7 +727,6 @@ int sht_plan_set_precision(sht_plan p, int prec)
 {
     if (!p) return fail(SHT_ERR_ARG, "null plan");
     if (prec != SHT_FP64 && prec != SHT_FP32 && prec != SHT_BF16X3) return fail(SHT_ERR_ARG, "unknown precision");
-    if (prec == SHT_BF16X3) return fail(SHT_ERR_UNSUPPORTED, "BF16x3 contraction is not built yet");
     p->prec = prec;
     return prep(p);
 }

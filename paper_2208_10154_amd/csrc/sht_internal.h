@@ -181,8 +181,10 @@ hipError_t launch_seeds(const SeedArgs& a, hipStream_t st);
 // recursion coefficient table (layout of LegArgs::coef); rows must be zeroed first
 hipError_t launch_coefs(double* coef, const int64_t* rowoff, int lmax, int spin, hipStream_t st);
 
-// prec: 0 FP64, 1 FP32, 2 BF16x3
+// prec: 0 FP64, 1 FP32, 2 BF16x3 (operands in the FP32 workspace)
 hipError_t launch_leg_m2a(const LegArgs& a, int prec, hipStream_t st);
 hipError_t launch_leg_a2m(const LegArgs& a, int prec, hipStream_t st);
+hipError_t launch_leg_m2a_bf16(const LegArgs& a, hipStream_t st);
+hipError_t launch_leg_a2m_bf16(const LegArgs& a, hipStream_t st);
 
 }  // namespace sht

@@ -1,7 +1,8 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Bars: FP64 <= 1e-10 relative RMS per map and component, FP32 <= 1e-5 (the
-tolerances of the transform's stated parity targets), on the same seeded inputs.
+Bars: FP64 <= 1e-10 relative RMS per map and component, FP32 and split-BF16
+(BF16x3) <= 1e-5 (the tolerances of the transform's stated parity targets), on
+the same seeded inputs.
 Sizes span several Legendre tiles (64 l x 32/64 rings), ragged column tiles
 (odd map counts), several chunks, Bluestein ring lengths (prime factors > 7)
 and odd nside.
@@ -16,7 +17,7 @@ from .gpu_util import alm_inputs, from_dev, note, rel_rms, to_dev
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-10, "fp32": 1e-5}
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -64,7 +65,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("nside,lmax,nmaps,chunk", CASES)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_alm2map_spin0(sht, nside, lmax, nmaps, chunk, prec):
     note(f"alm2map spin0 nside={nside} lmax={lmax} nmaps={nmaps} chunk={chunk} {prec}")
     a, c = alm_inputs(lmax, nmaps, False, workload=1)
@@ -75,7 +76,7 @@ def test_alm2map_spin0(sht, nside, lmax, nmaps, chunk, prec):
 
 
 @pytest.mark.parametrize("nside,lmax,nmaps,chunk", CASES)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_map2alm_spin0(sht, nside, lmax, nmaps, chunk, prec):
     note(f"map2alm spin0 nside={nside} lmax={lmax} nmaps={nmaps} chunk={chunk} {prec}")
     a, _ = alm_inputs(lmax, nmaps, False, workload=1)
@@ -97,7 +98,7 @@ POL_CASES = [
 
 
 @pytest.mark.parametrize("nside,lmax,nmaps,chunk", POL_CASES)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_alm2map_iqu(sht, nside, lmax, nmaps, chunk, prec):
     note(f"alm2map IQU nside={nside} lmax={lmax} nmaps={nmaps} chunk={chunk} {prec}")
     a, c = alm_inputs(lmax, nmaps, True, workload=2)
@@ -108,7 +109,7 @@ def test_alm2map_iqu(sht, nside, lmax, nmaps, chunk, prec):
 
 
 @pytest.mark.parametrize("nside,lmax,nmaps,chunk", POL_CASES)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_map2alm_iqu(sht, nside, lmax, nmaps, chunk, prec):
     note(f"map2alm IQU nside={nside} lmax={lmax} nmaps={nmaps} chunk={chunk} {prec}")
     a, _ = alm_inputs(lmax, nmaps, True, workload=2)
@@ -142,6 +143,30 @@ def test_map2alm_iter_matches_oracle_jacobi(sht, pol):
     # oracle residuals are 2-norms over all pixels; the library reports RMS
     rms_ref = np.array(ref_res) / np.sqrt(maps.size)
     np.testing.assert_allclose(res, rms_ref, rtol=1e-9)
+    assert all(np.diff(res) < 0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_map2alm_iter_mixed_precision(sht, prec):
+    """Jacobi iteration with the contraction in FP32 / BF16x3 and the residual in
+    FP64: the result stays within the mixed-precision bar of the oracle's FP64
+    iterates, and the residual still falls every iteration."""
+    import torch
+    nside, lmax, nmaps, niter = 16, 40, 2, 3
+    note(f"map2alm_iter mixed {prec} nside={nside} lmax={lmax} niter={niter}")
+    a, _ = alm_inputs(lmax, nmaps, True, workload=5)
+    maps = oracle.alm2map_iqu(nside, lmax, a)
+    maps = maps + synth.white_noise_like(maps, 1e-2, workload=5)
+    ref_a, _ = oracle.map2alm_iter(nside, lmax, maps, niter, pol=True)
+    ref = oracle.to_compact(ref_a)
+    p = sht.Plan(nside, lmax, 2, nmaps, precision=prec)
+    out = torch.zeros(p.alm_shape(), dtype=torch.float64, device="cuda")
+    res = p.map2alm_iter(to_dev(maps), out, niter, residuals=True)
+    p.sync()
+    got = from_dev(out)
+    p.close()
+    err = rel_rms(got, ref)
+    assert np.all(err <= TOL[prec]), err
     assert all(np.diff(res) < 0)
 
 
