@@ -44,7 +44,7 @@ constexpr int NT = 256;
 constexpr int HALF = TL / 2;   // rows of one parity class per l tile
 constexpr int KS = 8;          // MFMA K-steps per tile (4 rings, or 4 l per class, each)
 constexpr int RPK = SEG / KS;  // recursion rows emitted per K-step
-static_assert(RPK == 4, "the fill of one segment is spread over the K-steps of a tile");
+static_assert(RPK * KS == SEG, "the fill of one segment is spread over the K-steps of a tile");
 constexpr int M_TR = 32;       // map2alm: rings per chunk (= RCHUNK, the skip granularity)
 static_assert(M_TR == RCHUNK, "ring chunks and skip-table entries coincide");
 
@@ -67,9 +67,11 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
     // fill items: 32 rings x 2 segments; lanes 0..15 compute, every lane loads
-    const bool filler = lane < 16;
-    const int frl = 16 * (wave & 1) + (lane & 15);
-    const int fs = wave >> 1;
+    // fill items: 32 rings x SPT segments, one per lane (segment uniform per half-wave)
+    static_assert(M_TR * SPT == NT, "one fill item per thread");
+    constexpr bool filler = true;
+    const int frl = lane & 31;
+    const int fs = 2 * wave + (lane >> 5);
     const int ls = l0 + SEG * fs;
     const int cnt = min(SEG, L - ls + 1);
     const int64_t row0 = a.rowoff[m];
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
     CoefTile<2>::put(ctile, CoefTile<2>::fetch(a, row0 + (l0 - lb)));
     __syncthreads();
     const double* cp = ctile + SEG * fs * 2;
-    const int jseg = min(2 * lt + fs, (L - lb) / SEG);
+    const int jseg = min(SPT * lt + fs, (L - lb) / SEG);
     const int64_t sbase = a.seedoff[m] + (int64_t)jseg * a.rn;
 
     using MF = Mfma<T>;
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
         };
         auto emit_to = [&](int b) {
             Emit<T, 1, 0> e;
-            e.e0 = lam + b * BUF + frl * RS + 16 * fs;
+            e.e0 = lam + b * BUF + frl * RS + (SEG / 2) * fs;
             e.e1 = e.e0 + CLS;
             return e;
         };
@@ -201,9 +203,11 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
     const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
     const int pcol = col ^ 1;                           // Y = iU swaps re/im: partner column
     const unsigned ysg = (col & 1) ? 0u : 0x80000000u;  // Y_re = -U_im, Y_im = U_re
-    const bool filler = lane < 16;
-    const int frl = 16 * (wave & 1) + (lane & 15);
-    const int fs = wave >> 1;
+    // fill items: 32 rings x SPT segments, one per lane (segment uniform per half-wave)
+    static_assert(M_TR * SPT == NT, "one fill item per thread");
+    constexpr bool filler = true;
+    const int frl = lane & 31;
+    const int fs = 2 * wave + (lane >> 5);
     const int ls = l0 + SEG * fs;
     const int cnt = min(SEG, L - ls + 1);
     const int64_t row0 = a.rowoff[m];
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
     CoefTile<4>::put(ctile, CoefTile<4>::fetch(a, row0 + (l0 - lb)));
     __syncthreads();
     const double* cp = ctile + SEG * fs * 4;
-    const int jseg = min(2 * lt + fs, (L - lb) / SEG);
+    const int jseg = min(SPT * lt + fs, (L - lb) / SEG);
     const int64_t sbase = a.seedoff[m] + (int64_t)jseg * a.rn;
 
     using MF = Mfma<T>;
@@ -235,8 +239,8 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
         };
         auto emit_to = [&](int b) {
             Emit<T, 1, FOFF> e;
-            e.e0 = fpm + b * BUF + po * CLS + frl * RS + 16 * fs;
-            e.e1 = fpm + b * BUF + (po ^ 1) * CLS + frl * RS + 16 * fs;
+            e.e0 = fpm + b * BUF + po * CLS + frl * RS + (SEG / 2) * fs;
+            e.e1 = fpm + b * BUF + (po ^ 1) * CLS + frl * RS + (SEG / 2) * fs;
             return e;
         };
         T xb[2][4][NU];  // [K-step parity][Q_N, Q_S, U_N, U_S (partner column)][column tile]
@@ -356,10 +360,11 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
     const int r0 = rt * A0_TR;
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
-    // fill items: 64 rings x 2 segments; lanes 0..31 compute, every lane loads
-    const bool filler = lane < 32;
-    const int frl = 32 * (wave & 1) + (lane & 31);
-    const int fs = wave >> 1;
+    // fill items: 64 rings x SPT segments, two per lane: ring = lane, segments
+    // wave and wave + 4 (wave-uniform)
+    static_assert(A0_TR * SPT == 2 * NT && SPT == 8, "two fill items per thread");
+    const int frl = lane;
+    const int fs0 = wave;
     const int fr = r0 + frl;
     const int frc = min(fr, a.rn - 1);
     const double w = fr < a.rn ? 1.0 : 0.0;
@@ -378,13 +383,16 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
         const int64_t row0 = a.rowoff[m];
         const T* Am = aptr<T>(a, 0) + row0 * a.ldx + col;
         const int64_t sb = a.seedoff[m] + frc;
-        const int j0 = (lfirst - lb) / SEG + fs;
+        const int j0 = (lfirst - lb) / SEG + fs0;
         const int jmax = (L - lb) / SEG;  // last segment of this m
-        auto seed_of = [&](Seed<0>& s, int c) { seed_load(s, a, sb + (int64_t)min(j0 + 2 * c, jmax) * a.rn, frc); };
-        auto ls_of = [&](int c) { return lfirst + TL * c + SEG * fs; };
-        auto emit_to = [&](int b) {
+        // item i of this lane: segment fs0 + 4 i
+        auto seed_of = [&](Seed<0>& s, int c, int i) {
+            seed_load(s, a, sb + (int64_t)min(j0 + 4 * i + SPT * c, jmax) * a.rn, frc);
+        };
+        auto ls_of = [&](int c, int i) { return lfirst + TL * c + SEG * (fs0 + 4 * i); };
+        auto emit_to = [&](int b, int i) {
             Emit<T, RS, 0> e;
-            e.e0 = lam + b * BUF + 16 * fs * RS + frl;
+            e.e0 = lam + b * BUF + (SEG / 2) * (fs0 + 4 * i) * RS + frl;
             e.e1 = e.e0 + CLS;
             return e;
         };
@@ -400,36 +408,44 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
             }
         };
 
-        Seed<0> sd;
-        Rec<0> f;
+        Seed<0> sd[2];
+        Rec<0> f[2];
         using CT = CoefTile<2>;
         auto tile_row = [&](int c) { return row0 + (lfirst + TL * c - lb); };
         CT::put(ctile[0], CT::fetch(a, tile_row(0)));
         CT::put(ctile[1], CT::fetch(a, tile_row(min(1, nch - 1))));
         double cnext = CT::fetch(a, tile_row(min(2, nch - 1)));
         __syncthreads();
-        seed_of(sd, 0);
-        if (filler) {
-            f.start(sd, w);
-            auto em = emit_to(0);
-            rec_all(f, ctile[0] + SEG * fs * 2, min(SEG, L - ls_of(0) + 1), em);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            seed_of(sd[i], 0, i);
+            f[i].start(sd[i], w);
+            auto em = emit_to(0, i);
+            rec_all(f[i], ctile[0] + SEG * (fs0 + 4 * i) * 2, min(SEG, L - ls_of(0, i) + 1), em);
         }
-        seed_of(sd, min(1, nch - 1));
+#pragma unroll
+        for (int i = 0; i < 2; ++i) seed_of(sd[i], min(1, nch - 1), i);
         load_a(0, 0, bb[0]);
         __syncthreads();
         for (int c = 0; c < nch; ++c) {
             const int b = c & 1;
             const int cn = min(c + 1, nch - 1);
-            const double* cp = ctile[(c + 1) & 1] + SEG * fs * 2;
-            const int cnt = min(SEG, L - ls_of(cn) + 1);
-            if (filler) f.start(sd, w);
-            auto em = emit_to(b ^ 1);
+            const double* cp0 = ctile[(c + 1) & 1] + SEG * fs0 * 2;
+            const double* cp1 = cp0 + SEG * 4 * 2;
+            const int cnt0 = min(SEG, L - ls_of(cn, 0) + 1), cnt1 = min(SEG, L - ls_of(cn, 1) + 1);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) f[i].start(sd[i], w);
+            auto em0 = emit_to(b ^ 1, 0);
+            auto em1 = emit_to(b ^ 1, 1);
             const T* lb_ = lam + b * BUF;
             static_for<0, KS>([&](auto ki) {
                 constexpr int ks = decltype(ki)::v;
                 if constexpr (ks + 1 < KS) load_a(c, ks + 1, bb[(ks + 1) & 1]);
                 else load_a(cn, 0, bb[0]);
-                if constexpr (ks == KS / 2) seed_of(sd, min(c + 2, nch - 1));
+                if constexpr (ks == KS / 2) {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) seed_of(sd[i], min(c + 2, nch - 1), i);
+                }
                 // keep the prefetch ahead of this step's compute (the scheduler may sink it)
                 __builtin_amdgcn_sched_barrier(0);
                 const int kl = 4 * ks + (lane >> 4);
@@ -443,7 +459,8 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
                         accO[t][u] = MF::run(aO, bb[ks & 1][1][u], accO[t][u]);
                     }
                 }
-                if (filler) rec_group<ks, RPK>(f, cp, cnt, em);
+                rec_group<ks, RPK>(f[0], cp0, cnt0, em0);
+                rec_group<ks, RPK>(f[1], cp1, cnt1, em1);
             });
             CT::put(ctile[c & 1], cnext);  // tile of chunk c + 2
             cnext = CT::fetch(a, tile_row(min(c + 3, nch - 1)));
@@ -496,9 +513,10 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
     const int r0 = rt * A2_TR;
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
-    const bool filler = lane < 16;
-    const int frl = 16 * (wave & 1) + (lane & 15);
-    const int fs = wave >> 1;
+    static_assert(A2_TR * SPT == NT, "one fill item per thread");
+    constexpr bool filler = true;
+    const int frl = lane & 31;
+    const int fs = 2 * wave + (lane >> 5);
     const int fr = r0 + frl;
     const int frc = min(fr, a.rn - 1);
     const double w = fr < a.rn ? 1.0 : 0.0;
@@ -520,12 +538,12 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
         const int64_t sb = a.seedoff[m] + frc;
         const int j0 = (lfirst - lb) / SEG + fs;
         const int jmax = (L - lb) / SEG;  // last segment of this m
-        auto seed_of = [&](Seed<2>& s, int c) { seed_load(s, a, sb + (int64_t)min(j0 + 2 * c, jmax) * a.rn, frc); };
+        auto seed_of = [&](Seed<2>& s, int c) { seed_load(s, a, sb + (int64_t)min(j0 + SPT * c, jmax) * a.rn, frc); };
         auto ls_of = [&](int c) { return lfirst + TL * c + SEG * fs; };
         auto emit_to = [&](int b) {
             Emit<T, RS, FOFF> e;
-            e.e0 = fpm + b * BUF + po * CLS + 16 * fs * RS + frl;
-            e.e1 = fpm + b * BUF + (po ^ 1) * CLS + 16 * fs * RS + frl;
+            e.e0 = fpm + b * BUF + po * CLS + (SEG / 2) * fs * RS + frl;
+            e.e1 = fpm + b * BUF + (po ^ 1) * CLS + (SEG / 2) * fs * RS + frl;
             return e;
         };
         T bb[2][4][NU];  // [K-step parity][E even, E odd, B' even, B' odd][column tile]

@@ -30,7 +30,7 @@ constexpr int HALF = TL / 2;
 constexpr int KP = HALF + 8;   // padded K row in LDS (bf16 elements, 80 bytes)
 constexpr int NPH = 8;         // phases per tile
 constexpr int RPP = SEG / NPH; // recursion rows per phase
-static_assert(RPP == 4, "four recursion rows per phase");
+static_assert(RPP * NPH == SEG, "the fill of one segment is spread over the phases of a tile");
 constexpr int M_TR = 32;
 
 __device__ __forceinline__ v4f mfma3(v8bf ah, v8bf al, v8bf bh, v8bf bl, v4f c)
@@ -101,9 +101,11 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
     const int k0 = 8 * (lane >> 4);
-    const bool filler = lane < 16;
-    const int frl = 16 * (wave & 1) + (lane & 15);
-    const int fs = wave >> 1;
+    // fill items: 32 rings x SPT segments, one per lane (segment uniform per half-wave)
+    static_assert(32 * SPT == NT, "one fill item per thread");
+    constexpr bool filler = true;
+    const int frl = lane & 31;
+    const int fs = 2 * wave + (lane >> 5);
     const int ls = l0 + SEG * fs;
     const int cnt = min(SEG, L - ls + 1);
     const int64_t row0 = a.rowoff[m];
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
     CoefTile<2>::put(ctile, CoefTile<2>::fetch(a, row0 + (l0 - lb)));
     __syncthreads();
     const double* cp = ctile + SEG * fs * 2;
-    const int jseg = min(2 * lt + fs, (L - lb) / SEG);
+    const int jseg = min(SPT * lt + fs, (L - lb) / SEG);
     const int64_t sbase = a.seedoff[m] + (int64_t)jseg * a.rn;
 
     v4f acc[2][2][NU];  // [class][row tile][column tile]
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
         };
         auto emit_to = [&](int b) {
             EmitBF<KP, 0, HL> e;
-            e.e0 = lam + b * BUF + 16 * fs * KP + frl;
+            e.e0 = lam + b * BUF + (SEG / 2) * fs * KP + frl;
             e.e1 = e.e0 + CLS;
             return e;
         };
@@ -234,9 +236,11 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
     const int pcol = col ^ 1;
     const unsigned ysg = (col & 1) ? 0u : 0x80000000u;
     const int k0 = 8 * (lane >> 4);
-    const bool filler = lane < 16;
-    const int frl = 16 * (wave & 1) + (lane & 15);
-    const int fs = wave >> 1;
+    // fill items: 32 rings x SPT segments, one per lane (segment uniform per half-wave)
+    static_assert(32 * SPT == NT, "one fill item per thread");
+    constexpr bool filler = true;
+    const int frl = lane & 31;
+    const int fs = 2 * wave + (lane >> 5);
     const int ls = l0 + SEG * fs;
     const int cnt = min(SEG, L - ls + 1);
     const int64_t row0 = a.rowoff[m];
@@ -244,7 +248,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
     CoefTile<4>::put(ctile, CoefTile<4>::fetch(a, row0 + (l0 - lb)));
     __syncthreads();
     const double* cp = ctile + SEG * fs * 4;
-    const int jseg = min(2 * lt + fs, (L - lb) / SEG);
+    const int jseg = min(SPT * lt + fs, (L - lb) / SEG);
     const int64_t sbase = a.seedoff[m] + (int64_t)jseg * a.rn;
 
     v4f accE[2][2][NU], accB[2][2][NU];  // [class][row tile][column tile]
@@ -267,8 +271,8 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
         };
         auto emit_to = [&](int b) {
             EmitBF<KP, FOFF, HL> e;
-            e.e0 = fpm + b * BUF + po * CLS + 16 * fs * KP + frl;
-            e.e1 = fpm + b * BUF + (po ^ 1) * CLS + 16 * fs * KP + frl;
+            e.e0 = fpm + b * BUF + po * CLS + (SEG / 2) * fs * KP + frl;
+            e.e1 = fpm + b * BUF + (po ^ 1) * CLS + (SEG / 2) * fs * KP + frl;
             return e;
         };
         float xr[4][NU][8];  // [Q_N, Q_S, U_N, U_S][column tile][ring k0 + e]
@@ -389,9 +393,11 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
     const int k0 = 8 * (lane >> 4);
-    const bool filler = lane < 32;
-    const int frl = 32 * (wave & 1) + (lane & 31);
-    const int fs = wave >> 1;
+    // fill items: 64 rings x SPT segments, two per lane: ring = lane, segments
+    // wave and wave + 4 (wave-uniform)
+    static_assert(A0_TR * SPT == 2 * NT && SPT == 8, "two fill items per thread");
+    const int frl = lane;
+    const int fs0 = wave;
     const int fr = r0 + frl;
     const int frc = min(fr, a.rn - 1);
     const double w = fr < a.rn ? 1.0 : 0.0;
@@ -409,13 +415,15 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
         const int64_t row0 = a.rowoff[m];
         const float* Am = static_cast<const float*>(a.A) + row0 * a.ldx + col;
         const int64_t sb = a.seedoff[m] + frc;
-        const int j0 = (lfirst - lb) / SEG + fs;
+        const int j0 = (lfirst - lb) / SEG + fs0;
         const int jmax = (L - lb) / SEG;
-        auto seed_of = [&](Seed<0>& s, int c) { seed_load(s, a, sb + (int64_t)min(j0 + 2 * c, jmax) * a.rn, frc); };
-        auto ls_of = [&](int c) { return lfirst + TL * c + SEG * fs; };
-        auto emit_to = [&](int b) {
+        auto seed_of = [&](Seed<0>& s, int c, int i) {
+            seed_load(s, a, sb + (int64_t)min(j0 + 4 * i + SPT * c, jmax) * a.rn, frc);
+        };
+        auto ls_of = [&](int c, int i) { return lfirst + TL * c + SEG * (fs0 + 4 * i); };
+        auto emit_to = [&](int b, int i) {
             EmitBF<1, 0, HL> e;
-            e.e0 = lam + b * BUF + frl * KP + 16 * fs;
+            e.e0 = lam + b * BUF + frl * KP + (SEG / 2) * (fs0 + 4 * i);
             e.e1 = e.e0 + CLS;
             return e;
         };
@@ -434,38 +442,44 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
             }
         };
 
-        Seed<0> sd;
-        Rec<0> f;
+        Seed<0> sd[2];
+        Rec<0> f[2];
         using CT = CoefTile<2>;
         auto tile_row = [&](int c) { return row0 + (lfirst + TL * c - lb); };
         CT::put(ctile[0], CT::fetch(a, tile_row(0)));
         CT::put(ctile[1], CT::fetch(a, tile_row(min(1, nch - 1))));
         double cnext = CT::fetch(a, tile_row(min(2, nch - 1)));
         __syncthreads();
-        seed_of(sd, 0);
-        if (filler) {
-            f.start(sd, w);
-            auto em = emit_to(0);
-            rec_all(f, ctile[0] + SEG * fs * 2, min(SEG, L - ls_of(0) + 1), em);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            seed_of(sd[i], 0, i);
+            f[i].start(sd[i], w);
+            auto em = emit_to(0, i);
+            rec_all(f[i], ctile[0] + SEG * (fs0 + 4 * i) * 2, min(SEG, L - ls_of(0, i) + 1), em);
         }
-        seed_of(sd, min(1, nch - 1));
+#pragma unroll
+        for (int i = 0; i < 2; ++i) seed_of(sd[i], min(1, nch - 1), i);
         load_a(0);
         __syncthreads();
         for (int c = 0; c < nch; ++c) {
             const int b = c & 1;
             const int cn = min(c + 1, nch - 1);
-            const double* cp = ctile[(c + 1) & 1] + SEG * fs * 2;
-            const int cnt = min(SEG, L - ls_of(cn) + 1);
-            if (filler) f.start(sd, w);
+            const double* cp0 = ctile[(c + 1) & 1] + SEG * fs0 * 2;
+            const double* cp1 = cp0 + SEG * 4 * 2;
+            const int cnt0 = min(SEG, L - ls_of(cn, 0) + 1), cnt1 = min(SEG, L - ls_of(cn, 1) + 1);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) f[i].start(sd[i], w);
             v8bf bh[2][NU], bl[2][NU];
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
                 for (int u = 0; u < NU; ++u) split8(ar[p][u], bh[p][u], bl[p][u]);
             load_a(cn);
-            seed_of(sd, min(c + 2, nch - 1));
+#pragma unroll
+            for (int i = 0; i < 2; ++i) seed_of(sd[i], min(c + 2, nch - 1), i);
             __builtin_amdgcn_sched_barrier(0);
-            auto em = emit_to(b ^ 1);
+            auto em0 = emit_to(b ^ 1, 0);
+            auto em1 = emit_to(b ^ 1, 1);
             const __bf16* lb_ = lam + b * BUF;
             static_for<0, NPH>([&](auto ph) {
                 constexpr int P = decltype(ph)::v;
@@ -477,7 +491,8 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
                     if constexpr (cls == 0) accE[t][u] = mfma3(ah, al, bh[0][u], bl[0][u], accE[t][u]);
                     else accO[t][u] = mfma3(ah, al, bh[1][u], bl[1][u], accO[t][u]);
                 }
-                if (filler) rec_group<P, RPP>(f, cp, cnt, em);
+                rec_group<P, RPP>(f[0], cp0, cnt0, em0);
+                rec_group<P, RPP>(f[1], cp1, cnt1, em1);
             });
             CT::put(ctile[c & 1], cnext);  // tile of chunk c + 2
             cnext = CT::fetch(a, tile_row(min(c + 3, nch - 1)));
@@ -527,9 +542,11 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
     const int k0 = 8 * (lane >> 4);
-    const bool filler = lane < 16;
-    const int frl = 16 * (wave & 1) + (lane & 15);
-    const int fs = wave >> 1;
+    // fill items: 32 rings x SPT segments, one per lane (segment uniform per half-wave)
+    static_assert(32 * SPT == NT, "one fill item per thread");
+    constexpr bool filler = true;
+    const int frl = lane & 31;
+    const int fs = 2 * wave + (lane >> 5);
     const int fr = r0 + frl;
     const int frc = min(fr, a.rn - 1);
     const double w = fr < a.rn ? 1.0 : 0.0;
@@ -550,12 +567,12 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
         const int64_t sb = a.seedoff[m] + frc;
         const int j0 = (lfirst - lb) / SEG + fs;
         const int jmax = (L - lb) / SEG;
-        auto seed_of = [&](Seed<2>& s, int c) { seed_load(s, a, sb + (int64_t)min(j0 + 2 * c, jmax) * a.rn, frc); };
+        auto seed_of = [&](Seed<2>& s, int c) { seed_load(s, a, sb + (int64_t)min(j0 + SPT * c, jmax) * a.rn, frc); };
         auto ls_of = [&](int c) { return lfirst + TL * c + SEG * fs; };
         auto emit_to = [&](int b) {
             EmitBF<1, FOFF, HL> e;
-            e.e0 = fpm + b * BUF + po * CLS + frl * KP + 16 * fs;
-            e.e1 = fpm + b * BUF + (po ^ 1) * CLS + frl * KP + 16 * fs;
+            e.e0 = fpm + b * BUF + po * CLS + frl * KP + (SEG / 2) * fs;
+            e.e1 = fpm + b * BUF + (po ^ 1) * CLS + frl * KP + (SEG / 2) * fs;
             return e;
         };
         float ar[4][NU][8];  // [E even, E odd, B' even, B' odd][column tile][class row k0 + e]

@@ -205,6 +205,7 @@ __device__ __forceinline__ void rec_group(Rec<SPIN>& f, const double* cp, int cn
 template <int SPIN, typename E>
 __device__ __forceinline__ void rec_all(Rec<SPIN>& f, const double* cp, int cnt, E& em)
 {
+    static_assert(SEG % 4 == 0, "segments are run in groups of four rows");
     static_for<0, SEG / 4>([&](auto g) { rec_group<decltype(g)::v, 4>(f, cp, cnt, em); });
 }
 
@@ -249,9 +250,9 @@ __device__ __forceinline__ double m2a_weight(const LegArgs& a, int r)
     return (r >= a.rn) ? 0.0 : (2 * r + 1 == a.nring ? 0.5 : 1.0);
 }
 
-// alm2map tile bounds shared by both spins: first l tile start (an even number of
-// segments past lb, at or below the first significant l of the ring tile) and
-// the number of l tiles.
+// alm2map tile bounds shared by both spins: first l tile start (a whole number of
+// tiles past lb, at or below the first significant l of the ring tile) and the
+// number of l tiles.
 __device__ __forceinline__ void a2m_range(const LegArgs& a, int m, int lb, int r0, int tr, int& lfirst, int& nch)
 {
     const int L = a.lmax;
@@ -261,7 +262,7 @@ __device__ __forceinline__ void a2m_range(const LegArgs& a, int m, int lb, int r
             lsig = min(lsig, a.lsig[(int64_t)m * a.nrc + c]);
     // the table loads make these look lane-dependent to the compiler; they are
     // wave-uniform, and the coefficient addresses built from them must be too
-    lfirst = __builtin_amdgcn_readfirstlane((lsig > L) ? L + 1 : lb + SEG * (((lsig - lb) / SEG) & ~1));
+    lfirst = __builtin_amdgcn_readfirstlane((lsig > L) ? L + 1 : lb + TL * ((lsig - lb) / TL));
     nch = __builtin_amdgcn_readfirstlane((lfirst > L) ? 0 : (L - lfirst) / TL + 1);
 }
 

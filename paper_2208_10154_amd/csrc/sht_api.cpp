@@ -383,7 +383,7 @@ int build_seeds(sht_plan p, SeedSet& S, int spin)
         rowoff[m] = rows;
         int ns = nsegs(spin, L, m);
         tot += (int64_t)ns * rn;
-        tt += (ns + 1) / 2;  // TL = 2 SEG
+        tt += (ns + SPT - 1) / SPT;  // l tiles of TL = SPT segments
         rows += std::max(0, L + 1 - lbase(spin, m));
     }
     seedoff[L + 1] = tot;

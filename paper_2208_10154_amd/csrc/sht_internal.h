@@ -16,10 +16,12 @@ constexpr double SCALE_DOWN = 0x1p-600;   // 2^-SCALE_BITS
 constexpr double RESCALE_AT = 0x1p500;    // rescale when |mu| exceeds this and k >= 1
 constexpr int SIG_LOG2 = -100;            // values below 2^SIG_LOG2 count as zero
 
-// Legendre tiling: l segments of SEG values start at lb(m) + SEG*j; contraction
-// tiles cover TL = 2*SEG values of l.
-constexpr int SEG = 32;
+// Legendre tiling: l segments of SEG values start at lb(m) + SEG*j (one stored
+// seed pair each, so SEG rows of one ring can be generated independently);
+// contraction tiles cover TL = SPT * SEG values of l.
+constexpr int SEG = 8;
 constexpr int TL = 64;
+constexpr int SPT = TL / SEG;  // segments per tile
 constexpr int RCHUNK = 32;   // ring granularity of the skip table
 
 // ----------------------------------------------------------------------------
