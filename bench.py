@@ -171,6 +171,74 @@ def cpu_baseline(args):
             "seconds_per_triple": round(sec_per_triple, 1)}
 
 
+def serving(args):
+    """Config 5: a seeded mix of requests (nside 64..1024, lmax = 3 nside - 1, T or
+    IQU, both directions, FP64 or BF16x3, log-normal map counts) through the
+    batching server: a saturated pass (all requests at once) gives the capacity,
+    a Poisson pass at 80% of it gives p50/p99 latency, and a serial FP64 pass (one
+    request at a time through the same library) is the baseline.  Plan creation
+    (and graph capture) happen in a warm-up pass, timed separately."""
+    import torch
+    from paper_2208_10154_amd import serve
+    N = args.serve_requests
+    base = serve.request_mix(N, rate_hz=1.0, seed=7, mixed=args.serve_mixed)
+
+    def make_io(d):
+        nside, spin, n = d["nside"], d["spin"], d["nmaps"]
+        L, nc = 3 * nside - 1, (1 if spin == 0 else 3)
+        a_shape, m_shape = (n, nc, (L + 1) ** 2), (n, nc, 12 * nside * nside)
+        ish, osh = (a_shape, m_shape) if d["direction"] == "alm2map" else (m_shape, a_shape)
+        inp = torch.randn(ish, dtype=torch.float64, device="cuda")
+        out = torch.empty(osh, dtype=torch.float64, device="cuda")
+        ev = torch.cuda.Event()
+        ev.record()
+        return inp, out, ev
+
+    def server(depth=2, nstreams=2):
+        return serve.Server(args.serve_budget_gb * 1e9, max_slots=512, depth=depth,
+                            executor=serve.Executor(nstreams=nstreams, graphs=args.serve_graphs))
+
+    srv = server()
+    t0 = time.perf_counter()
+    warm = []
+    for key in sorted({(d["nside"], d["spin"], d["direction"], d["precision"]) for d in base}):
+        warm.append(dict(arrival=0.0, nside=key[0], spin=key[1], direction=key[2], precision=key[3], nmaps=1))
+    serve.replay(srv, warm, make_io)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    log(f"serve: warm-up (plans for {len(srv.plans)} keys) {init_s:.1f}s, {srv.used / 1e9:.1f} GB held")
+
+    def rebased(mix, scale):
+        now = srv.now()
+        return [dict(d, arrival=now + 0.05 + d["arrival"] * scale) for d in mix]
+
+    sat = serve.replay(srv, rebased([dict(d, arrival=0.0) for d in base], 0.0), make_io)
+    st_sat = serve.latency_stats(sat)
+    cap_req = N / st_sat["makespan_s"]
+    rate = 0.8 * cap_req
+    log(f"serve: saturated {st_sat}")
+    poisson = serve.replay(srv, rebased(base, 1.0 / rate), make_io)
+    st_p = serve.latency_stats(poisson)
+    log(f"serve: poisson at {rate:.2f} req/s {st_p}")
+    # serial FP64 baseline: one request at a time, each waited for
+    serial = []
+    for d in base:
+        r = serve.replay(srv, [dict(d, precision="fp64", arrival=srv.now())], make_io)[0]
+        serial.append(r)
+    st_s = serve.latency_stats(serial)
+    log(f"serve: serial fp64 {st_s}")
+    out = {"requests": N, "mix": f"nside 64-1024 (lmax 3 nside - 1), T/IQU, alm2map/map2alm, fp64/{args.serve_mixed}, "
+                                 "log-normal maps (median 16)",
+           "rate_req_per_s": round(rate, 3), "capacity_req_per_s": round(cap_req, 3),
+           "p50_ms": st_p["p50_ms"], "p99_ms": st_p["p99_ms"], "maps_per_s": st_p["maps_per_s"],
+           "saturated_maps_per_s": st_sat["maps_per_s"],
+           "serial_fp64": {"maps_per_s": st_s["maps_per_s"], "p50_ms": st_s["p50_ms"], "p99_ms": st_s["p99_ms"]},
+           "graphs": bool(args.serve_graphs), "budget_gb": args.serve_budget_gb,
+           "peak_server_gb": round(srv.peak / 1e9, 1), "init_s": round(init_s, 1)}
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +251,11 @@ def main():
     ap.add_argument("--precisions", default="fp64,fp32")
     ap.add_argument("--cpu-stride", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg (config 5)")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-budget-gb", type=float, default=240.0)
+    ap.add_argument("--serve-mixed", default="bf16x3")
+    ap.add_argument("--serve-graphs", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU split "
@@ -226,6 +299,10 @@ def main():
         for k in results:
             if k != head:
                 line["by_precision"][k]["roofline"] = roofline(args, k, results[k])
+    del alm, maps, alm_out
+    torch.cuda.empty_cache()
+    if not args.no_serve:
+        line["serve"] = serving(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
         line["cpu_baseline"] = cpu_baseline(args)

@@ -68,8 +68,14 @@ struct sht_plan_s {
     SeedSet s0, s2;
 
     // FFT work items for the current chunk size
-    Dev items_dev;
-    std::vector<FftClass> classes;
+    // FFT work lists per chunk width (map pairs per chunk), kept so that changing
+    // the chunk between calls (serving batches of different sizes) reuploads nothing
+    struct ItemSet {
+        Dev dev;
+        std::vector<FftClass> classes;
+    };
+    std::map<int, ItemSet> item_sets;
+    std::vector<FftClass> classes;  // the current width's classes
     int items_npairs = -1;
 
     // workspace
@@ -280,6 +286,12 @@ int build_fft(sht_plan p)
 int build_items(sht_plan p, int npairs)
 {
     if (p->items_npairs == npairs) return SHT_OK;
+    auto found = p->item_sets.find(npairs);
+    if (found != p->item_sets.end()) {
+        p->classes = found->second.classes;
+        p->items_npairs = npairs;
+        return SHT_OK;
+    }
     std::vector<FftItem> cls_items[3];
     int lds[3] = {0, 0, 0};
     for (int r = 0; r < p->nring; ++r) {
@@ -292,20 +304,17 @@ int build_items(sht_plan p, int npairs)
     std::vector<FftItem> all;
     size_t off[3];
     for (int c = 0; c < 3; ++c) { off[c] = all.size(); all.insert(all.end(), cls_items[c].begin(), cls_items[c].end()); }
-    if (p->items_dev.p) {
-        (void)hipFree(p->items_dev.p);
-        p->table_bytes -= p->items_dev.n;
-        p->items_dev.p = nullptr;
-    }
+    sht_plan_s::ItemSet set;
     size_t bytes = std::max<size_t>(1, all.size()) * sizeof(FftItem);
-    HIPCHK(hipMalloc(&p->items_dev.p, bytes));
-    p->items_dev.n = bytes;
+    HIPCHK(hipMalloc(&set.dev.p, bytes));
+    set.dev.n = bytes;
+    HIPCHK(hipMemcpy(set.dev.p, all.data(), all.size() * sizeof(FftItem), hipMemcpyHostToDevice));
     p->table_bytes += bytes;
-    HIPCHK(hipMemcpy(p->items_dev.p, all.data(), all.size() * sizeof(FftItem), hipMemcpyHostToDevice));
-    p->classes.clear();
     const int elems[3] = {2, 8, 16};
     for (int c = 0; c < 3; ++c)
-        p->classes.push_back(FftClass{(const FftItem*)p->items_dev.p + off[c], (int)cls_items[c].size(), lds[c], elems[c]});
+        set.classes.push_back(FftClass{(const FftItem*)set.dev.p + off[c], (int)cls_items[c].size(), lds[c], elems[c]});
+    p->classes = set.classes;
+    p->item_sets.emplace(npairs, std::move(set));
     p->items_npairs = npairs;
     return SHT_OK;
 }
@@ -658,7 +667,8 @@ void destroy_all(sht_plan p)
     drop_records(p);
     for (auto& d : p->owned)
         if (d.p) (void)hipFree(d.p);
-    if (p->items_dev.p) (void)hipFree(p->items_dev.p);
+    for (auto& kv : p->item_sets)
+        if (kv.second.dev.p) (void)hipFree(kv.second.dev.p);
     if (p->ws && p->ws_owned) (void)hipFree(p->ws);
     if (p->F) (void)hipFree(p->F);
     if (p->norms) (void)hipFree(p->norms);
