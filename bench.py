@@ -171,6 +171,58 @@ def cpu_baseline(args):
             "seconds_per_triple": round(sec_per_triple, 1)}
 
 
+def iteration_leg(args):
+    """Config 4: map2alm_iter with N_iter = 3 on nside 1024, lmax 2047, 200 IQU
+    triples (Gaussian a_lm synthesised in FP64 plus white noise at 1e-2 of each
+    map's RMS), contraction in each requested precision, residual in FP64.  Reports
+    seconds per run at N_iter 0 and 3, the per-iteration cost, triples/s and the
+    RMS residual after every iteration."""
+    import torch
+    from paper_2208_10154_amd import sht
+    nside, n, niter = args.iter_nside, args.iter_nmaps, 3
+    L = 2 * nside - 1
+    t0 = time.perf_counter()
+    p = sht.Plan(nside, L, 2, n, chunk=args.iter_chunk)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    alm = torch.empty((n, 3, (L + 1) ** 2), dtype=torch.float64, device="cuda")
+    fill_alm(alm, L, seed=220810154 + 4)
+    maps = torch.empty((n, 3, 12 * nside * nside), dtype=torch.float64, device="cuda")
+    p.alm2map(alm, maps)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4)
+    maps += 1e-2 * maps.std(dim=2, keepdim=True) * torch.randn(maps.shape, generator=g, dtype=torch.float64,
+                                                                device="cuda")
+    out = torch.empty_like(alm)
+    torch.cuda.synchronize()
+    log(f"iteration: nside {nside} lmax {L} {n} IQU triples, plan {init_s:.1f}s, inputs ready")
+    res = {}
+    stream = torch.cuda.current_stream()
+    for prec in args.iter_precisions.split(","):
+        p.set_precision(prec)
+        p.map2alm_iter(maps, out, 0)  # warm-up (work lists, iteration buffers)
+        torch.cuda.synchronize()
+        times = {}
+        for k in (0, niter):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            r = p.map2alm_iter(maps, out, k, residuals=True)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times[k] = e0.elapsed_time(e1) / 1e3
+        err = float(((out - alm).norm() / alm.norm()).item())
+        res[prec] = {"s_niter0": round(times[0], 3), f"s_niter{niter}": round(times[niter], 3),
+                     "s_per_iteration": round((times[niter] - times[0]) / niter, 3),
+                     "triples_per_s": round(n / times[niter], 2), "residual_rms": [float(f"{x:.6e}") for x in r],
+                     "rel_err_vs_input_alm": float(f"{err:.4e}")}
+        log(f"iteration {prec}: {res[prec]}")
+    p.close()
+    del alm, maps, out
+    torch.cuda.empty_cache()
+    return {"workload": f"healpix_iqu_nside{nside}_lmax{L}_x{n}_map2alm_iter{niter}", "plan_init_s": round(init_s, 2),
+            "chunk": args.iter_chunk, "noise": "white, 1e-2 of each map's RMS", "by_precision": res}
+
+
 def serving(args):
     """Config 5: a seeded mix of requests (nside 64..1024, lmax = 3 nside - 1, T or
     IQU, both directions, FP64 or BF16x3, log-normal map counts) through the
@@ -248,10 +300,15 @@ def main():
     ap.add_argument("--lmax", type=int, default=None)
     ap.add_argument("--nmaps", type=int, default=1000, help="IQU map triples per step")
     ap.add_argument("--chunk", type=int, default=125)
-    ap.add_argument("--precisions", default="fp64,fp32")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3")
     ap.add_argument("--cpu-stride", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg (config 5)")
+    ap.add_argument("--no-iter", action="store_true", help="skip the iteration leg (config 4)")
+    ap.add_argument("--iter-nside", type=int, default=1024)
+    ap.add_argument("--iter-nmaps", type=int, default=200)
+    ap.add_argument("--iter-chunk", type=int, default=64)
+    ap.add_argument("--iter-precisions", default="bf16x3,fp32,fp64")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-budget-gb", type=float, default=240.0)
     ap.add_argument("--serve-mixed", default="bf16x3")
@@ -301,6 +358,8 @@ def main():
                 line["by_precision"][k]["roofline"] = roofline(args, k, results[k])
     del alm, maps, alm_out
     torch.cuda.empty_cache()
+    if not args.no_iter:
+        line["iteration"] = iteration_leg(args)
     if not args.no_serve:
         line["serve"] = serving(args)
     if not args.no_cpu_baseline:

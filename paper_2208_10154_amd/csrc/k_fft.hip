@@ -417,6 +417,11 @@ __global__ __launch_bounds__(NT) void k_residual(FftArgs a, const FftItem* items
     const int n = c.rg.n, nseq = c.L->nseq, ls = c.L->lstride;
     const FastDiv dn(n);
 
+    // residual sums of squares per map of each sequence: accumulated in LDS within
+    // the workgroup, then one global atomic per map (same-address global atomics
+    // from every element serialise in the L2)
+    __shared__ double ssum[2 * 16];
+    if (threadIdx.x < 2 * 16) ssum[threadIdx.x] = 0.0;
     fold_load(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
     double2 res[ELEMS];
     double ssa[ELEMS], ssb[ELEMS];
@@ -451,14 +456,17 @@ __global__ __launch_bounds__(NT) void k_residual(FftArgs a, const FftItem* items
         if (e < nseq * n) {
             const int sq = dn.div(e), j = e - sq * n;
             lds[P(sq, j, ls)] = res[q];
-            const int k = 2 * (c.it.pair0 + sq);
             if (a.norms) {
-                if (ssa[q] != 0.0) atomicAdd(a.norms + (int64_t)k * a.ncomp + c.comp, ssa[q]);
-                if (ssb[q] != 0.0) atomicAdd(a.norms + (int64_t)(k + 1) * a.ncomp + c.comp, ssb[q]);
+                atomicAdd(&ssum[2 * sq], ssa[q]);
+                atomicAdd(&ssum[2 * sq + 1], ssb[q]);
             }
         }
     }
     __syncthreads();
+    if (a.norms && threadIdx.x < 2 * nseq) {
+        const int sq = threadIdx.x >> 1, k = 2 * (c.it.pair0 + sq) + (threadIdx.x & 1);
+        if (k < a.nmaps) atomicAdd(a.norms + (int64_t)k * a.ncomp + c.comp, ssum[threadIdx.x]);
+    }
     if (a.iteration_sub) unfold_store(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
 }
 

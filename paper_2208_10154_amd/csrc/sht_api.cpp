@@ -77,6 +77,7 @@ struct sht_plan_s {
     std::map<int, ItemSet> item_sets;
     std::vector<FftClass> classes;  // the current width's classes
     int items_npairs = -1;
+    int64_t ldx_cur = 0;            // row pitch of the m-major arrays for the chunk being run
 
     // workspace
     void* ws = nullptr;
@@ -531,7 +532,7 @@ FftArgs fft_args(sht_plan p, int nmaps_chunk)
     a.ncomp = p->ncomp;
     a.comp0 = 0;
     a.nmaps = nmaps_chunk;
-    a.ldx = ldx_for(p->chunk);
+    a.ldx = p->ldx_cur;
     a.npairs = (int)(a.ldx / 4);
     a.lmax = p->lmax;
     a.nring = p->nring;
@@ -558,7 +559,7 @@ LegArgs leg_args(sht_plan p, const SeedSet& S)
     a.acomp = acomp_elems(p);
     a.rowoff = (const int64_t*)S.rowoff.p;
     a.coef = (const double*)S.coef.p;
-    a.ldx = ldx_for(p->chunk);
+    a.ldx = p->ldx_cur;
     a.lmax = p->lmax;
     a.rn = p->rn;
     a.nring = p->nring;
@@ -574,7 +575,7 @@ AlmArgs alm_args(sht_plan p, const SeedSet& S, int nmaps_chunk)
     a.rowoff = (const int64_t*)S.rowoff.p;
     a.tileoff = (const int*)S.tileoff.p;
     a.ntiles = S.ntiles;
-    a.ldx = ldx_for(p->chunk);
+    a.ldx = p->ldx_cur;
     a.kblocks = (int)(a.ldx / 64);
     a.almstride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
     a.lmax = p->lmax;
@@ -589,7 +590,17 @@ int prep(sht_plan p)
 {
     int rc = ensure_workspace(p);
     if (rc) return rc;
-    return build_items(p, (int)(ldx_for(p->chunk) / 4));
+    p->ldx_cur = ldx_for(p->chunk);
+    return build_items(p, (int)(p->ldx_cur / 4));
+}
+
+// Narrow the m-major row pitch to what a chunk of nm map sets needs (a last,
+// partial chunk then computes only its own columns); the component arrays keep
+// the full chunk's spacing, so any narrower pitch fits the workspace.
+int use_width(sht_plan p, int nm)
+{
+    p->ldx_cur = ldx_for(nm);
+    return build_items(p, (int)(p->ldx_cur / 4));
 }
 
 int run_a2m(sht_plan p, const double* alm, int nm)
@@ -790,6 +801,7 @@ int sht_alm2map(sht_plan p, const double* alm, double* map)
     const int64_t mstride = (int64_t)p->ncomp * p->npix;
     for (int k0 = 0; k0 < p->nmaps; k0 += p->chunk) {
         int nm = std::min(p->chunk, p->nmaps - k0);
+        if ((rc = use_width(p, nm))) return rc;
         if ((rc = run_a2m(p, alm + k0 * astride, nm))) return rc;
         FftArgs f = fft_args(p, nm);
         f.maps_out = map + k0 * mstride;
@@ -809,6 +821,7 @@ int sht_map2alm(sht_plan p, const double* map, double* alm)
     const int64_t mstride = (int64_t)p->ncomp * p->npix;
     for (int k0 = 0; k0 < p->nmaps; k0 += p->chunk) {
         int nm = std::min(p->chunk, p->nmaps - k0);
+        if ((rc = use_width(p, nm))) return rc;
         FftArgs f = fft_args(p, nm);
         f.maps_in = map + k0 * mstride;
         {
@@ -833,6 +846,7 @@ int sht_map2alm_iter(sht_plan p, const double* map, double* alm, int niter, doub
     std::vector<double> sums(niter + 1, 0.0), hn;
     for (int k0 = 0; k0 < p->nmaps; k0 += p->chunk) {
         int nm = std::min(p->chunk, p->nmaps - k0);
+        if ((rc = use_width(p, nm))) return rc;
         double* a = alm + k0 * astride;
         FftArgs f = fft_args(p, nm);
         f.maps_in = map + k0 * mstride;

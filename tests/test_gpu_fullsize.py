@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 NSIDE, LMAX, NMAPS, CHUNK = 512, 1535, 250, 125
 SLOTS = (0, 137)
-TOL = {"fp64": 1e-10, "fp32": 1e-5}
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
 
 
 def rel(got, ref):
@@ -87,3 +87,77 @@ def test_map2alm_sampled_coefficients(batch, prec):
             e = rel(re + 1j * im, ref[c])
             assert e <= TOL[prec], (s, c, e)
     p.close()
+
+
+# --- nside 1024, lmax 2047 (the iteration workload's resolution): deep underflow of
+# the starting values (lambda_mm down to ~1e-396), Bluestein ring lengths up to 4092
+N4, L4 = 1024, 2047
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    assert torch.cuda.is_available()
+    alm_c = synth.gaussian_alm(L4, 1, True, workload=12)
+    maps_np = synth.white_maps(12 * N4 ** 2, 1, 3, workload=12)
+    return alm_c, to_dev(oracle.to_compact(alm_c)), maps_np, to_dev(maps_np)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_nside1024_sampled(big, prec):
+    import torch
+    from paper_2208_10154_amd import sht
+    alm_c, alm, maps_np, maps = big
+    note(f"nside {N4} lmax {L4} sampled alm2map/map2alm {prec}")
+    p = sht.Plan(N4, L4, 2, 1, precision=prec)
+    m_out = torch.empty(p.map_shape(), dtype=torch.float64, device="cuda")
+    a_out = torch.empty(p.alm_shape(), dtype=torch.float64, device="cuda")
+    p.alm2map(alm, m_out)
+    p.map2alm(maps, a_out)
+    p.sync()
+    p.close()
+    rng = np.random.default_rng(9)
+    pix = np.concatenate([[0, 5, 12 * N4 ** 2 - 1, 6 * N4 ** 2 + 3], rng.integers(0, 12 * N4 ** 2, 16)])
+    got = from_dev(m_out[0][:, pix])
+    ref = oracle.synth_pixels(N4, L4, alm_c[0], pix, pol=True)
+    for c in range(3):
+        assert rel(got[c], ref[c]) <= TOL[prec], ("alm2map", c)
+    ls = np.array([2, 5, 300, 1500, 2047, 2047, 1800, 2000])
+    ms = np.array([0, 3, 299, 1500, 0, 2047, 17, 1999])
+    L1 = L4 + 1
+    comp = from_dev(a_out[0])
+    ref = oracle.analyze_lm(N4, L4, maps_np[0], ls, ms, pol=True)
+    for c in range(3):
+        re = comp[c][ms * L1 + ls]
+        msafe = np.maximum(ms, 1)
+        im = np.where(ms > 0, comp[c][(L1 - msafe) * L1 + (ls - msafe)], 0.0)
+        assert rel(re + 1j * im, ref[c]) <= TOL[prec], ("map2alm", c)
+
+
+def test_nside1024_iteration_converges_and_mixed_agrees(big):
+    """Band-limited maps (lmax 2047 < 3 nside): Jacobi iterates approach the true
+    a_lm every iteration; the BF16x3 / FP64-residual iterates stay within the mixed
+    bar of the FP64 ones."""
+    import torch
+    from paper_2208_10154_amd import sht
+    _, alm, _, _ = big
+    note(f"nside {N4} iteration")
+    p = sht.Plan(N4, L4, 2, 1)
+    maps = torch.empty(p.map_shape(), dtype=torch.float64, device="cuda")
+    p.alm2map(alm, maps)
+    truth = from_dev(alm)[0]
+    errs = []
+    out = torch.empty(p.alm_shape(), dtype=torch.float64, device="cuda")
+    for niter in (0, 1, 3):
+        p.map2alm_iter(maps, out, niter)
+        p.sync()
+        errs.append(rel(from_dev(out)[0], truth))
+    fp64 = from_dev(out)[0]
+    p.set_precision("bf16x3")
+    res = p.map2alm_iter(maps, out, 3, residuals=True)
+    p.sync()
+    mixed = from_dev(out)[0]
+    p.close()
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 0.05 * errs[0], errs
+    assert all(np.diff(res) < 0), res
+    assert rel(mixed, fp64) <= 1e-5
