@@ -117,6 +117,37 @@ def run_precision(sht, args, prec, alm, maps, alm_out):
     return {"ms_per_step": per_step, "value": n * 1000.0 / per_step, "init_s": init_s, "stages": prof}
 
 
+LEG_SOURCES = ["paper_2208_10154_amd/csrc/k_leg.hip", "paper_2208_10154_amd/csrc/k_leg_bf16.hip",
+               "paper_2208_10154_amd/csrc/leg_rec.h", "paper_2208_10154_amd/csrc/leg_common.h",
+               "paper_2208_10154_amd/csrc/sht_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def leg_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in LEG_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, nside: int, lmax: int, per_launch_maps: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it
+    was taken on the current kernel sources at this workload (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = rec.get(kernel)
+    if not e or e.get("source_hash") != leg_source_hash():
+        return None
+    if (e.get("nside"), e.get("lmax"), e.get("maps_per_launch")) != (nside, lmax, per_launch_maps):
+        return None
+    return e.get("bytes_per_launch")
+
+
 def roofline(args, prec, res):
     """Dominant Legendre kernel's achieved FLOP rate from the live stage timings."""
     st = res["stages"]
@@ -127,11 +158,12 @@ def roofline(args, prec, res):
     flops_per_step = leg_flops(args.nside, args.lmax, spin, args.nmaps)
     achieved = flops_per_step * args.steps / (ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
+    kname = "k_" + name + {"fp64": "<double>", "fp32": "<float>", "bf16x3": "_bf"}[prec]
     return {
-        "kernel": {"m2a_spin0": "k_m2a_spin0", "m2a_spin2": "k_m2a_spin2", "a2m_spin0": "k_a2m_spin0",
-                   "a2m_spin2": "k_a2m_spin2"}[name] + ("<double>" if prec == "fp64" else "<float>"),
+        "kernel": kname,
         "bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-        "frac": round(achieved / peak, 4), "traffic": None,
+        "frac": round(achieved / peak, 4),
+        "traffic": measured_traffic(kname, args.nside, args.lmax, args.chunk),
         "launches": launches, "avg_launch_ms": round(ms / launches, 3),
         "flops_per_launch": flops_per_step * args.steps / launches,
     }
@@ -313,6 +345,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=240.0)
     ap.add_argument("--serve-mixed", default="bf16x3")
     ap.add_argument("--serve-graphs", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="run one plain device copy of this many GiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU split "
@@ -323,6 +357,14 @@ def main():
     import torch
     from paper_2208_10154_amd import sht
     sht.lib()
+    if args.copy_probe_gib > 0:
+        nbytes = int(args.copy_probe_gib * 2 ** 30)
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nbytes} bytes read and written once")
+        del src, dst
     n, L = args.nmaps, args.lmax
     log(f"workload nside {args.nside} lmax {L} nmaps {n} (IQU), chunk {args.chunk}")
     alm = torch.empty((n, 3, (L + 1) ** 2), dtype=torch.float64, device="cuda")
