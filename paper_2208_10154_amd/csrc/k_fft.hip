@@ -50,12 +50,36 @@ struct FastDiv {
 // LDS slot of element i of sequence sq
 __device__ __forceinline__ int P(int sq, int i, int ls) { return sq * ls + i + (i >> 4); }
 
-// R-point forward DFT (odd R) in registers with W[t] = e^{-2 pi i t/R}, using
-// the conjugate symmetry W^{(R-r)q} = conj(W^{rq}): with s_r = v_r + v_{R-r},
+// e^{-2 pi i t / R} for the odd radices: real parts c, imaginary parts s
+// (correctly rounded values of the cosines and sines of 2 pi t / R)
+template <int R>
+struct Roots;
+template <>
+struct Roots<3> {
+    static constexpr double c[3] = {1.0, -0.5, -0.5};
+    static constexpr double s[3] = {0.0, -0.8660254037844386, 0.8660254037844386};
+};
+template <>
+struct Roots<5> {
+    static constexpr double c[5] = {1.0, 0.30901699437494745, -0.8090169943749475, -0.8090169943749475,
+                                    0.30901699437494745};
+    static constexpr double s[5] = {0.0, -0.9510565162951535, -0.5877852522924731, 0.5877852522924731,
+                                    0.9510565162951535};
+};
+template <>
+struct Roots<7> {
+    static constexpr double c[7] = {1.0, 0.6234898018587335, -0.2225209339563144, -0.9009688679024191,
+                                    -0.9009688679024191, -0.2225209339563144, 0.6234898018587335};
+    static constexpr double s[7] = {0.0, -0.7818314824680298, -0.9749279121818236, -0.4338837391175581,
+                                    0.4338837391175581, 0.9749279121818236, 0.7818314824680298};
+};
+
+// R-point forward DFT (odd R) in registers, using the conjugate symmetry
+// W^{(R-r)q} = conj(W^{rq}) of W = e^{-2 pi i/R}: with s_r = v_r + v_{R-r},
 // d_r = v_r - v_{R-r}, out_q = A + iB and out_{R-q} = A - iB where
 // A = v_0 + sum_r Re(W^{rq}) s_r and B = sum_r Im(W^{rq}) d_r.
 template <int R>
-__device__ __forceinline__ void dft(double2* v, const double2* W)
+__device__ __forceinline__ void dft(double2* v)
 {
     constexpr int H = (R - 1) / 2;
     double2 sv[H], dv[H];
@@ -73,9 +97,9 @@ __device__ __forceinline__ void dft(double2* v, const double2* W)
         double2 A = v[0], B = make_double2(0.0, 0.0);
 #pragma unroll
         for (int r = 1; r <= H; ++r) {
-            const double2 w = W[(r * q) % R];
-            A.x += w.x * sv[r - 1].x; A.y += w.x * sv[r - 1].y;
-            B.x += w.y * dv[r - 1].x; B.y += w.y * dv[r - 1].y;
+            const double wc = Roots<R>::c[(r * q) % R], ws = Roots<R>::s[(r * q) % R];
+            A.x += wc * sv[r - 1].x; A.y += wc * sv[r - 1].y;
+            B.x += ws * dv[r - 1].x; B.y += ws * dv[r - 1].y;
         }
         o[q] = make_double2(A.x - B.y, A.y + B.x);
         o[R - q] = make_double2(A.x + B.y, A.y - B.x);
@@ -84,14 +108,14 @@ __device__ __forceinline__ void dft(double2* v, const double2* W)
     for (int q = 0; q < R; ++q) v[q] = o[q];
 }
 template <>
-__device__ __forceinline__ void dft<2>(double2* v, const double2*)
+__device__ __forceinline__ void dft<2>(double2* v)
 {
     double2 t = v[0];
     v[0] = cadd(t, v[1]);
     v[1] = csub(t, v[1]);
 }
 template <>
-__device__ __forceinline__ void dft<4>(double2* v, const double2*)
+__device__ __forceinline__ void dft<4>(double2* v)
 {
     double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
     double2 a2 = cadd(v[1], v[3]), a3 = csub(v[1], v[3]);
@@ -104,42 +128,51 @@ __device__ __forceinline__ void dft<4>(double2* v, const double2*)
 // One radix-R Stockham step over nseq sequences of length n held in LDS, in
 // place: every thread first reads all of its butterfly inputs, then (after a
 // barrier) writes all outputs.  Ns = product of the radices already applied.
+// For radices 2 and 4 the twiddle loads are issued before the LDS reads so that
+// their latency overlaps the reads and the barrier (the odd radices, rarer and
+// with more registers per butterfly, load them after the barrier); butterfly
+// indices past the end are clamped (reads only), so no load sits in a branch.
 template <int R, int ELEMS>
 __device__ __forceinline__ void stockham_step(double2* buf, int nseq, int n, int ls, int Ns, const double2* tw)
 {
     constexpr int MAXB = (ELEMS + R - 1) / R;
+    constexpr bool PRE = (R == 2 || R == 4);
     const int nb = n / R;
     const int tot = nseq * nb;
     const int unit = 2 * (n / (Ns * R));
     const FastDiv dnb(nb), dns(Ns);
-    double2 W[R];
-    if (R != 2 && R != 4) {
-#pragma unroll
-        for (int t = 0; t < R; ++t) W[t] = tw[(2 * n / R) * t];
-    }
-    double2 v[MAXB][R];
+    double2 v[MAXB][R], wt[MAXB][R - 1];
     int sqs[MAXB], js[MAXB];
 #pragma unroll
     for (int q = 0; q < MAXB; ++q) {
-        const int w = threadIdx.x + q * NT;
-        if (w < tot) {
-            const int sq = dnb.div(w), j = w - sq * nb;
-            sqs[q] = sq;
-            js[q] = j;
+        const int w = min((int)threadIdx.x + q * NT, tot - 1);
+        const int sq = dnb.div(w), j = w - sq * nb;
+        const int k = j - dns.div(j) * Ns;
+        sqs[q] = sq;
+        js[q] = j;
+        if (PRE) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[P(sq, j + r * nb, ls)];
+            for (int r = 1; r < R; ++r) wt[q][r - 1] = tw[r * k * unit];
         }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = buf[P(sqs[q], js[q] + r * nb, ls)];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MAXB; ++q) {
-        const int w = threadIdx.x + q * NT;
-        if (w < tot) {
+        if ((int)threadIdx.x + q * NT < tot) {
             const int sq = sqs[q], j = js[q];
             const int k = j - dns.div(j) * Ns;
+            if (!PRE) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * unit]);
-            dft<R>(v[q], W);
+                for (int r = 1; r < R; ++r) wt[q][r - 1] = tw[r * k * unit];
+            }
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], wt[q][r - 1]);
+            dft<R>(v[q]);
             const int base = (j - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[P(sq, base + r * Ns, ls)] = v[q][r];
@@ -181,23 +214,54 @@ __device__ __forceinline__ void ring_dft(double2* buf, int nseq, const FftLen* L
     }
     const int m = L->m;
     const FastDiv dm(m), dn(n);
-    for (int e = threadIdx.x; e < nseq * m; e += NT) {
+    const int totm = nseq * m, totn = nseq * n;
+    double2 c[ELEMS];
+    // x_i w_i, zero-padded to length m
+#pragma unroll
+    for (int q = 0; q < ELEMS; ++q) {
+        const int e = min((int)threadIdx.x + q * NT, totm - 1);
         const int sq = dm.div(e), i = e - sq * m;
-        double2 v = make_double2(0.0, 0.0);
-        if (i < n) v = cmul(buf[P(sq, i, ls)], chirp[i]);
-        buf[P(sq, i, ls)] = v;
+        c[q] = chirp[min(i, n - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < ELEMS; ++q) {
+        const int e = (int)threadIdx.x + q * NT;
+        if (e < totm) {
+            const int sq = dm.div(e), i = e - sq * m;
+            buf[P(sq, i, ls)] = (i < n) ? cmul(buf[P(sq, i, ls)], c[q]) : make_double2(0.0, 0.0);
+        }
     }
     __syncthreads();
     fft_lds<ELEMS>(buf, nseq, m, ls, L->nstage, L->radix, tw_m);
-    for (int e = threadIdx.x; e < nseq * m; e += NT) {
+#pragma unroll
+    for (int q = 0; q < ELEMS; ++q) {
+        const int e = min((int)threadIdx.x + q * NT, totm - 1);
         const int sq = dm.div(e), i = e - sq * m;
-        buf[P(sq, i, ls)] = conjd(cmul(buf[P(sq, i, ls)], bhat[i]));
+        c[q] = bhat[i];
+    }
+#pragma unroll
+    for (int q = 0; q < ELEMS; ++q) {
+        const int e = (int)threadIdx.x + q * NT;
+        if (e < totm) {
+            const int sq = dm.div(e), i = e - sq * m;
+            buf[P(sq, i, ls)] = conjd(cmul(buf[P(sq, i, ls)], c[q]));
+        }
     }
     __syncthreads();
     fft_lds<ELEMS>(buf, nseq, m, ls, L->nstage, L->radix, tw_m);
-    for (int e = threadIdx.x; e < nseq * n; e += NT) {
+#pragma unroll
+    for (int q = 0; q < ELEMS; ++q) {
+        const int e = min((int)threadIdx.x + q * NT, totn - 1);
         const int sq = dn.div(e), j = e - sq * n;
-        buf[P(sq, j, ls)] = cmul(chirp[j], conjd(buf[P(sq, j, ls)]));
+        c[q] = chirp[j];
+    }
+#pragma unroll
+    for (int q = 0; q < ELEMS; ++q) {
+        const int e = (int)threadIdx.x + q * NT;
+        if (e < totn) {
+            const int sq = dn.div(e), j = e - sq * n;
+            buf[P(sq, j, ls)] = cmul(c[q], conjd(buf[P(sq, j, ls)]));
+        }
     }
     __syncthreads();
 }
@@ -254,70 +318,152 @@ __device__ __forceinline__ void load_x4(const FftArgs& a, int64_t idx, double2& 
     }
 }
 
+// m values a thread handles per batch in the (un)folding: the global loads of a
+// batch (phase factors, and coefficients when folding) are all issued before
+// the first is used, so a thread waits for memory once per batch, not per m.
+constexpr int MB = 8;
+
 // Unfold the packed spectrum Z = A + i B (both Hermitian) of each sequence onto
-// T_m = e^{-i m phi0} F_{m mod n} for m = 0..lmax and store m-major.
+// T_m = e^{-i m phi0} F_{m mod n} for m = 0..lmax and store m-major.  Lanes run
+// over (m, sequence, part): an FP64 row takes two 16-byte parts per map pair
+// (map a, map b), an FP32 row one, so a wave stores contiguous row segments of
+// all nseq pairs of the ring.
 __device__ __forceinline__ void unfold_store(const FftArgs& a, const double2* buf, const FftLen* L, int s, int ring, int pair0,
                                              int comp, const double2* tw_n)
 {
     const int n = L->n, ls = L->lstride;
-    const int sq = threadIdx.x & (L->nseq - 1);
-    const int m0 = threadIdx.x >> L->lgseq, dm = NT >> L->lgseq;
-    const int col = 4 * (pair0 + sq);
+    const int lp = a.x32 ? 0 : 1;  // log2 parts per pair
+    const int part = (int)threadIdx.x & ((1 << lp) - 1);
+    const int sq = ((int)threadIdx.x >> lp) & (L->nseq - 1);
+    const int m0 = (int)threadIdx.x >> (lp + L->lgseq), dm = NT >> (lp + L->lgseq);
+    const int col = 4 * (pair0 + sq) + 2 * part;
+    const int64_t xstep = (int64_t)dm * a.nring * a.ldx;
+    int64_t xi = xidx(a, comp, m0, ring, col);
     MWalk w(m0, dm, n, s);
-    for (int mm = m0; mm <= a.lmax; mm += dm) {
-        const int jn = w.j ? n - w.j : 0;
-        const double2 z = buf[P(sq, w.j, ls)], y = buf[P(sq, jn, ls)];
-        const double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
-        const double2 Fb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
-        const double2 t = tw_n[w.ph];
-        store_x4(a, xidx(a, comp, mm, ring, col), cmul(t, Fa), cmul(t, Fb));
-        w.next();
+    for (int mb = m0; mb <= a.lmax; mb += MB * dm) {
+        double2 t[MB];
+        int jj[MB];
+#pragma unroll
+        for (int u = 0; u < MB; ++u) {
+            t[u] = tw_n[w.ph];
+            jj[u] = w.j;
+            w.next();
+        }
+#pragma unroll
+        for (int u = 0; u < MB; ++u) {
+            if (mb + u * dm <= a.lmax) {
+                const int j = jj[u], jn = j ? n - j : 0;
+                const double2 z = buf[P(sq, j, ls)], y = buf[P(sq, jn, ls)];
+                const double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
+                const double2 Fb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
+                if (a.x32) {
+                    store_x4(a, xi + u * xstep, cmul(t[u], Fa), cmul(t[u], Fb));
+                } else {
+                    *reinterpret_cast<double2*>(static_cast<double*>(a.X) + xi + u * xstep) = cmul(t[u], part ? Fb : Fa);
+                }
+            }
+        }
+        xi += MB * xstep;
     }
 }
 
 // Fold the m-major coefficients of each sequence's two maps onto the ring bins:
 // Z_j = C^a_j + i C^b_j with C_j = sum_{m = j} c_m + sum_{m >= 1, -m = j} conj(c_m),
-// c_m = e^{i m phi0} T_m.
+// c_m = e^{i m phi0} T_m.  CONJ accumulates conj(Z) instead (the input of an
+// inverse DFT taken as conj(DFT(conj Z))).  Lanes run over (m, sequence, part)
+// as in the unfolding, so a wave reads contiguous row segments; the map-b lane
+// of each pair hands its term to the map-a lane, which adds both.
+template <bool CONJ>
 __device__ __forceinline__ void fold_load(const FftArgs& a, double2* buf, const FftLen* L, int s, int ring, int pair0, int comp,
                                           const double2* tw_n)
 {
     const int n = L->n, ls = L->lstride;
     for (int e = threadIdx.x; e < L->nseq * ls; e += NT) buf[e] = make_double2(0.0, 0.0);
     __syncthreads();
-    const int sq = threadIdx.x & (L->nseq - 1);
-    const int m0 = threadIdx.x >> L->lgseq, dm = NT >> L->lgseq;
-    const int col = 4 * (pair0 + sq);
+    const int part = (int)threadIdx.x & 1;
+    const int sq = ((int)threadIdx.x >> 1) & (L->nseq - 1);
+    const int m0 = (int)threadIdx.x >> (1 + L->lgseq), dm = NT >> (1 + L->lgseq);
+    const int col = 4 * (pair0 + sq) + 2 * part;
+    const int64_t xstep = (int64_t)dm * a.nring * a.ldx;
+    const int64_t xlast = xidx(a, comp, a.lmax, ring, col);
+    int64_t xi = xidx(a, comp, m0, ring, col);
+    const double sg = CONJ ? -1.0 : 1.0;
     MWalk w(m0, dm, n, s);
-    for (int mm = m0; mm <= a.lmax; mm += dm) {
-        double2 ta, tb;
-        load_x4(a, xidx(a, comp, mm, ring, col), ta, tb);
-        const double2 ph = conjd(tw_n[w.ph]);
-        const double2 ca = cmul(ph, ta), cb = cmul(ph, tb);
-        double* p1 = reinterpret_cast<double*>(buf + P(sq, w.j, ls));
-        atomicAdd(p1, ca.x - cb.y);
-        atomicAdd(p1 + 1, ca.y + cb.x);
-        if (mm >= 1) {
-            const int jn = w.j ? n - w.j : 0;
-            double* p2 = reinterpret_cast<double*>(buf + P(sq, jn, ls));
-            atomicAdd(p2, ca.x + cb.y);
-            atomicAdd(p2 + 1, cb.x - ca.y);
+    for (int mb = m0; mb <= a.lmax; mb += MB * dm) {
+        double2 tv[MB], t[MB];
+        int jj[MB];
+#pragma unroll
+        for (int u = 0; u < MB; ++u) {
+            const int64_t xu = min(xi + u * xstep, xlast);  // rows past lmax: clamped, unused
+            if (a.x32) {
+                const float2 f = *reinterpret_cast<const float2*>(static_cast<const float*>(a.X) + xu);
+                tv[u] = make_double2(f.x, f.y);
+            } else {
+                tv[u] = *reinterpret_cast<const double2*>(static_cast<const double*>(a.X) + xu);
+            }
+            t[u] = tw_n[w.ph];
+            jj[u] = w.j;
+            w.next();
         }
-        w.next();
+#pragma unroll
+        for (int u = 0; u < MB; ++u) {
+            const int mm = mb + u * dm;
+            const double2 ph = conjd(t[u]);
+            const double2 c = cmul(ph, tv[u]);  // c_m of this lane's map
+            // the map-b lane's term, received by the map-a lane (lanes differ in bit 0)
+            const double cbx = __shfl_xor(c.x, 1), cby = __shfl_xor(c.y, 1);
+            if (part == 0 && mm <= a.lmax) {
+                const double2 ca = c, cb = make_double2(cbx, cby);
+                double* p1 = reinterpret_cast<double*>(buf + P(sq, jj[u], ls));
+                atomicAdd(p1, ca.x - cb.y);
+                atomicAdd(p1 + 1, sg * (ca.y + cb.x));
+                if (mm >= 1) {
+                    const int jn = jj[u] ? n - jj[u] : 0;
+                    double* p2 = reinterpret_cast<double*>(buf + P(sq, jn, ls));
+                    atomicAdd(p2, ca.x + cb.y);
+                    atomicAdd(p2 + 1, sg * (cb.x - ca.y));
+                }
+            }
+        }
+        xi += MB * xstep;
     }
     __syncthreads();
 }
 
-// halfcomplex position of bin j (0 <= j <= n/2) of a real length-n sequence:
-// [re F0, re F1, im F1, ..., re F(n/2-1), im F(n/2-1), re F(n/2)]
-__device__ __forceinline__ double2 hc_get(const double* f, int n, int j)
+// Halfcomplex storage of the spectrum of a real sequence of even length n:
+// [re F0, re F1, im F1, ..., re F(n/2-1), im F(n/2-1), re F(n/2)].  Positions of
+// the real and imaginary parts of bin j (0 <= j < n, bins above n/2 are the
+// conjugates of n - j); hc_im is -1 where the imaginary part is zero.
+__device__ __forceinline__ int hc_re(int n, int j)
 {
-    bool conj = false;
-    if (j > n / 2) { j = n - j; conj = true; }
-    double re, im;
-    if (j == 0) { re = f[0]; im = 0.0; }
-    else if (2 * j == n) { re = f[n - 1]; im = 0.0; }
-    else { re = f[2 * j - 1]; im = f[2 * j]; }
-    return make_double2(re, conj ? -im : im);
+    const int h = (2 * j > n) ? n - j : j;
+    return h == 0 ? 0 : (2 * h == n ? n - 1 : 2 * h - 1);
+}
+__device__ __forceinline__ int hc_im(int n, int j)
+{
+    const int h = (2 * j > n) ? n - j : j;
+    return (h == 0 || 2 * h == n) ? -1 : 2 * h;
+}
+
+// ssum[2 sq] += va, ssum[2 sq + 1] += vb, called by every lane of the wave:
+// one LDS atomic per wave when all lanes hold the same sequence
+__device__ __forceinline__ void add_norms(double* ssum, int sq, double va, double vb)
+{
+    const int s0 = __builtin_amdgcn_readfirstlane(sq);
+    if (__all(sq == s0)) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            va += __shfl_xor(va, o);
+            vb += __shfl_xor(vb, o);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&ssum[2 * s0], va);
+            atomicAdd(&ssum[2 * s0 + 1], vb);
+        }
+    } else {
+        atomicAdd(&ssum[2 * sq], va);
+        atomicAdd(&ssum[2 * sq + 1], vb);
+    }
 }
 
 struct RingCtx {
@@ -330,11 +476,19 @@ struct RingCtx {
     const double2* chirp;
     const double2* bhat;
 };
-__device__ __forceinline__ RingCtx ring_ctx(const FftArgs& a, const FftItem* items)
+// Work item of this workgroup.  The grid is one-dimensional over (component,
+// item); workgroups are dealt to the 8 XCDs round-robin, so the linear index is
+// remapped to give each XCD one contiguous range: the pair groups of a ring,
+// which write neighbouring columns of the same m-major rows, then share an L2.
+__device__ __forceinline__ RingCtx ring_ctx(const FftArgs& a, const FftItem* items, int nitems)
 {
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    const int idx = x * q + min(x, r) + (b >> 3);
+    const int comp = idx / nitems;
     RingCtx c;
-    c.it = items[blockIdx.x];
-    c.comp = a.comp0 + blockIdx.y;
+    c.it = items[idx - comp * nitems];
+    c.comp = a.comp0 + comp;
     c.rg = a.rings[c.it.ring];
     c.L = a.lens + c.rg.len;
     c.tw_n = a.tw + c.L->tw;
@@ -345,20 +499,37 @@ __device__ __forceinline__ RingCtx ring_ctx(const FftArgs& a, const FftItem* ite
 }
 
 template <int ELEMS>
-__global__ __launch_bounds__(NT) void k_fft_fwd(FftArgs a, const FftItem* items)
+__global__ __launch_bounds__(NT, ELEMS == 16 ? 2 : 4) void k_fft_fwd(FftArgs a, const FftItem* items, int nitems)
 {
     extern __shared__ double2 lds[];
-    const RingCtx c = ring_ctx(a, items);
+    const RingCtx c = ring_ctx(a, items, nitems);
     const int n = c.rg.n, nseq = c.L->nseq, ls = c.L->lstride;
     const FastDiv dn(n);
 
-    for (int e = threadIdx.x; e < nseq * n; e += NT) {
-        const int sq = dn.div(e), i = e - sq * n;
-        const int k = 2 * (c.it.pair0 + sq);
-        double re = 0.0, im = 0.0;
-        if (k < a.nmaps) re = a.maps_in[((int64_t)k * a.ncomp + c.comp) * a.npix + c.rg.first + i];
-        if (k + 1 < a.nmaps) im = a.maps_in[((int64_t)(k + 1) * a.ncomp + c.comp) * a.npix + c.rg.first + i];
-        lds[P(sq, i, ls)] = make_double2(re, im);
+    {
+        // all pixel loads of the thread first (indices clamped, so none sits in
+        // a branch), then the LDS writes: one wait for memory
+        const int tot = nseq * n;
+        const double* base = a.maps_in + (int64_t)c.comp * a.npix + c.rg.first;
+        const int64_t mstride = (int64_t)a.ncomp * a.npix;
+        double re[ELEMS], im[ELEMS];
+#pragma unroll
+        for (int q = 0; q < ELEMS; ++q) {
+            const int e = min((int)threadIdx.x + q * NT, tot - 1);
+            const int sq = dn.div(e), i = e - sq * n;
+            const int k = 2 * (c.it.pair0 + sq);
+            re[q] = base[min(k, a.nmaps - 1) * mstride + i];
+            im[q] = base[min(k + 1, a.nmaps - 1) * mstride + i];
+        }
+#pragma unroll
+        for (int q = 0; q < ELEMS; ++q) {
+            const int e = (int)threadIdx.x + q * NT;
+            if (e < tot) {
+                const int sq = dn.div(e), i = e - sq * n;
+                const int k = 2 * (c.it.pair0 + sq);
+                lds[P(sq, i, ls)] = make_double2(k < a.nmaps ? re[q] : 0.0, k + 1 < a.nmaps ? im[q] : 0.0);
+            }
+        }
     }
     __syncthreads();
     ring_dft<ELEMS>(lds, nseq, c.L, c.tw_m, c.chirp, c.bhat);
@@ -381,20 +552,15 @@ __global__ __launch_bounds__(NT) void k_fft_fwd(FftArgs a, const FftItem* items)
 }
 
 template <int ELEMS>
-__global__ __launch_bounds__(NT) void k_fft_inv(FftArgs a, const FftItem* items)
+__global__ __launch_bounds__(NT, ELEMS == 16 ? 2 : 4) void k_fft_inv(FftArgs a, const FftItem* items, int nitems)
 {
     extern __shared__ double2 lds[];
-    const RingCtx c = ring_ctx(a, items);
+    const RingCtx c = ring_ctx(a, items, nitems);
     const int n = c.rg.n, nseq = c.L->nseq, ls = c.L->lstride;
     const FastDiv dn(n);
 
-    fold_load(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
-    // inverse DFT as conj(DFT(conj(Z)))
-    for (int e = threadIdx.x; e < nseq * n; e += NT) {
-        const int sq = dn.div(e), j = e - sq * n;
-        lds[P(sq, j, ls)] = conjd(lds[P(sq, j, ls)]);
-    }
-    __syncthreads();
+    // inverse DFT as conj(DFT(conj(Z))): the fold accumulates conj(Z)
+    fold_load<true>(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
     ring_dft<ELEMS>(lds, nseq, c.L, c.tw_m, c.chirp, c.bhat);
     for (int e = threadIdx.x; e < nseq * n; e += NT) {
         const int sq = dn.div(e), i = e - sq * n;
@@ -410,57 +576,68 @@ __global__ __launch_bounds__(NT) void k_fft_inv(FftArgs a, const FftItem* items)
 // T^res_m = e^{-i m phi0} R_{m mod n} written over X; sum |r|^2 = (1/n) sum_j |R_j|^2
 // is accumulated per map (Parseval).
 template <int ELEMS>
-__global__ __launch_bounds__(NT) void k_residual(FftArgs a, const FftItem* items)
+__global__ __launch_bounds__(NT, ELEMS == 16 ? 2 : 4) void k_residual(FftArgs a, const FftItem* items, int nitems)
 {
     extern __shared__ double2 lds[];
-    const RingCtx c = ring_ctx(a, items);
+    const RingCtx c = ring_ctx(a, items, nitems);
     const int n = c.rg.n, nseq = c.L->nseq, ls = c.L->lstride;
     const FastDiv dn(n);
 
-    // residual sums of squares per map of each sequence: accumulated in LDS within
-    // the workgroup, then one global atomic per map (same-address global atomics
-    // from every element serialise in the L2)
+    // residual sums of squares per map of each sequence: reduced over the wave
+    // when the wave holds one sequence, accumulated in LDS within the workgroup,
+    // then one global atomic per map (same-address global atomics from every
+    // element serialise in the L2)
     __shared__ double ssum[2 * 16];
     if (threadIdx.x < 2 * 16) ssum[threadIdx.x] = 0.0;
-    fold_load(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
-    double2 res[ELEMS];
-    double ssa[ELEMS], ssb[ELEMS];
+    fold_load<false>(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
+    const int tot = nseq * n;
     const double dnn = (double)n;
+    const double* fbase = a.F + (int64_t)c.comp * a.npix + c.rg.first;
+    const int64_t mstride = (int64_t)a.ncomp * a.npix;
+    // stored data spectra of both maps at bin j: all loads first
+    double fa[ELEMS][2], fb[ELEMS][2];
 #pragma unroll
     for (int q = 0; q < ELEMS; ++q) {
-        const int e = threadIdx.x + q * NT;
-        ssa[q] = ssb[q] = 0.0;
-        if (e < nseq * n) {
-            const int sq = dn.div(e), j = e - sq * n;
-            const int jn = j ? n - j : 0;
-            const double2 z = lds[P(sq, j, ls)], y = lds[P(sq, jn, ls)];
-            const double2 Ca = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
-            const double2 Cb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
-            const int k = 2 * (c.it.pair0 + sq);
-            double2 Fa = make_double2(0.0, 0.0), Fb = make_double2(0.0, 0.0);
-            if (k < a.nmaps) Fa = hc_get(a.F + ((int64_t)k * a.ncomp + c.comp) * a.npix + c.rg.first, n, j);
-            if (k + 1 < a.nmaps) Fb = hc_get(a.F + ((int64_t)(k + 1) * a.ncomp + c.comp) * a.npix + c.rg.first, n, j);
-            double2 Ra = make_double2(Fa.x - dnn * Ca.x, Fa.y - dnn * Ca.y);
-            double2 Rb = make_double2(Fb.x - dnn * Cb.x, Fb.y - dnn * Cb.y);
-            if (k >= a.nmaps) Ra = make_double2(0.0, 0.0);
-            if (k + 1 >= a.nmaps) Rb = make_double2(0.0, 0.0);
-            ssa[q] = (Ra.x * Ra.x + Ra.y * Ra.y) / dnn;
-            ssb[q] = (Rb.x * Rb.x + Rb.y * Rb.y) / dnn;
-            res[q] = make_double2(Ra.x - Rb.y, Ra.y + Rb.x);  // pack as Ra + i Rb
-        }
+        const int e = min((int)threadIdx.x + q * NT, tot - 1);
+        const int sq = dn.div(e), j = e - sq * n;
+        const int k = 2 * (c.it.pair0 + sq);
+        const int ir = hc_re(n, j), ii = max(hc_im(n, j), 0);
+        const double* f0 = fbase + min(k, a.nmaps - 1) * mstride;
+        const double* f1 = fbase + min(k + 1, a.nmaps - 1) * mstride;
+        fa[q][0] = f0[ir];
+        fa[q][1] = f0[ii];
+        fb[q][0] = f1[ir];
+        fb[q][1] = f1[ii];
+    }
+    double2 res[ELEMS];
+    double ssa[ELEMS], ssb[ELEMS];
+#pragma unroll
+    for (int q = 0; q < ELEMS; ++q) {
+        const int e = min((int)threadIdx.x + q * NT, tot - 1);
+        const int sq = dn.div(e), j = e - sq * n;
+        const int jn = j ? n - j : 0;
+        const double2 z = lds[P(sq, j, ls)], y = lds[P(sq, jn, ls)];
+        const double2 Ca = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
+        const double2 Cb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
+        const int k = 2 * (c.it.pair0 + sq);
+        const double isg = hc_im(n, j) < 0 ? 0.0 : (2 * j > n ? -1.0 : 1.0);
+        const double2 Fa = make_double2(fa[q][0], isg * fa[q][1]), Fb = make_double2(fb[q][0], isg * fb[q][1]);
+        double2 Ra = make_double2(Fa.x - dnn * Ca.x, Fa.y - dnn * Ca.y);
+        double2 Rb = make_double2(Fb.x - dnn * Cb.x, Fb.y - dnn * Cb.y);
+        if (k >= a.nmaps) Ra = make_double2(0.0, 0.0);
+        if (k + 1 >= a.nmaps) Rb = make_double2(0.0, 0.0);
+        const bool live = (int)threadIdx.x + q * NT < tot;
+        ssa[q] = live ? (Ra.x * Ra.x + Ra.y * Ra.y) / dnn : 0.0;
+        ssb[q] = live ? (Rb.x * Rb.x + Rb.y * Rb.y) / dnn : 0.0;
+        res[q] = make_double2(Ra.x - Rb.y, Ra.y + Rb.x);  // pack as Ra + i Rb
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < ELEMS; ++q) {
-        const int e = threadIdx.x + q * NT;
-        if (e < nseq * n) {
-            const int sq = dn.div(e), j = e - sq * n;
-            lds[P(sq, j, ls)] = res[q];
-            if (a.norms) {
-                atomicAdd(&ssum[2 * sq], ssa[q]);
-                atomicAdd(&ssum[2 * sq + 1], ssb[q]);
-            }
-        }
+        const int e = (int)threadIdx.x + q * NT;
+        const int sq = dn.div(min(e, tot - 1));
+        if (e < tot) lds[P(sq, e - sq * n, ls)] = res[q];
+        if (a.norms) add_norms(ssum, sq, ssa[q], ssb[q]);
     }
     __syncthreads();
     if (a.norms && threadIdx.x < 2 * nseq) {
@@ -501,16 +678,16 @@ template <int E>
 hipError_t launch_one(Kind kind, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st)
 {
     size_t sh = (size_t)c.lds * sizeof(double2);
-    dim3 grid(c.nitems, ncompl);
+    dim3 grid(c.nitems * ncompl);
     if (sh > 65536) {
         const void* f = (kind == Kind::Fwd) ? (const void*)k_fft_fwd<E>
                         : (kind == Kind::Inv) ? (const void*)k_fft_inv<E> : (const void*)k_residual<E>;
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         if (e != hipSuccess) return e;
     }
-    if (kind == Kind::Fwd) hipLaunchKernelGGL(k_fft_fwd<E>, grid, dim3(NT), sh, st, a, c.items);
-    else if (kind == Kind::Inv) hipLaunchKernelGGL(k_fft_inv<E>, grid, dim3(NT), sh, st, a, c.items);
-    else hipLaunchKernelGGL(k_residual<E>, grid, dim3(NT), sh, st, a, c.items);
+    if (kind == Kind::Fwd) hipLaunchKernelGGL(k_fft_fwd<E>, grid, dim3(NT), sh, st, a, c.items, c.nitems);
+    else if (kind == Kind::Inv) hipLaunchKernelGGL(k_fft_inv<E>, grid, dim3(NT), sh, st, a, c.items, c.nitems);
+    else hipLaunchKernelGGL(k_residual<E>, grid, dim3(NT), sh, st, a, c.items, c.nitems);
     return hipGetLastError();
 }
 
@@ -519,7 +696,8 @@ hipError_t launch_classes(Kind kind, const FftArgs& a, const FftClass* cls, int 
     for (int i = 0; i < ncls; ++i) {
         if (cls[i].nitems <= 0) continue;
         hipError_t e;
-        if (cls[i].elems <= 2) e = launch_one<2>(kind, a, cls[i], ncompl, st);
+        if (cls[i].p2 && kind != Kind::Res) e = launch_fft_p2(kind == Kind::Fwd, a, cls[i], ncompl, st);
+        else if (cls[i].elems <= 2) e = launch_one<2>(kind, a, cls[i], ncompl, st);
         else if (cls[i].elems <= 8) e = launch_one<8>(kind, a, cls[i], ncompl, st);
         else e = launch_one<16>(kind, a, cls[i], ncompl, st);
         if (e != hipSuccess) return e;

@@ -1,0 +1,476 @@
+// Ring FFTs for power-of-two ring lengths (HIP, gfx950).
+//
+// Every equatorial-belt ring of a HEALPix grid has N = 4 nside pixels, a power of
+// two for the usual resolutions, and those rings hold two thirds of the pixels.
+// For them the length is a template parameter, so every stride, pass count and
+// LDS offset below is a compile-time constant: the index arithmetic that the
+// runtime-length kernels (k_fft.hip) spend most of their instructions on folds
+// into immediate offsets, and what remains is the butterflies themselves.
+//
+// Transform: two real maps are packed as z = a + i b (forward) and the length-N
+// DFT is a Stockham autosort FFT of radix-8 passes with one final radix-2, -4 or
+// -8 pass.  Each thread owns 8 values of one sequence: the first pass reads them
+// straight from global memory (forward) or gathers them from the m-major
+// coefficients (inverse), later passes exchange through LDS, and the last pass
+// leaves its outputs in natural order.  The FFT mapping is that of the paper
+// (Sec. 2.1 eq. "mm", Appendix A.1): T_m = e^{-i m phi0} F_{m mod N} forward, and
+// C_j = sum_{m = j} c_m + sum_{m >= 1, -m = j} conj(c_m), c_m = e^{i m phi0} T_m,
+// backward (mod N), with the inverse DFT taken as conj(DFT(conj C)).
+#include "sht_internal.h"
+
+namespace sht {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// forward DFTs (e^{-2 pi i jk/R}) of R values in registers, natural order out
+__device__ __forceinline__ void dft2(double2* v)
+{
+    const double2 t = v[0];
+    v[0] = cadd(t, v[1]);
+    v[1] = csub(t, v[1]);
+}
+__device__ __forceinline__ void dft4(double2* v)
+{
+    const double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    const double2 a2 = cadd(v[1], v[3]), a3 = csub(v[1], v[3]);
+    v[0] = cadd(a0, a2);
+    v[2] = csub(a0, a2);
+    v[1] = make_double2(a1.x + a3.y, a1.y - a3.x);  // a1 - i a3
+    v[3] = make_double2(a1.x - a3.y, a1.y + a3.x);  // a1 + i a3
+}
+// radix 8 by decimation in frequency: X_{2q} = DFT4(x_n + x_{n+4}),
+// X_{2q+1} = DFT4((x_n - x_{n+4}) W^n), W = e^{-2 pi i/8}
+__device__ __forceinline__ void dft8(double2* v)
+{
+    constexpr double H = 0.7071067811865476;  // 1/sqrt(2), correctly rounded
+    double2 a[4], b[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        a[n] = cadd(v[n], v[n + 4]);
+        b[n] = csub(v[n], v[n + 4]);
+    }
+    b[1] = make_double2(H * (b[1].x + b[1].y), H * (b[1].y - b[1].x));    // * (1 - i)/sqrt(2)
+    b[2] = make_double2(b[2].y, -b[2].x);                                  // * -i
+    b[3] = make_double2(H * (b[3].y - b[3].x), -H * (b[3].x + b[3].y));   // * (-1 - i)/sqrt(2)
+    dft4(a);
+    dft4(b);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[2 * q] = a[q];
+        v[2 * q + 1] = b[q];
+    }
+}
+template <int R>
+__device__ __forceinline__ void dftr(double2* v)
+{
+    if constexpr (R == 2) dft2(v);
+    else if constexpr (R == 4) dft4(v);
+    else dft8(v);
+}
+
+template <int LOGN>
+struct P2 {
+    static constexpr int N = 1 << LOGN;
+    static constexpr int E = 8;                      // values per thread
+    static constexpr int T = N / E;                  // threads per sequence
+    // sequences (map pairs) per workgroup: 4096 values (two rings of 2048) per
+    // workgroup, at most 32 pairs.  Two or more pairs give every coefficient
+    // row access 64 contiguous bytes or more (a single pair's 32 bytes per row
+    // leave every access its own partial line and page translation).
+    static constexpr int S = (4096 / N) < 1 ? 1 : ((4096 / N) > 32 ? 32 : 4096 / N);
+    static constexpr int LOGS = S == 1 ? 0 : (S == 2 ? 1 : (S == 4 ? 2 : (S == 8 ? 3 : (S == 16 ? 4 : 5))));
+    static constexpr int NTH = S * T;                // threads per workgroup
+    static constexpr int NP = (LOGN + 2) / 3;        // passes
+    static constexpr int LOGRL = LOGN - 3 * (NP - 1);  // log2 of the last radix (1..3)
+    static constexpr int SEQ = N + N / 8;            // LDS slots per sequence
+    static constexpr int LDS_BYTES = S * SEQ * 16;
+};
+
+// LDS position of element pos at the boundary after pass P (radix 8, stride
+// 8^P between the values of one butterfly).  After the first pass a thread's
+// outputs are 8 consecutive slots, after the second 8 runs of 8 lanes, 64
+// slots apart: one pad slot per 8 (resp. 8 per 64) spreads those over the
+// banks.  Later boundaries are written in runs of >= 64 lanes and need none.
+template <int P>
+__device__ __forceinline__ int padp(int pos)
+{
+    if constexpr (P == 0) return pos + (pos >> 3);
+    else if constexpr (P == 1) return pos + ((pos >> 6) << 3);
+    else return pos;
+}
+
+template <int LOGN, int PASS>
+struct Pass {
+    using C = P2<LOGN>;
+    static constexpr bool LAST = (PASS == C::NP - 1);
+    static constexpr int LOGR = LAST ? C::LOGRL : 3;
+    static constexpr int R = 1 << LOGR;
+    static constexpr int B = 8 / R;                  // butterflies per thread
+    static constexpr int LOGNS = 3 * PASS;
+    static constexpr int NS = 1 << LOGNS;            // product of the earlier radices
+    static constexpr int TWS = 2 * (C::N >> (LOGNS + LOGR));  // twiddle index step in e^{-i pi t/N}
+};
+
+// twiddles of pass PASS (>= 1): w^{r k}, w = e^{-2 pi i/(NS R)}, k = j mod NS
+template <int LOGN, int PASS>
+__device__ __forceinline__ void load_twiddles(double2 (&w)[8], int tl, const double2* tw)
+{
+    using Q = Pass<LOGN, PASS>;
+#pragma unroll
+    for (int b = 0; b < Q::B; ++b) {
+        const int k = (tl + P2<LOGN>::T * b) & (Q::NS - 1);
+#pragma unroll
+        for (int r = 1; r < Q::R; ++r) w[b * Q::R + r] = tw[Q::TWS * r * k];
+    }
+}
+
+// Runs passes PASS..NP-1 on the values in v (inputs of pass PASS, twiddles w
+// already loaded).  On return v holds the last pass's outputs: value b*R + r is
+// element tl + T*b + r*N/R of the transform.
+template <int LOGN, int PASS>
+__device__ __forceinline__ void run_passes(double2 (&v)[8], double2 (&w)[8], double2* sb, int tl, const double2* tw)
+{
+    using C = P2<LOGN>;
+    using Q = Pass<LOGN, PASS>;
+    if constexpr (PASS > 0) {
+#pragma unroll
+        for (int b = 0; b < Q::B; ++b) {
+#pragma unroll
+            for (int r = 1; r < Q::R; ++r) v[b * Q::R + r] = cmul(v[b * Q::R + r], w[b * Q::R + r]);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < Q::B; ++b) dftr<Q::R>(v + b * Q::R);
+    if constexpr (!Q::LAST) {
+        using Q2 = Pass<LOGN, PASS + 1>;
+        load_twiddles<LOGN, PASS + 1>(w, tl, tw);  // in flight across the exchange
+        if constexpr (PASS > 0) __syncthreads();    // earlier readers of sb are done
+        // outputs y[(j - k) R + k + r NS] (radix 8, one butterfly per thread)
+        {
+            const int j = tl, k = j & (Q::NS - 1);
+            const int pos = (j - k) * 8 + k;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) sb[padp<PASS>(pos + r * Q::NS)] = v[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < Q2::B; ++b) {
+#pragma unroll
+            for (int r = 0; r < Q2::R; ++r)
+                v[b * Q2::R + r] = sb[padp<PASS>(tl + C::T * b + r * (C::N / Q2::R))];
+        }
+        run_passes<LOGN, PASS + 1>(v, w, sb, tl, tw);
+    }
+}
+
+// Work item of this workgroup: the grid is one-dimensional over (component,
+// item); workgroups are dealt to the 8 XCDs round-robin, so the block index is
+// remapped to give each XCD one contiguous range (neighbouring pair groups of a
+// ring, which write adjacent columns of the same m-major rows, then share an L2).
+struct Item {
+    int ring, pair0, comp;
+};
+__device__ __forceinline__ Item work_item(const FftItem* items, int nitems, int comp0)
+{
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    const int idx = x * q + min(x, r) + (b >> 3);
+    const int comp = idx / nitems;
+    const FftItem it = items[idx - comp * nitems];
+    return Item{it.ring, it.pair0, comp0 + comp};
+}
+
+// m values per thread and batch in the unfolding (loads of a batch issued first)
+constexpr int MB = 8;
+
+template <typename XT>
+__device__ __forceinline__ void store4(XT* p, double2 ta, double2 tb)
+{
+    if constexpr (sizeof(XT) == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4((float)ta.x, (float)ta.y, (float)tb.x, (float)tb.y);
+    } else {
+        reinterpret_cast<double2*>(p)[0] = ta;
+        reinterpret_cast<double2*>(p)[1] = tb;
+    }
+}
+template <typename XT>
+__device__ __forceinline__ void load4(const XT* p, double2& ta, double2& tb)
+{
+    if constexpr (sizeof(XT) == 4) {
+        const float4 f = *reinterpret_cast<const float4*>(p);
+        ta = make_double2(f.x, f.y);
+        tb = make_double2(f.z, f.w);
+    } else {
+        ta = reinterpret_cast<const double2*>(p)[0];
+        tb = reinterpret_cast<const double2*>(p)[1];
+    }
+}
+
+template <int LOGN, typename XT>
+__device__ __forceinline__ void fwd_item(const FftArgs& a, const Item it, double2* lds)
+{
+    using C = P2<LOGN>;
+    constexpr int N = C::N, T = C::T, S = C::S;
+    const RingDev rg = a.rings[it.ring];
+    const double2* tw = a.tw + a.lens[rg.len].tw;  // e^{-i pi t/N}, t < 2N
+    const int seq = (int)threadIdx.x / T, tl = (int)threadIdx.x % T;
+    double2* sb = lds + seq * C::SEQ;
+    const int k = 2 * (it.pair0 + seq);
+
+    // pass-0 inputs x[tl + r T] of map pair (k, k+1), straight from global memory
+    double2 v[8], w[8];
+    {
+        const int64_t ms = (int64_t)a.ncomp * a.npix;
+        const double* pa = a.maps_in + (int64_t)it.comp * a.npix + rg.first + min(k, a.nmaps - 1) * ms;
+        const double* pb = a.maps_in + (int64_t)it.comp * a.npix + rg.first + min(k + 1, a.nmaps - 1) * ms;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = make_double2(pa[tl + r * T], pb[tl + r * T]);
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            v[r] = make_double2(k < a.nmaps ? v[r].x : 0.0, k + 1 < a.nmaps ? v[r].y : 0.0);
+    }
+    run_passes<LOGN, 0>(v, w, sb, tl, tw);
+
+    // spectrum Z in natural order into LDS
+    using QL = Pass<LOGN, C::NP - 1>;
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < QL::B; ++b) {
+#pragma unroll
+        for (int r = 0; r < QL::R; ++r) sb[tl + T * b + r * (N / QL::R)] = v[b * QL::R + r];
+    }
+    __syncthreads();
+
+    if (a.F) {  // keep the data spectra of both maps (iterative map2alm), halfcomplex
+        for (int pos = tl; pos < N; pos += T) {
+            const int j = (pos == 0) ? 0 : (pos == N - 1 ? N / 2 : (pos + 1) / 2);
+            const int jn = (N - j) & (N - 1);
+            const double2 z = sb[j], y = sb[jn];
+            const double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
+            const double2 Fb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
+            const bool im = (pos != 0) && (pos != N - 1) && ((pos & 1) == 0);
+            if (k < a.nmaps) a.F[((int64_t)k * a.ncomp + it.comp) * a.npix + rg.first + pos] = im ? Fa.y : Fa.x;
+            if (k + 1 < a.nmaps)
+                a.F[((int64_t)(k + 1) * a.ncomp + it.comp) * a.npix + rg.first + pos] = im ? Fb.y : Fb.x;
+        }
+    }
+
+    // unfold T_m = e^{-i m phi0} F_{m mod N}.  Lanes run over (m, pair, part):
+    // FP64 rows take two 16-byte parts per pair (map k, map k+1), FP32 rows one,
+    // so the lanes of a wave store contiguous row segments of all S pairs.
+    constexpr int LP = sizeof(XT) == 8 ? 1 : 0;  // log2 parts per pair
+    constexpr int MSTEP = C::NTH >> (LP + C::LOGS);
+    const int part = (int)threadIdx.x & ((1 << LP) - 1);
+    const int sq = ((int)threadIdx.x >> LP) & (S - 1);
+    const int mi = (int)threadIdx.x >> (LP + C::LOGS);
+    const double2* zs = lds + sq * C::SEQ;
+    XT* X = static_cast<XT*>(a.X) + (int64_t)it.comp * a.xcomp + (int64_t)it.ring * a.ldx + 4 * (it.pair0 + sq) + 2 * part;
+    const int64_t mrow = (int64_t)a.nring * a.ldx;
+    const int s = rg.s;
+    for (int m0 = mi; m0 <= a.lmax; m0 += MB * MSTEP) {
+        double2 ph[MB];
+#pragma unroll
+        for (int u = 0; u < MB; ++u) ph[u] = tw[((m0 + u * MSTEP) * s) & (2 * N - 1)];
+#pragma unroll
+        for (int u = 0; u < MB; ++u) {
+            const int m = m0 + u * MSTEP;
+            if (m <= a.lmax) {
+                const int j = m & (N - 1), jn = (N - j) & (N - 1);
+                const double2 z = zs[j], y = zs[jn];
+                const double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
+                const double2 Fb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
+                if constexpr (sizeof(XT) == 8) {
+                    *reinterpret_cast<double2*>(X + m * mrow) = cmul(ph[u], part ? Fb : Fa);
+                } else {
+                    store4<XT>(X + m * mrow, cmul(ph[u], Fa), cmul(ph[u], Fb));
+                }
+            }
+        }
+    }
+}
+
+template <int LOGN, typename XT>
+__global__ __launch_bounds__(P2<LOGN>::NTH, 4) void k_fft_fwd_p2(FftArgs a, const FftItem* items, int nitems)
+{
+    extern __shared__ double2 lds[];
+    fwd_item<LOGN, XT>(a, work_item(items, nitems, a.comp0), lds);
+}
+
+template <int LOGN, typename XT>
+__device__ __forceinline__ void inv_item(const FftArgs& a, const Item it, double2* lds)
+{
+    using C = P2<LOGN>;
+    constexpr int N = C::N, T = C::T, S = C::S;
+    constexpr int MSTEP = C::NTH >> C::LOGS;  // = T
+    const RingDev rg = a.rings[it.ring];
+    const double2* tw = a.tw + a.lens[rg.len].tw;
+    const int s = rg.s, lmax = a.lmax;
+
+    // Fold: C_j = sum_{m = j} c_m + sum_{m >= 1, -m = j} conj(c_m) of both maps,
+    // Z = C^a + i C^b, into LDS in natural order.  Lanes run over (m, pair) so a
+    // wave reads contiguous row segments of all S pairs.  d_m = c^a_m + i c^b_m is
+    // the direct term, e_m = conj(c^a_m) + i conj(c^b_m) the mirror term.
+    {
+        const int sq = (int)threadIdx.x & (S - 1);
+        const int mi = (int)threadIdx.x >> C::LOGS;
+        double2* zs = lds + sq * C::SEQ;
+        const XT* X = static_cast<const XT*>(a.X) + (int64_t)it.comp * a.xcomp + (int64_t)it.ring * a.ldx +
+                      4 * (it.pair0 + sq);
+        const int64_t mrow = (int64_t)a.nring * a.ldx;
+        if (lmax < N) {
+            // every bin has at most one direct and one mirror term: bins j = m
+            // take d_m (zero beyond lmax), then bins N - m add e_m
+            double2 e[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {  // m = mi + u T covers 0..N-1
+                const int m = mi + u * MSTEP;
+                double2 ta, tb;
+                load4<XT>(X + min(m, lmax) * mrow, ta, tb);
+                const double2 p = tw[(m * s) & (2 * N - 1)];
+                const double2 ph = make_double2(p.x, -p.y);  // e^{+i m phi0}
+                const double2 ca = cmul(ph, ta), cb = cmul(ph, tb);
+                const bool live = m <= lmax;
+                zs[m] = live ? make_double2(ca.x - cb.y, ca.y + cb.x) : make_double2(0.0, 0.0);
+                e[u] = (live && m >= 1) ? make_double2(ca.x + cb.y, cb.x - ca.y) : make_double2(0.0, 0.0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int m = mi + u * MSTEP;
+                if (m >= 1 && m <= lmax) {
+                    double2& z = zs[N - m];
+                    z = make_double2(z.x + e[u].x, z.y + e[u].y);
+                }
+            }
+        } else {
+            // aliased rows (lmax >= N): several terms per bin, added atomically
+            for (int e = (int)threadIdx.x; e < S * C::SEQ; e += C::NTH) lds[e] = make_double2(0.0, 0.0);
+            __syncthreads();
+            for (int m0 = mi; m0 <= lmax; m0 += MB * MSTEP) {
+                double2 ta[MB], tb[MB], p[MB];
+#pragma unroll
+                for (int u = 0; u < MB; ++u) {
+                    const int m = m0 + u * MSTEP;
+                    load4<XT>(X + min(m, lmax) * mrow, ta[u], tb[u]);
+                    p[u] = tw[(m * s) & (2 * N - 1)];
+                }
+#pragma unroll
+                for (int u = 0; u < MB; ++u) {
+                    const int m = m0 + u * MSTEP;
+                    if (m <= lmax) {
+                        const double2 ph = make_double2(p[u].x, -p[u].y);
+                        const double2 ca = cmul(ph, ta[u]), cb = cmul(ph, tb[u]);
+                        double* z1 = reinterpret_cast<double*>(zs + (m & (N - 1)));
+                        atomicAdd(z1, ca.x - cb.y);
+                        atomicAdd(z1 + 1, ca.y + cb.x);
+                        if (m >= 1) {
+                            double* z2 = reinterpret_cast<double*>(zs + ((N - (m & (N - 1))) & (N - 1)));
+                            atomicAdd(z2, ca.x + cb.y);
+                            atomicAdd(z2 + 1, cb.x - ca.y);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // pass-0 inputs conj(Z_j) at bins j = tl + r T; the inverse DFT is conj(DFT(conj Z))
+    const int seq = (int)threadIdx.x / T, tl = (int)threadIdx.x % T;
+    double2* sb = lds + seq * C::SEQ;
+    double2 v[8], w[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const double2 z = sb[tl + r * T];
+        v[r] = make_double2(z.x, -z.y);
+    }
+    __syncthreads();  // pass 0 overwrites the buffer
+    run_passes<LOGN, 0>(v, w, sb, tl, tw);
+
+    // natural-order outputs: map k = Re, map k+1 = -Im (conjugate of the DFT)
+    using QL = Pass<LOGN, C::NP - 1>;
+    const int k = 2 * (it.pair0 + seq);
+    const int64_t ms = (int64_t)a.ncomp * a.npix;
+    double* oa = a.maps_out + (int64_t)it.comp * a.npix + rg.first + (int64_t)k * ms;
+    if (k < a.nmaps) {
+#pragma unroll
+        for (int b = 0; b < QL::B; ++b) {
+#pragma unroll
+            for (int r = 0; r < QL::R; ++r) oa[tl + T * b + r * (N / QL::R)] = v[b * QL::R + r].x;
+        }
+    }
+    if (k + 1 < a.nmaps) {
+#pragma unroll
+        for (int b = 0; b < QL::B; ++b) {
+#pragma unroll
+            for (int r = 0; r < QL::R; ++r) oa[ms + tl + T * b + r * (N / QL::R)] = -v[b * QL::R + r].y;
+        }
+    }
+}
+
+template <int LOGN, typename XT>
+__global__ __launch_bounds__(P2<LOGN>::NTH, 4) void k_fft_inv_p2(FftArgs a, const FftItem* items, int nitems)
+{
+    extern __shared__ double2 lds[];
+    inv_item<LOGN, XT>(a, work_item(items, nitems, a.comp0), lds);
+}
+
+template <int LOGN, typename XT>
+hipError_t launch_p2(bool fwd, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st)
+{
+    using C = P2<LOGN>;
+    const dim3 grid(c.nitems * ncompl);
+    if (C::LDS_BYTES > 65536) {
+        const void* f = fwd ? (const void*)k_fft_fwd_p2<LOGN, XT> : (const void*)k_fft_inv_p2<LOGN, XT>;
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
+        if (e != hipSuccess) return e;
+    }
+    if (fwd) hipLaunchKernelGGL((k_fft_fwd_p2<LOGN, XT>), grid, dim3(C::NTH), C::LDS_BYTES, st, a, c.items, c.nitems);
+    else hipLaunchKernelGGL((k_fft_inv_p2<LOGN, XT>), grid, dim3(C::NTH), C::LDS_BYTES, st, a, c.items, c.nitems);
+    return hipGetLastError();
+}
+
+template <typename XT>
+hipError_t launch_p2_x(bool fwd, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st)
+{
+    switch (c.p2) {
+        case 6: return launch_p2<6, XT>(fwd, a, c, ncompl, st);
+        case 7: return launch_p2<7, XT>(fwd, a, c, ncompl, st);
+        case 8: return launch_p2<8, XT>(fwd, a, c, ncompl, st);
+        case 9: return launch_p2<9, XT>(fwd, a, c, ncompl, st);
+        case 10: return launch_p2<10, XT>(fwd, a, c, ncompl, st);
+        case 11: return launch_p2<11, XT>(fwd, a, c, ncompl, st);
+        case 12: return launch_p2<12, XT>(fwd, a, c, ncompl, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int p2_seqs_per_group(int logn)
+{
+    switch (logn) {
+        case 6: return P2<6>::S;
+        case 7: return P2<7>::S;
+        case 8: return P2<8>::S;
+        case 9: return P2<9>::S;
+        case 10: return P2<10>::S;
+        case 11: return P2<11>::S;
+        case 12: return P2<12>::S;
+        default: return 0;
+    }
+}
+
+hipError_t launch_fft_p2(bool forward, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st)
+{
+    if (c.nitems <= 0) return hipSuccess;
+    return a.x32 ? launch_p2_x<float>(forward, a, c, ncompl, st) : launch_p2_x<double>(forward, a, c, ncompl, st);
+}
+
+}  // namespace sht

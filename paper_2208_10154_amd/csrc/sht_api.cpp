@@ -260,6 +260,25 @@ int build_fft(sht_plan p)
             L.lstride = base + (((want - base) % 16) + 16) % 16;
         }
         L.lds = L.nseq * L.lstride;
+        // power-of-two lengths run the compile-time-length kernels, which fix
+        // their own map pairs per workgroup (the runtime-length layout above is
+        // kept for the residual kernel of the iteration)
+        L.p2 = 0;
+        if (!L.blue && (r.n & (r.n - 1)) == 0) {
+            int lg = 0;
+            while ((1 << lg) < r.n) ++lg;
+            const int S = p2_seqs_per_group(lg);
+            if (S > 0) {
+                L.p2 = lg;
+                L.nseq = S;
+                L.lgseq = 0;
+                while ((1 << L.lgseq) < S) ++L.lgseq;
+                L.ldsc = S * r.n;
+                const int base = len + len / 16, want = (16 / L.nseq) % 16;
+                L.lstride = base + (((want - base) % 16) + 16) % 16;
+                L.lds = L.nseq * L.lstride;
+            }
+        }
         r.len = (int)p->lens.size();
         len_index[r.n] = r.len;
         if (L.blue) blue.push_back(r.len);
@@ -275,6 +294,7 @@ int build_fft(sht_plan p)
     p->d_lens = (FftLen*)dlens.p;
     p->d_tw = (double2*)dtw.p;
     p->d_bhat = (double2*)dbhat.p;
+
     if (!blue.empty()) {
         if ((rc = upload(p, dblue, blue))) return rc;
         HIPCHK(launch_bluestein_init(p->d_lens, (const int*)dblue.p, (int)blue.size(), p->d_tw, p->d_bhat,
@@ -293,27 +313,34 @@ int build_items(sht_plan p, int npairs)
         p->items_npairs = npairs;
         return SHT_OK;
     }
-    std::vector<FftItem> cls_items[3];
-    int lds[3] = {0, 0, 0};
+    // classes 0..2: runtime-length kernels by LDS size; 3 + (k - 6): length 2^k
+    constexpr int NCLS = 3 + 7;
+    std::vector<FftItem> cls_items[NCLS];
+    int lds[NCLS] = {};
     for (int r = 0; r < p->nring; ++r) {
         const FftLen& L = p->lens[p->rings[r].len];
         int c = (L.ldsc <= 2 * FFT_THREADS) ? 0 : (L.ldsc <= 8 * FFT_THREADS ? 1 : 2);
+        if (L.p2) c = 3 + (L.p2 - 6);
         lds[c] = std::max(lds[c], L.lds);
         if (npairs % L.nseq) return fail(SHT_ERR_UNSUPPORTED, "map pairs per chunk not a multiple of the ring batch");
         for (int q = 0; q < npairs; q += L.nseq) cls_items[c].push_back(FftItem{r, q});
     }
     std::vector<FftItem> all;
-    size_t off[3];
-    for (int c = 0; c < 3; ++c) { off[c] = all.size(); all.insert(all.end(), cls_items[c].begin(), cls_items[c].end()); }
+    size_t off[NCLS];
+    for (int c = 0; c < NCLS; ++c) { off[c] = all.size(); all.insert(all.end(), cls_items[c].begin(), cls_items[c].end()); }
     sht_plan_s::ItemSet set;
     size_t bytes = std::max<size_t>(1, all.size()) * sizeof(FftItem);
     HIPCHK(hipMalloc(&set.dev.p, bytes));
     set.dev.n = bytes;
     HIPCHK(hipMemcpy(set.dev.p, all.data(), all.size() * sizeof(FftItem), hipMemcpyHostToDevice));
     p->table_bytes += bytes;
-    const int elems[3] = {2, 8, 16};
-    for (int c = 0; c < 3; ++c)
-        set.classes.push_back(FftClass{(const FftItem*)set.dev.p + off[c], (int)cls_items[c].size(), lds[c], elems[c]});
+    // the residual kernel runs every class with the runtime-length code: the
+    // power-of-two classes hold at most 4096 values per workgroup (8 per thread)
+    for (int c = 0; c < NCLS; ++c) {
+        const int elems = c == 0 ? 2 : (c == 2 ? 16 : 8);
+        set.classes.push_back(FftClass{(const FftItem*)set.dev.p + off[c], (int)cls_items[c].size(), lds[c], elems,
+                                       c >= 3 ? c - 3 + 6 : 0});
+    }
     p->classes = set.classes;
     p->item_sets.emplace(npairs, std::move(set));
     p->items_npairs = npairs;

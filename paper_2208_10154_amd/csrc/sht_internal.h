@@ -43,6 +43,7 @@ struct FftLen {
     int ldsc;               // complex values per workgroup = nseq * (blue ? m : n)
     int lstride;            // LDS stride between sequences: >= len + len/16, = 16/nseq mod 16 (see k_fft.hip)
     int lds;                // complex LDS slots per workgroup = nseq * lstride
+    int p2;                 // log2(n) when n is a power of two handled by k_fft_p2.hip, else 0
 };
 
 struct RingDev {
@@ -160,7 +161,11 @@ struct FftClass {
     int nitems;
     int lds;     // complex LDS elements per workgroup
     int elems;   // 2, 8 or 16
+    int p2;      // 0: runtime-length kernels; else log2 of the ring length (k_fft_p2.hip)
 };
+// power-of-two ring lengths 2^6 .. 2^12: map pairs per workgroup (0: not handled)
+int p2_seqs_per_group(int logn);
+hipError_t launch_fft_p2(bool forward, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st);
 hipError_t launch_fft_forward(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
 hipError_t launch_fft_inverse(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
 hipError_t launch_residual(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
