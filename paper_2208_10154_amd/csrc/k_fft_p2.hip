@@ -421,18 +421,302 @@ __global__ __launch_bounds__(P2<LOGN>::NTH, 4) void k_fft_inv_p2(FftArgs a, cons
     inv_item<LOGN, XT>(a, work_item(items, nitems, a.comp0), lds);
 }
 
+// ----------------------------------------------------------------------------
+// Rings whose length n has a prime factor above 7 (most polar-cap rings):
+// Bluestein's chirp-z form, y_j = w_j sum_i (x_i w_i) conj(w_{j-i}) with
+// w_i = e^{-i pi i^2/n}, the circular convolution taken through a power-of-two
+// length M >= 2n - 1 with the compile-time passes above.  The kernel spectrum
+// bhat (FFT of conj(w) placed circularly, times 1/M) is precomputed per length.
+// The last pass of a length-M transform leaves element tl + T k in register
+// slot b R + r with k = b + r B, exactly the pass-0 inputs of the next
+// transform: the two transforms are chained in registers.
+// ----------------------------------------------------------------------------
+
+// m = m0, m0 + dm, ...: keeps j = m mod n and ph = (m s) mod 2n
+struct MStep {
+    int j, ph, dj, dph, n, two_n;
+    __device__ __forceinline__ MStep(int m0, int dm, int n_, int s)
+    {
+        n = n_;
+        two_n = 2 * n_;
+        j = m0 % n;
+        ph = (int)(((int64_t)m0 * s) % two_n);
+        dj = dm % n;
+        dph = (int)(((int64_t)dm * s) % two_n);
+    }
+    __device__ __forceinline__ void next()
+    {
+        j += dj;
+        if (j >= n) j -= n;
+        ph += dph;
+        if (ph >= two_n) ph -= two_n;
+    }
+};
+
+// the registers after a transform, reordered to the pass-0 layout
+template <int LOGM>
+__device__ __forceinline__ void to_pass0(const double2 (&v)[8], double2 (&u)[8])
+{
+    using QL = Pass<LOGM, P2<LOGM>::NP - 1>;
+#pragma unroll
+    for (int b = 0; b < QL::B; ++b) {
+#pragma unroll
+        for (int r = 0; r < QL::R; ++r) u[b + r * QL::B] = v[b * QL::R + r];
+    }
+}
+
+// Convolution step of Bluestein on the pass-0 values u (x_i w_i at i = tl + k T,
+// zero for i >= n): on return y_j = w_j u[k] for j = tl + k T < n.
+template <int LOGM>
+__device__ __forceinline__ void blue_core(double2 (&u)[8], double2* sb, int tl, const double2* twM, const double2* bhat)
+{
+    constexpr int T = P2<LOGM>::T;
+    double2 v[8], w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = u[k];
+    run_passes<LOGM, 0>(v, w, sb, tl, twM);
+    to_pass0<LOGM>(v, u);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double2 z = cmul(u[k], bhat[tl + k * T]);
+        u[k] = make_double2(z.x, -z.y);
+    }
+    __syncthreads();  // the first transform's last readers of sb are done
+    run_passes<LOGM, 0>(u, w, sb, tl, twM);
+    to_pass0<LOGM>(u, v);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[k] = make_double2(v[k].x, -v[k].y);
+}
+
+template <int LOGM, typename XT>
+__device__ __forceinline__ void fwd_item_blue(const FftArgs& a, const Item it, double2* lds)
+{
+    using C = P2<LOGM>;
+    constexpr int T = C::T, S = C::S;
+    const RingDev rg = a.rings[it.ring];
+    const FftLen* L = a.lens + rg.len;
+    const int n = rg.n;
+    const double2* twn = a.tw + L->tw;      // e^{-i pi t/n}, t < 2n
+    const double2* twM = a.tw + L->twm;     // e^{-i pi t/M}, t < 2M
+    const double2* chirp = a.tw + L->chirp;
+    const double2* bhat = a.bhat + L->bhat;
+    const int seq = (int)threadIdx.x / T, tl = (int)threadIdx.x % T;
+    double2* sb = lds + seq * C::SEQ;
+    const int k = 2 * (it.pair0 + seq);
+
+    double2 u[8];
+    {
+        const int64_t ms = (int64_t)a.ncomp * a.npix;
+        const double* pa = a.maps_in + (int64_t)it.comp * a.npix + rg.first + min(k, a.nmaps - 1) * ms;
+        const double* pb = a.maps_in + (int64_t)it.comp * a.npix + rg.first + min(k + 1, a.nmaps - 1) * ms;
+        double2 c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = min(tl + q * T, n - 1);
+            u[q] = make_double2(pa[i], pb[i]);
+            c[q] = chirp[i];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const bool live = tl + q * T < n;
+            const double2 x = make_double2(k < a.nmaps ? u[q].x : 0.0, k + 1 < a.nmaps ? u[q].y : 0.0);
+            u[q] = live ? cmul(x, c[q]) : make_double2(0.0, 0.0);
+        }
+    }
+    blue_core<LOGM>(u, sb, tl, twM, bhat);
+
+    // spectrum y_j = w_j u[k] (j = tl + k T < n) into LDS in natural order
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int j = tl + q * T;
+        if (j < n) sb[j] = cmul(chirp[j], u[q]);
+    }
+    __syncthreads();
+
+    if (a.F) {  // data spectra of both maps (iterative map2alm), halfcomplex
+        for (int pos = tl; pos < n; pos += T) {
+            const int j = (pos == 0) ? 0 : (pos == n - 1 ? n / 2 : (pos + 1) / 2);
+            const int jn = j ? n - j : 0;
+            const double2 z = sb[j], y = sb[jn];
+            const double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
+            const double2 Fb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
+            const bool im = (pos != 0) && (pos != n - 1) && ((pos & 1) == 0);
+            if (k < a.nmaps) a.F[((int64_t)k * a.ncomp + it.comp) * a.npix + rg.first + pos] = im ? Fa.y : Fa.x;
+            if (k + 1 < a.nmaps)
+                a.F[((int64_t)(k + 1) * a.ncomp + it.comp) * a.npix + rg.first + pos] = im ? Fb.y : Fb.x;
+        }
+    }
+
+    // unfold T_m = e^{-i m phi0} F_{m mod n}, lanes over (m, pair, part)
+    constexpr int LP = sizeof(XT) == 8 ? 1 : 0;
+    constexpr int MSTEP = C::NTH >> (LP + C::LOGS);
+    const int part = (int)threadIdx.x & ((1 << LP) - 1);
+    const int sq = ((int)threadIdx.x >> LP) & (S - 1);
+    const int mi = (int)threadIdx.x >> (LP + C::LOGS);
+    const double2* zs = lds + sq * C::SEQ;
+    XT* X = static_cast<XT*>(a.X) + (int64_t)it.comp * a.xcomp + (int64_t)it.ring * a.ldx + 4 * (it.pair0 + sq) + 2 * part;
+    const int64_t mrow = (int64_t)a.nring * a.ldx;
+    MStep ws(mi, MSTEP, n, rg.s);
+    for (int m0 = mi; m0 <= a.lmax; m0 += MB * MSTEP) {
+        double2 ph[MB];
+        int jj[MB];
+#pragma unroll
+        for (int q = 0; q < MB; ++q) {
+            ph[q] = twn[ws.ph];
+            jj[q] = ws.j;
+            ws.next();
+        }
+#pragma unroll
+        for (int q = 0; q < MB; ++q) {
+            const int m = m0 + q * MSTEP;
+            if (m <= a.lmax) {
+                const int j = jj[q], jn = j ? n - j : 0;
+                const double2 z = zs[j], y = zs[jn];
+                const double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
+                const double2 Fb = make_double2(0.5 * (z.y + y.y), 0.5 * (y.x - z.x));
+                if constexpr (sizeof(XT) == 8) {
+                    *reinterpret_cast<double2*>(X + m * mrow) = cmul(ph[q], part ? Fb : Fa);
+                } else {
+                    store4<XT>(X + m * mrow, cmul(ph[q], Fa), cmul(ph[q], Fb));
+                }
+            }
+        }
+    }
+}
+
+template <int LOGM, typename XT>
+__device__ __forceinline__ void inv_item_blue(const FftArgs& a, const Item it, double2* lds)
+{
+    using C = P2<LOGM>;
+    constexpr int T = C::T, S = C::S;
+    const RingDev rg = a.rings[it.ring];
+    const FftLen* L = a.lens + rg.len;
+    const int n = rg.n, lmax = a.lmax;
+    const double2* twn = a.tw + L->tw;
+    const double2* twM = a.tw + L->twm;
+    const double2* chirp = a.tw + L->chirp;
+    const double2* bhat = a.bhat + L->bhat;
+
+    // fold into conj(Z_j), j < n, in LDS (every m <= lmax lands on bin m mod n
+    // and its mirror; several terms per bin, so added atomically); lanes over
+    // (m, pair, part), the map-b lane handing its term to the map-a lane
+    {
+        for (int e = (int)threadIdx.x; e < S * C::SEQ; e += C::NTH) lds[e] = make_double2(0.0, 0.0);
+        __syncthreads();
+        const int part = (int)threadIdx.x & 1;
+        const int sq = ((int)threadIdx.x >> 1) & (S - 1);
+        const int mi = (int)threadIdx.x >> (1 + C::LOGS);
+        constexpr int MSTEP = C::NTH >> (1 + C::LOGS);
+        double2* zs = lds + sq * C::SEQ;
+        const XT* X = static_cast<const XT*>(a.X) + (int64_t)it.comp * a.xcomp + (int64_t)it.ring * a.ldx +
+                      4 * (it.pair0 + sq) + 2 * part;
+        const int64_t mrow = (int64_t)a.nring * a.ldx;
+        MStep ws(mi, MSTEP, n, rg.s);
+        for (int m0 = mi; m0 <= lmax; m0 += MB * MSTEP) {
+            double2 tv[MB], p[MB];
+            int jj[MB];
+#pragma unroll
+            for (int q = 0; q < MB; ++q) {
+                const XT* xr = X + min(m0 + q * MSTEP, lmax) * mrow;
+                if constexpr (sizeof(XT) == 8) {
+                    tv[q] = *reinterpret_cast<const double2*>(xr);
+                } else {
+                    const float2 f = *reinterpret_cast<const float2*>(xr);
+                    tv[q] = make_double2(f.x, f.y);
+                }
+                p[q] = twn[ws.ph];
+                jj[q] = ws.j;
+                ws.next();
+            }
+#pragma unroll
+            for (int q = 0; q < MB; ++q) {
+                const int m = m0 + q * MSTEP;
+                const double2 c = cmul(make_double2(p[q].x, -p[q].y), tv[q]);  // c_m of this lane's map
+                const double cbx = __shfl_xor(c.x, 1), cby = __shfl_xor(c.y, 1);
+                if (part == 0 && m <= lmax) {
+                    const double2 ca = c, cb = make_double2(cbx, cby);
+                    double* z1 = reinterpret_cast<double*>(zs + jj[q]);
+                    atomicAdd(z1, ca.x - cb.y);
+                    atomicAdd(z1 + 1, -(ca.y + cb.x));
+                    if (m >= 1) {
+                        double* z2 = reinterpret_cast<double*>(zs + (jj[q] ? n - jj[q] : 0));
+                        atomicAdd(z2, ca.x + cb.y);
+                        atomicAdd(z2 + 1, -(cb.x - ca.y));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // Bluestein on conj(Z): pass-0 values conj(Z_i) w_i
+    const int seq = (int)threadIdx.x / T, tl = (int)threadIdx.x % T;
+    double2* sb = lds + seq * C::SEQ;
+    double2 u[8];
+    {
+        double2 c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = chirp[min(tl + q * T, n - 1)];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = tl + q * T;
+            u[q] = i < n ? cmul(sb[i], c[q]) : make_double2(0.0, 0.0);
+        }
+    }
+    __syncthreads();  // pass 0 overwrites the buffer
+    blue_core<LOGM>(u, sb, tl, twM, bhat);
+
+    // pixels: y_j = w_j u[k] = DFT(conj Z)_j; map k = Re(conj y), map k+1 = Im(conj y)
+    const int k = 2 * (it.pair0 + seq);
+    const int64_t ms = (int64_t)a.ncomp * a.npix;
+    double* oa = a.maps_out + (int64_t)it.comp * a.npix + rg.first + (int64_t)k * ms;
+    double2 c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c[q] = chirp[min(tl + q * T, n - 1)];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int j = tl + q * T;
+        const double2 y = cmul(c[q], u[q]);
+        if (j < n) {
+            if (k < a.nmaps) oa[j] = y.x;
+            if (k + 1 < a.nmaps) oa[ms + j] = -y.y;
+        }
+    }
+}
+
+template <int LOGM, typename XT>
+__global__ __launch_bounds__(P2<LOGM>::NTH, 4) void k_fft_fwd_blue(FftArgs a, const FftItem* items, int nitems)
+{
+    extern __shared__ double2 lds[];
+    fwd_item_blue<LOGM, XT>(a, work_item(items, nitems, a.comp0), lds);
+}
+
+template <int LOGM, typename XT>
+__global__ __launch_bounds__(P2<LOGM>::NTH, 4) void k_fft_inv_blue(FftArgs a, const FftItem* items, int nitems)
+{
+    extern __shared__ double2 lds[];
+    inv_item_blue<LOGM, XT>(a, work_item(items, nitems, a.comp0), lds);
+}
+
 template <int LOGN, typename XT>
 hipError_t launch_p2(bool fwd, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st)
 {
     using C = P2<LOGN>;
     const dim3 grid(c.nitems * ncompl);
     if (C::LDS_BYTES > 65536) {
-        const void* f = fwd ? (const void*)k_fft_fwd_p2<LOGN, XT> : (const void*)k_fft_inv_p2<LOGN, XT>;
+        const void* f = c.blue ? (fwd ? (const void*)k_fft_fwd_blue<LOGN, XT> : (const void*)k_fft_inv_blue<LOGN, XT>)
+                               : (fwd ? (const void*)k_fft_fwd_p2<LOGN, XT> : (const void*)k_fft_inv_p2<LOGN, XT>);
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
         if (e != hipSuccess) return e;
     }
-    if (fwd) hipLaunchKernelGGL((k_fft_fwd_p2<LOGN, XT>), grid, dim3(C::NTH), C::LDS_BYTES, st, a, c.items, c.nitems);
-    else hipLaunchKernelGGL((k_fft_inv_p2<LOGN, XT>), grid, dim3(C::NTH), C::LDS_BYTES, st, a, c.items, c.nitems);
+    if (c.blue) {
+        if (fwd) hipLaunchKernelGGL((k_fft_fwd_blue<LOGN, XT>), grid, dim3(C::NTH), C::LDS_BYTES, st, a, c.items, c.nitems);
+        else hipLaunchKernelGGL((k_fft_inv_blue<LOGN, XT>), grid, dim3(C::NTH), C::LDS_BYTES, st, a, c.items, c.nitems);
+    } else {
+        if (fwd) hipLaunchKernelGGL((k_fft_fwd_p2<LOGN, XT>), grid, dim3(C::NTH), C::LDS_BYTES, st, a, c.items, c.nitems);
+        else hipLaunchKernelGGL((k_fft_inv_p2<LOGN, XT>), grid, dim3(C::NTH), C::LDS_BYTES, st, a, c.items, c.nitems);
+    }
     return hipGetLastError();
 }
 

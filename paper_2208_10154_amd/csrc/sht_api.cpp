@@ -234,7 +234,16 @@ int build_fft(sht_plan p)
                 const ld ang = PI_L * (ld)q / (ld)r.n;
                 pool.push_back(make_double2((double)cosl(ang), (double)(-sinl(ang))));
             }
-            L.m = smooth_at_least(2 * r.n - 1);
+            // convolution length: a power of two up to 2^12 (compile-time
+            // kernels of k_fft_p2.hip), else the smallest 7-smooth length
+            int pm = 64, lg = 6;
+            while (pm < 2 * r.n - 1) { pm *= 2; ++lg; }
+            if (lg <= 12 && p2_seqs_per_group(lg) > 0) {
+                L.m = pm;
+                L.bp2 = lg;
+            } else {
+                L.m = smooth_at_least(2 * r.n - 1);
+            }
             factor_radices(L.m, rad);
             if (!tw_of.count(L.m)) { tw_of[L.m] = (int64_t)pool.size(); push_twiddles(pool, L.m); }
             L.twm = tw_of[L.m];
@@ -264,6 +273,16 @@ int build_fft(sht_plan p)
         // their own map pairs per workgroup (the runtime-length layout above is
         // kept for the residual kernel of the iteration)
         L.p2 = 0;
+        if (L.bp2) {
+            const int S = p2_seqs_per_group(L.bp2);
+            L.nseq = S;
+            L.lgseq = 0;
+            while ((1 << L.lgseq) < S) ++L.lgseq;
+            L.ldsc = S * L.m;
+            const int base = len + len / 16, want = (16 / L.nseq) % 16;
+            L.lstride = base + (((want - base) % 16) + 16) % 16;
+            L.lds = L.nseq * L.lstride;
+        }
         if (!L.blue && (r.n & (r.n - 1)) == 0) {
             int lg = 0;
             while ((1 << lg) < r.n) ++lg;
@@ -313,14 +332,16 @@ int build_items(sht_plan p, int npairs)
         p->items_npairs = npairs;
         return SHT_OK;
     }
-    // classes 0..2: runtime-length kernels by LDS size; 3 + (k - 6): length 2^k
-    constexpr int NCLS = 3 + 7;
+    // classes 0..2: runtime-length kernels by LDS size; 3 + (k - 6): length 2^k;
+    // 10 + (k - 6): Bluestein through length 2^k
+    constexpr int NCLS = 3 + 7 + 7;
     std::vector<FftItem> cls_items[NCLS];
     int lds[NCLS] = {};
     for (int r = 0; r < p->nring; ++r) {
         const FftLen& L = p->lens[p->rings[r].len];
         int c = (L.ldsc <= 2 * FFT_THREADS) ? 0 : (L.ldsc <= 8 * FFT_THREADS ? 1 : 2);
         if (L.p2) c = 3 + (L.p2 - 6);
+        if (L.bp2) c = 10 + (L.bp2 - 6);
         lds[c] = std::max(lds[c], L.lds);
         if (npairs % L.nseq) return fail(SHT_ERR_UNSUPPORTED, "map pairs per chunk not a multiple of the ring batch");
         for (int q = 0; q < npairs; q += L.nseq) cls_items[c].push_back(FftItem{r, q});
@@ -338,8 +359,9 @@ int build_items(sht_plan p, int npairs)
     // power-of-two classes hold at most 4096 values per workgroup (8 per thread)
     for (int c = 0; c < NCLS; ++c) {
         const int elems = c == 0 ? 2 : (c == 2 ? 16 : 8);
+        const int lg = c >= 10 ? c - 10 + 6 : (c >= 3 ? c - 3 + 6 : 0);
         set.classes.push_back(FftClass{(const FftItem*)set.dev.p + off[c], (int)cls_items[c].size(), lds[c], elems,
-                                       c >= 3 ? c - 3 + 6 : 0});
+                                       lg, c >= 10 ? 1 : 0});
     }
     p->classes = set.classes;
     p->item_sets.emplace(npairs, std::move(set));

@@ -44,6 +44,7 @@ struct FftLen {
     int lstride;            // LDS stride between sequences: >= len + len/16, = 16/nseq mod 16 (see k_fft.hip)
     int lds;                // complex LDS slots per workgroup = nseq * lstride
     int p2;                 // log2(n) when n is a power of two handled by k_fft_p2.hip, else 0
+    int bp2;                // log2(m) when a Bluestein length m = 2^bp2 is handled by k_fft_p2.hip, else 0
 };
 
 struct RingDev {
@@ -161,7 +162,8 @@ struct FftClass {
     int nitems;
     int lds;     // complex LDS elements per workgroup
     int elems;   // 2, 8 or 16
-    int p2;      // 0: runtime-length kernels; else log2 of the ring length (k_fft_p2.hip)
+    int p2;      // 0: runtime-length kernels; else log2 of the (convolution) length (k_fft_p2.hip)
+    int blue;    // with p2: Bluestein rings through a power-of-two convolution
 };
 // power-of-two ring lengths 2^6 .. 2^12: map pairs per workgroup (0: not handled)
 int p2_seqs_per_group(int logn);
