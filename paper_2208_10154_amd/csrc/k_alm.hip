@@ -77,7 +77,9 @@ __global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
     T* A = static_cast<T*>(a.A) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
     for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
         const int li = e / (2 * TK), c = e % (2 * TK);
-        if (l0 + li <= L) A[(int64_t)li * a.ldx + c] = (T)tile[li][c];
+        if (l0 + li > L) continue;
+        if constexpr (__is_same(T, uint32_t)) A[(int64_t)li * a.ldx + c] = pack_bf16_pair((float)tile[li][c]);
+        else A[(int64_t)li * a.ldx + c] = (T)tile[li][c];
     }
 }
 
@@ -142,6 +144,7 @@ hipError_t launch_alm_to_mmajor(const AlmArgs& a, int ncompl, int prec, hipStrea
 {
     dim3 grid(a.ntiles * a.kblocks, ncompl);
     if (prec == 0) hipLaunchKernelGGL(k_to_mmajor<double>, grid, dim3(NT), 0, st, a);
+    else if (prec == 2) hipLaunchKernelGGL(k_to_mmajor<uint32_t>, grid, dim3(NT), 0, st, a);  // split-BF16 words
     else hipLaunchKernelGGL(k_to_mmajor<float>, grid, dim3(NT), 0, st, a);
     return hipGetLastError();
 }

@@ -9,6 +9,12 @@
 // same as in the FP32 path (recursion FP64, workspace FP32), so only the MFMA
 // step changes precision.
 //
+// alm2map reads its coefficient rows already split, as 32-bit words holding hi
+// and lo (written so by the layout kernel), and only regroups them; map2alm
+// splits the ring coefficients itself after folding the hemispheres (north +
+// south and north - south in FP32), since splitting north and south apart
+// would double its matrix products.
+//
 // One v_mfma_f32_16x16x32_bf16 covers the whole K extent of a tile (32 rings,
 // or the 32 rows of one parity class of a 64-row l tile), so a tile is one burst
 // of MFMAs per (class, row tile, column tile).  The bursts are spread over eight
@@ -52,6 +58,22 @@ __device__ __forceinline__ void split8(const float (&x)[8], v8bf& hi, v8bf& lo)
 }
 
 __device__ __forceinline__ v8bf lds8(const __bf16* p) { return *reinterpret_cast<const v8bf*>(p); }
+
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+// hi and lo operand vectors of eight split-BF16 words (hi in the low half of
+// each word): two halves regrouped per output word
+__device__ __forceinline__ void unpack8(const uint32_t (&d)[8], v8bf& hi, v8bf& lo)
+{
+    v4u h, l;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        h[j] = __builtin_amdgcn_perm(d[2 * j + 1], d[2 * j], 0x05040100u);
+        l[j] = __builtin_amdgcn_perm(d[2 * j + 1], d[2 * j], 0x07060302u);
+    }
+    hi = __builtin_bit_cast(v8bf, h);
+    lo = __builtin_bit_cast(v8bf, l);
+}
 
 // Emitter for the split tiles: hi at d, lo LOFF further on, F- FOFF after F+.
 template <int STEP, int FOFF, int LOFF>
@@ -413,7 +435,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
 
     if (nch > 0) {
         const int64_t row0 = a.rowoff[m];
-        const float* Am = static_cast<const float*>(a.A) + row0 * a.ldx + col;
+        const uint32_t* Am = static_cast<const uint32_t*>(a.A) + row0 * a.ldx + col;
         const int64_t sb = a.seedoff[m] + frc;
         const int j0 = (lfirst - lb) / SEG + fs0;
         const int jmax = (L - lb) / SEG;
@@ -427,13 +449,13 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
             e.e1 = e.e0 + CLS;
             return e;
         };
-        float ar[2][NU][8];  // [even, odd class][column tile][class row k0 + e] of the next chunk
+        uint32_t ar[2][NU][8];  // [even, odd class][column tile][class row k0 + e] of the next chunk
         auto load_a = [&](int c) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int le = lfirst + TL * c + 2 * (k0 + e);
-                const float* pe = Am + (int64_t)(min(le, L) - lb) * a.ldx;
-                const float* pq = Am + (int64_t)(min(le + 1, L) - lb) * a.ldx;
+                const uint32_t* pe = Am + (int64_t)(min(le, L) - lb) * a.ldx;
+                const uint32_t* pq = Am + (int64_t)(min(le + 1, L) - lb) * a.ldx;
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
                     ar[0][u][e] = pe[16 * u];
@@ -473,7 +495,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int u = 0; u < NU; ++u) split8(ar[p][u], bh[p][u], bl[p][u]);
+                for (int u = 0; u < NU; ++u) unpack8(ar[p][u], bh[p][u], bl[p][u]);
             load_a(cn);
 #pragma unroll
             for (int i = 0; i < 2; ++i) seed_of(sd[i], min(c + 2, nch - 1), i);
@@ -562,8 +584,8 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
 
     if (nch > 0) {
         const int64_t row0 = a.rowoff[m];
-        const float* AE = static_cast<const float*>(a.A) + a.acomp + row0 * a.ldx + col;
-        const float* AB = static_cast<const float*>(a.A) + 2 * a.acomp + row0 * a.ldx + col;
+        const uint32_t* AE = static_cast<const uint32_t*>(a.A) + a.acomp + row0 * a.ldx + col;
+        const uint32_t* AB = static_cast<const uint32_t*>(a.A) + 2 * a.acomp + row0 * a.ldx + col;
         const int64_t sb = a.seedoff[m] + frc;
         const int j0 = (lfirst - lb) / SEG + fs;
         const int jmax = (L - lb) / SEG;
@@ -575,7 +597,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
             e.e1 = fpm + b * BUF + (po ^ 1) * CLS + frl * KP + (SEG / 2) * fs;
             return e;
         };
-        float ar[4][NU][8];  // [E even, E odd, B' even, B' odd][column tile][class row k0 + e]
+        uint32_t ar[4][NU][8];  // [E even, E odd, B' even, B' odd][column tile][class row k0 + e]
         auto load_a_tile = [&](int c, int u) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -614,7 +636,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
             const int cnt = min(SEG, L - ls_of(cn) + 1);
             if (filler) f.start(sd, w);
             // Phases run column tile by column tile (u = P / (NPH / NU)): a tile's
-            // operands are split when its first phase starts and its loads for the
+            // operands are regrouped when its first phase starts and its loads for the
             // next chunk issued right after, so only one tile's split operands and
             // one tile's raw prefetch are live besides the accumulators.
             static_assert(NPH % NU == 0 && NPH / NU >= 4, "four MFMA phases per column tile");
@@ -627,7 +649,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
                 constexpr int u = P / PPU, pu = P % PPU;
                 if constexpr (pu == 0) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) split8(ar[i][u], bh[i], bl[i]);
+                    for (int i = 0; i < 4; ++i) unpack8(ar[i][u], bh[i], bl[i]);
                     load_a_tile(cn, u);
                     if constexpr (u == 0) seed_of(sd, min(c + 2, nch - 1));
                     __builtin_amdgcn_sched_barrier(0);

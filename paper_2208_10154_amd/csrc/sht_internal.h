@@ -25,6 +25,20 @@ constexpr int SPT = TL / SEG;  // segments per tile
 constexpr int RCHUNK = 32;   // ring granularity of the skip table
 
 // ----------------------------------------------------------------------------
+// Split-BF16 operands: x (rounded to FP32) = hi + lo with hi = bf16(x) and
+// lo = bf16(x - hi), stored as one 32-bit word, hi in the low half.  The layout
+// kernel writes the coefficient rows of the BF16x3 alm2map contraction in this
+// form, so that kernel only regroups halves instead of splitting every operand
+// in every tile.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t pack_bf16_pair(float x)
+{
+    const __bf16 h = (__bf16)x;
+    const __bf16 l = (__bf16)(x - (float)h);
+    return (uint32_t)__builtin_bit_cast(unsigned short, h) | ((uint32_t)__builtin_bit_cast(unsigned short, l) << 16);
+}
+
+// ----------------------------------------------------------------------------
 // FFT tables
 // ----------------------------------------------------------------------------
 constexpr int MAX_STAGES = 16;

@@ -159,5 +159,8 @@ def test_nside1024_iteration_converges_and_mixed_agrees(big):
     mixed = from_dev(out)[0]
     p.close()
     assert errs[0] > errs[1] > errs[2] and errs[2] < 0.05 * errs[0], errs
-    assert all(np.diff(res) < 0), res
+    # with the mixed-precision operator the residual falls to a floor set by the
+    # operator's own error (a few 1e-6 here) and then stays there to rounding
+    assert res[1] < 0.5 * res[0] and res[2] < res[1] * 1.01, res
+    assert res[-1] <= 1.01 * min(res) and res[-1] < 1e-5, res
     assert rel(mixed, fp64) <= 1e-5
