@@ -278,7 +278,7 @@ def serving(args):
         ev.record()
         return inp, out, ev
 
-    def server(depth=2, nstreams=2):
+    def server(depth=2, nstreams=4):
         return serve.Server(args.serve_budget_gb * 1e9, max_slots=512, depth=depth,
                             executor=serve.Executor(nstreams=nstreams, graphs=args.serve_graphs))
 

@@ -16,8 +16,12 @@ precision arriving at any time.  This module groups them back into batches:
   used) before creating new ones.  A request whose slot copy would not fit runs
   alone in place on the caller's tensors, and the plan chunks it internally; a
   request whose plan alone exceeds the budget is rejected with SHT_ERR_NOMEM.
-* Every plan has its own stream (default priority), so batches of different
-  plans overlap on the GPU while a plan's own batches stay ordered.
+* Batches of different plans overlap on several streams (default priority).  A
+  plan's batches share its workspace, so while any is in flight the next one
+  follows on the same stream; an idle plan takes the stream with the least work
+  outstanding (estimated from the batch sizes), so small requests are not
+  queued behind large batches of other plans.  Finished batches retire in any
+  order.
 * Optional graph replay: a batch bucket's launch sequence on the slot buffers is
   captured once as a HIP graph and replayed for later batches of that bucket.
 
@@ -108,6 +112,12 @@ def mapset_bytes(nside: int, lmax: int, spin: int) -> int:
 SEG, TL = 8, 64  # Legendre seed segment and tile (rows of l), as in the library
 
 
+def batch_cost(req: Request, n: int) -> float:
+    """Relative GPU work of a batch of n map sets of req's key: the contraction
+    dominates, columns x (lmax + 1)^2 x northern rings (the FFTs scale alike)."""
+    return float(bucket(n) * req.ncomp * (req.lmax + 1) ** 2 * req.nside)
+
+
 def plan_bytes_estimate(nside: int, lmax: int, spin: int, slots: int) -> int:
     """Upper estimate of a plan's device bytes before it exists: the FP64
     workspace for a chunk of `slots` map sets (m-major ring coefficients for every
@@ -135,7 +145,7 @@ def plan_bytes_estimate(nside: int, lmax: int, spin: int, slots: int) -> int:
 class Executor:
     """Runs batches on the GPU through the C-ABI plans (the product path)."""
 
-    def __init__(self, nstreams: int = 2, graphs: bool = False):
+    def __init__(self, nstreams: int = 4, graphs: bool = False):
         import torch
         self.torch = torch
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
@@ -275,7 +285,8 @@ class Server:
         self.tickets = {}
         self._next_ticket = 0
         self._next_batch = 0
-        self._next_stream = 0
+        self.nstreams = max(1, len(getattr(self.ex, "streams", [0])))
+        self.stream_load = [0.0] * self.nstreams  # estimated work in flight per stream
         self.batches = []  # (batch id, key, maps, requests)
         self.t0 = self.ex.start_clock()
         self.ex.set_origin(self.t0)
@@ -329,14 +340,21 @@ class Server:
         return changed
 
     def _retire(self) -> bool:
-        changed = False
-        while self.inflight and self.ex.ready(self.inflight[0][0]):
-            ev, pk, reqs = self.inflight.popleft()
+        """Retire every finished batch, in whatever order they finished."""
+        changed, waiting = False, collections.deque()
+        while self.inflight:
+            item = self.inflight.popleft()
+            ev, pk, reqs, sid, cost = item
+            if not self.ex.ready(ev):
+                waiting.append(item)
+                continue
             t = self.ex.event_time(ev)
             for r in reqs:
                 r.done = t
             self.plans[pk].inflight -= 1
+            self.stream_load[sid] -= cost
             changed = True
+        self.inflight = waiting
         return changed
 
     def _slots_for(self, nside, lmax, spin) -> int:
@@ -362,8 +380,7 @@ class Server:
             self._evict(min(idle)[1])
         plan = self.ex.new_plan(req.nside, req.lmax, req.spin, slots)
         nbytes = max(est, self.ex.plan_bytes(plan, slots, "fp64"))
-        p = _Plan(plan, self._next_stream % len(getattr(self.ex, "streams", [0])), slots, nbytes)
-        self._next_stream += 1
+        p = _Plan(plan, 0, slots, nbytes)
         self.plans[pk] = p
         self.used += nbytes
         self.peak = max(self.peak, self.used)
@@ -438,10 +455,14 @@ class Server:
         self._next_batch += 1
         for r in reqs:
             r.batch = bid
+        if p.inflight == 0:  # free to move: the least-loaded stream
+            p.stream = min(range(self.nstreams), key=lambda i: self.stream_load[i])
+        cost = batch_cost(head, n)
         ev = self.ex.run(p.plan, p.stream, head.direction, head.precision, reqs, n, slot_in, slot_out)
         p.inflight += 1
         p.last_use = self.now()
-        self.inflight.append((ev, head.plan_key, reqs))
+        self.stream_load[p.stream] += cost
+        self.inflight.append((ev, head.plan_key, reqs, p.stream, cost))
         self.batches.append((bid, key, n, len(reqs)))
         return True
 

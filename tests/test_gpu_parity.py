@@ -61,6 +61,7 @@ CASES = [
     (13, 38, 5, 2),           # odd nside (Bluestein equator), ragged maps, 3 chunks
     (8, 31, 3, None),         # lmax = 4 nside - 1 (maximum)
     (32, 40, 2, None),        # lmax < 2 nside
+    (24, 71, 3, None),        # power-of-two and Bluestein polar rings with lmax >= n (aliased rows)
 ]
 
 
@@ -94,6 +95,7 @@ POL_CASES = [
     (11, 32, 4, 3),
     (16, 47, 2, None),
     (4, 15, 1, None),
+    (24, 71, 2, None),  # aliased rows in the power-of-two and Bluestein ring kernels
 ]
 
 

@@ -220,3 +220,47 @@ def test_request_validation():
         serve.Request(nside=16, spin=0, direction="sideways", precision="fp64", nmaps=1)
     with pytest.raises(ValueError):
         serve.Request(nside=16, spin=0, direction="alm2map", precision="fp64", nmaps=0)
+
+
+class StreamExecutor(RecordingExecutor):
+    """Each stream runs its batches one after another; streams run side by side.
+    A batch takes `cost[nside]` seconds."""
+
+    def __init__(self, cost, nstreams=2):
+        super().__init__()
+        self.streams = list(range(nstreams))
+        self.cost = cost
+        self.until = [0.0] * nstreams
+
+    def run(self, plan, stream, direction, precision, reqs, n, slot_in, slot_out):
+        self.runs.append(dict(plan=plan.key, stream=stream, rids=[r.ticket for r in reqs], n=n))
+        start = max(time.perf_counter() - self.t0, self.until[stream])
+        self.until[stream] = start + self.cost[plan.key[0]]
+        return _Ev(self.until[stream])
+
+
+def test_small_batches_retire_behind_a_large_one():
+    # a long nside-64 batch is launched first; nside-16 batches on the other stream
+    # finish and retire while it runs, so their plan keeps launching (depth 1)
+    ex = StreamExecutor({64: 0.3, 16: 0.01})
+    s = serve.Server(1e12, max_slots=64, executor=ex, depth=1)
+    big = s.submit(req(nside=64, arrival=0.0))
+    small = [s.submit(req(nside=16, arrival=0.001 + 0.02 * i)) for i in range(5)]
+    s.drain()
+    assert [r["stream"] for r in ex.runs if r["plan"][0] == 16] == [1] * 5
+    for t in small:
+        assert s.tickets[t].latency < 0.05, s.tickets[t].latency
+    assert s.tickets[big].latency >= 0.3
+
+
+def test_idle_plan_takes_the_least_loaded_stream():
+    ex = StreamExecutor({64: 0.2, 32: 0.05, 16: 0.01}, nstreams=2)
+    s = serve.Server(1e12, max_slots=64, executor=ex, depth=2)
+    s.submit(req(nside=64, nmaps=64, arrival=0.0))   # heavy: stream 0
+    s.submit(req(nside=32, nmaps=1, arrival=0.0))    # stream 1
+    s.submit(req(nside=16, nmaps=1, arrival=0.0))    # lighter load is stream 1
+    s.drain()
+    st = {r["plan"][0]: r["stream"] for r in ex.runs}
+    assert st[64] != st[32] and st[16] == st[32]
+    assert all(v == 0.0 for v in s.stream_load)
+
