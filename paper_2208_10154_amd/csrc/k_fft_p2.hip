@@ -80,11 +80,12 @@ struct P2 {
     static constexpr int E = 8;                      // values per thread
     static constexpr int T = N / E;                  // threads per sequence
     // sequences (map pairs) per workgroup: 4096 values (two rings of 2048) per
-    // workgroup, at most 32 pairs.  Two or more pairs give every coefficient
-    // row access 64 contiguous bytes or more (a single pair's 32 bytes per row
-    // leave every access its own partial line and page translation).
-    static constexpr int S = (4096 / N) < 1 ? 1 : ((4096 / N) > 32 ? 32 : 4096 / N);
-    static constexpr int LOGS = S == 1 ? 0 : (S == 2 ? 1 : (S == 4 ? 2 : (S == 8 ? 3 : (S == 16 ? 4 : 5))));
+    // workgroup, at most 16 pairs (the map pairs of the narrowest chunk, 32 map
+    // sets).  Two or more pairs give every coefficient row access 64 contiguous
+    // bytes or more (a single pair's 32 bytes per row leave every access its own
+    // partial line and page translation).
+    static constexpr int S = (4096 / N) < 1 ? 1 : ((4096 / N) > 16 ? 16 : 4096 / N);
+    static constexpr int LOGS = S == 1 ? 0 : (S == 2 ? 1 : (S == 4 ? 2 : (S == 8 ? 3 : 4)));
     static constexpr int NTH = S * T;                // threads per workgroup
     static constexpr int NP = (LOGN + 2) / 3;        // passes
     static constexpr int LOGRL = LOGN - 3 * (NP - 1);  // log2 of the last radix (1..3)

@@ -652,12 +652,13 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
 int pick_nu(int numax, int64_t ldx)
 {
     int nu = numax;
-    while (nu > 2 && ldx % (64 * nu) != 0) nu >>= 1;
+    while (nu > 1 && ldx % (64 * nu) != 0) nu >>= 1;
     return nu;
 }
 
 // Column tiling per kernel: the widest NU whose registers fit two waves per SIMD
-// without spilling (spin 0, map2alm FP64: 4; spin-0 FP32: 4; the rest: 2).
+// without spilling (spin 0, map2alm FP64: 4; spin-0 FP32: 4; the rest: 2), and
+// NU = 1 for batches of at most 32 map sets (64 columns).
 template <typename T>
 hipError_t launch_m2a_t(const LegArgs& a, hipStream_t st)
 {
@@ -668,10 +669,13 @@ hipError_t launch_m2a_t(const LegArgs& a, hipStream_t st)
         b.ctiles = (int)(a.ldx / (64 * nu));
         const dim3 grid(b.ntiles * b.ctiles);
         if (nu == 4) hipLaunchKernelGGL((k_m2a_spin0<T, 4>), grid, blk, 0, st, b);
-        else hipLaunchKernelGGL((k_m2a_spin0<T, 2>), grid, blk, 0, st, b);
+        else if (nu == 2) hipLaunchKernelGGL((k_m2a_spin0<T, 2>), grid, blk, 0, st, b);
+        else hipLaunchKernelGGL((k_m2a_spin0<T, 1>), grid, blk, 0, st, b);
     } else {
-        b.ctiles = (int)(a.ldx / 128);
-        hipLaunchKernelGGL((k_m2a_spin2<T, 2>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
+        const int nu = pick_nu(2, a.ldx);
+        b.ctiles = (int)(a.ldx / (64 * nu));
+        if (nu == 2) hipLaunchKernelGGL((k_m2a_spin2<T, 2>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
+        else hipLaunchKernelGGL((k_m2a_spin2<T, 1>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
     }
     return hipGetLastError();
 }
@@ -692,11 +696,14 @@ hipError_t launch_a2m_t(const LegArgs& a, hipStream_t st)
                 return hipGetLastError();
             }
         }
-        hipLaunchKernelGGL((k_a2m_spin0<T, 2>), grid, blk, 0, st, b);
+        if (nu == 1) hipLaunchKernelGGL((k_a2m_spin0<T, 1>), grid, blk, 0, st, b);
+        else hipLaunchKernelGGL((k_a2m_spin0<T, 2>), grid, blk, 0, st, b);
     } else {
-        b.ctiles = (int)(a.ldx / 128);
+        const int nu = pick_nu(2, a.ldx);
+        b.ctiles = (int)(a.ldx / (64 * nu));
         const dim3 grid((a.lmax + 1) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR));
-        hipLaunchKernelGGL((k_a2m_spin2<T, 2>), grid, blk, 0, st, b);
+        if (nu == 2) hipLaunchKernelGGL((k_a2m_spin2<T, 2>), grid, blk, 0, st, b);
+        else hipLaunchKernelGGL((k_a2m_spin2<T, 1>), grid, blk, 0, st, b);
     }
     return hipGetLastError();
 }

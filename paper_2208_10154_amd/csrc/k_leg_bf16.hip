@@ -715,8 +715,13 @@ hipError_t launch_leg_m2a_bf16(const LegArgs& a, hipStream_t st)
     LegArgs b = a;
     const dim3 blk(NT);
     if (a.spin == 0) {
-        b.ctiles = (int)(a.ldx / 128);
-        hipLaunchKernelGGL((k_m2a_spin0_bf<2>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
+        if (a.ldx % 128 == 0) {
+            b.ctiles = (int)(a.ldx / 128);
+            hipLaunchKernelGGL((k_m2a_spin0_bf<2>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
+        } else {
+            b.ctiles = (int)(a.ldx / 64);
+            hipLaunchKernelGGL((k_m2a_spin0_bf<1>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
+        }
     } else {
         b.ctiles = (int)(a.ldx / 64);
         hipLaunchKernelGGL((k_m2a_spin2_bf<1>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
@@ -729,9 +734,11 @@ hipError_t launch_leg_a2m_bf16(const LegArgs& a, hipStream_t st)
     LegArgs b = a;
     const dim3 blk(NT);
     if (a.spin == 0) {
-        b.ctiles = (int)(a.ldx / 128);
+        const int nu = a.ldx % 128 == 0 ? 2 : 1;
+        b.ctiles = (int)(a.ldx / (64 * nu));
         const dim3 grid((a.lmax + 1) * b.ctiles * ((a.rn + A0_TR - 1) / A0_TR));
-        hipLaunchKernelGGL((k_a2m_spin0_bf<2>), grid, blk, 0, st, b);
+        if (nu == 2) hipLaunchKernelGGL((k_a2m_spin0_bf<2>), grid, blk, 0, st, b);
+        else hipLaunchKernelGGL((k_a2m_spin0_bf<1>), grid, blk, 0, st, b);
     } else {
         b.ctiles = (int)(a.ldx / 64);
         const dim3 grid((a.lmax + 1) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR));

@@ -506,8 +506,9 @@ int build_seeds(sht_plan p, SeedSet& S, int spin)
 // --------------------------------------------------------------------------
 size_t esize(int prec) { return prec == SHT_FP64 ? sizeof(double) : sizeof(float); }
 
-// columns of the m-major operand arrays: 2 * map sets padded to a multiple of 64
-int64_t ldx_for(int chunk) { return 2 * (int64_t)((chunk + 63) / 64 * 64); }
+// columns of the m-major operand arrays: 2 * map sets, padded to 32 map sets for
+// batches of up to 32 (one 64-column tile) and to a multiple of 64 beyond
+int64_t ldx_for(int chunk) { return chunk <= 32 ? 64 : 2 * (int64_t)((chunk + 63) / 64 * 64); }
 
 int64_t xcomp_elems(sht_plan p) { return (int64_t)(p->lmax + 1) * p->nring * ldx_for(p->chunk); }
 

@@ -9,8 +9,9 @@ precision arriving at any time.  This module groups them back into batches:
 * Requests with the same plan key (nside, lmax, spin, precision, direction) that
   are waiting when their plan's stream can take work are packed, oldest first,
   into the slots of one batched call (map sets concatenated along the batch
-  axis); the call's chunk is the batch size rounded up to the 64-map granularity
-  of the kernels, so a small batch pays for what it holds, not for the slots.
+  axis); the call's chunk is the batch size rounded up to the column granularity
+  of the kernels (32 map sets for small batches, then multiples of 64), so a
+  small batch pays for what it holds, not for the slots.
 * HBM admission: the server owns plan tables, plan workspaces and slot buffers
   and keeps their sum under a byte budget, evicting idle plans (least recently
   used) before creating new ones.  A request whose slot copy would not fit runs
@@ -38,7 +39,8 @@ import time
 from . import sht
 
 SHT_ERR_NOMEM = -2
-GRANULE = 64  # map sets per kernel column tile
+GRANULE = 64  # map sets per column granule of the kernels beyond one small tile
+SMALL = 32    # batches of up to this many map sets use a single 64-column tile
 
 
 def lmax_of(nside: int) -> int:
@@ -51,7 +53,7 @@ def npix(nside: int) -> int:
 
 def bucket(n: int) -> int:
     """Chunk width for a batch of n map sets (the kernels' column granularity)."""
-    return -(-n // GRANULE) * GRANULE
+    return SMALL if n <= SMALL else -(-n // GRANULE) * GRANULE
 
 
 @dataclasses.dataclass
@@ -121,7 +123,7 @@ def batch_cost(req: Request, n: int) -> float:
 def plan_bytes_estimate(nside: int, lmax: int, spin: int, slots: int) -> int:
     """Upper estimate of a plan's device bytes before it exists: the FP64
     workspace for a chunk of `slots` map sets (m-major ring coefficients for every
-    m and ring plus m-major alm rows, columns padded to the kernels' 64-map
+    m and ring plus m-major alm rows, columns padded to the kernels' column
     granularity) and the recursion tables (seed pairs every SEG rows of l per north
     ring, coefficient rows, skip bounds); ring and FFT tables are small and covered
     by a 5% margin."""

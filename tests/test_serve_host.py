@@ -195,8 +195,11 @@ def test_plan_estimate_grows_with_size():
     small = serve.plan_bytes_estimate(64, 191, 0, 16)
     assert serve.plan_bytes_estimate(64, 191, 2, 16) > small
     assert serve.plan_bytes_estimate(128, 383, 0, 16) > small
-    # 64-map column granularity: 1..64 map sets cost the same workspace
-    assert serve.plan_bytes_estimate(64, 191, 0, 1) == serve.plan_bytes_estimate(64, 191, 0, 64)
+    # column granularity: 1..32 map sets share one tile, then multiples of 64
+    assert serve.plan_bytes_estimate(64, 191, 0, 1) == serve.plan_bytes_estimate(64, 191, 0, 32)
+    assert serve.plan_bytes_estimate(64, 191, 0, 33) == serve.plan_bytes_estimate(64, 191, 0, 64)
+    assert serve.plan_bytes_estimate(64, 191, 0, 32) < serve.plan_bytes_estimate(64, 191, 0, 33)
+    assert [serve.bucket(n) for n in (1, 32, 33, 64, 65)] == [32, 32, 64, 64, 128]
 
 
 def test_request_mix_is_seeded_and_bounded():
