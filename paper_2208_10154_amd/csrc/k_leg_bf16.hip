@@ -61,6 +61,26 @@ __device__ __forceinline__ v8bf lds8(const __bf16* p) { return *reinterpret_cast
 
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
+// Row loads through a buffer descriptor: one per-lane offset for the first row
+// and a wave-uniform scalar offset per further row, so a chunk's eight rows cost
+// no vector address arithmetic.  Used only where every row lies inside the block
+// (the scalar offset is outside the hardware range check); the last, overhanging
+// chunk takes the clamped per-row addresses instead.
+struct Rows {
+    __amdgpu_buffer_rsrc_t r;
+    bool ok;  // the block fits 31-bit byte offsets
+    __device__ __forceinline__ Rows(const void* base, int64_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                              (int)(bytes < 0x7fffffff ? bytes : 0x7fffffff), 0x00020000)),
+          ok(bytes < 0x7fffffff)
+    {
+    }
+    __device__ __forceinline__ uint32_t ld(int voff, int soff) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    }
+};
+
 // hi and lo operand vectors of eight split-BF16 words (hi in the low half of
 // each word): two halves regrouped per output word
 __device__ __forceinline__ void unpack8(const uint32_t (&d)[8], v8bf& hi, v8bf& lo)
@@ -161,7 +181,21 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
             return e;
         };
         float xr[2][NU][8];  // [north, south][column tile][ring k0 + e] of the next chunk
+        const Rows xb(static_cast<const float*>(a.X) + (int64_t)m * a.nring * a.ldx, (int64_t)a.nring * a.ldx * 4);
+        const int rstep = (int)a.ldx * 4;
         auto load_x = [&](int rc) {
+            if (xb.ok && (rc + 1) * M_TR <= a.rn) {  // whole chunk inside the hemisphere
+                const int vn = ((rc * M_TR + k0) * (int)a.ldx + col) * 4;
+                const int vs = ((a.nring - 1 - (rc * M_TR + k0 + 7)) * (int)a.ldx + col) * 4;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int u = 0; u < NU; ++u) {
+                        xr[0][u][e] = __builtin_bit_cast(float, xb.ld(vn + 64 * u, e * rstep));
+                        xr[1][u][e] = __builtin_bit_cast(float, xb.ld(vs + 64 * u, (7 - e) * rstep));
+                    }
+                return;
+            }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int r = min(rc * M_TR + k0 + e, a.rn - 1);
@@ -298,7 +332,25 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
             return e;
         };
         float xr[4][NU][8];  // [Q_N, Q_S, U_N, U_S][column tile][ring k0 + e]
+        const int64_t xblk = (int64_t)a.nring * a.ldx;
+        const Rows qb(static_cast<const float*>(a.X) + a.xcomp + xm, xblk * 4);
+        const Rows ub(static_cast<const float*>(a.X) + 2 * a.xcomp + xm, xblk * 4);
+        const int rstep = (int)a.ldx * 4;
         auto load_x = [&](int rc) {
+            if (qb.ok && (rc + 1) * M_TR <= a.rn) {  // whole chunk inside the hemisphere
+                const int rn0 = (rc * M_TR + k0) * (int)a.ldx * 4;
+                const int rs0 = (a.nring - 1 - (rc * M_TR + k0 + 7)) * (int)a.ldx * 4;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int u = 0; u < NU; ++u) {
+                        xr[0][u][e] = __builtin_bit_cast(float, qb.ld(rn0 + (col + 16 * u) * 4, e * rstep));
+                        xr[1][u][e] = __builtin_bit_cast(float, qb.ld(rs0 + (col + 16 * u) * 4, (7 - e) * rstep));
+                        xr[2][u][e] = __builtin_bit_cast(float, ub.ld(rn0 + (pcol + 16 * u) * 4, e * rstep));
+                        xr[3][u][e] = __builtin_bit_cast(float, ub.ld(rs0 + (pcol + 16 * u) * 4, (7 - e) * rstep));
+                    }
+                return;
+            }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int r = min(rc * M_TR + k0 + e, a.rn - 1);
