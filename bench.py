@@ -81,6 +81,51 @@ def paper_form_flops(nside: int, lmax: int) -> float:
     return 5 * 2.0 * (4 * nside - 1) * (lmax + 1) * (lmax + 2)
 
 
+def cl_index(lmax: int, device):
+    """l and weight of every entry of the compact (lmax+1)^2 storage: entry (row i,
+    col j) holds Re a_{i,j} (i >= j, weight 1 for m = 0, else 2) or Im a_{l,m} with
+    m = lmax+1-j, l = i+m (i < j, weight 2), so C_l = sum w a^2 / (2l+1)."""
+    import torch
+    n = lmax + 1
+    i = torch.arange(n, device=device).repeat(n)          # row (fast index, column-major)
+    j = torch.arange(n, device=device).repeat_interleave(n)
+    re = i >= j
+    ell = torch.where(re, i, i + n - j)
+    w = torch.where(re & (j == 0), 1.0, 2.0).to(torch.float64)
+    return ell, w
+
+
+def accuracy(sht, args, prec, alm, maps, alm_out, ref):
+    """Mixed-precision error statistics on the first IQU triple against the FP64
+    results of the same inputs (the paper gives no mixed-precision bar beyond what
+    is reported here): relative RMS of the synthesised maps and of the analysed
+    a_lm (worst component), the largest relative error of the power spectrum
+    C_l (l >= 2) of the analysed a_lm, and the round-trip residual
+    |m - Y A m| / |m| of this precision."""
+    import torch
+    L = args.lmax
+    ell, w = cl_index(L, alm.device)
+
+    def cl(a):
+        c = torch.zeros((3, L + 1), dtype=torch.float64, device=a.device)
+        c.index_add_(1, ell, w * a * a)
+        return c / (2 * torch.arange(L + 1, device=a.device, dtype=torch.float64) + 1)
+
+    def rel(x, y):
+        return float(((x - y).norm(dim=-1) / y.norm(dim=-1)).max().item())
+
+    out = {"maps_rel_rms": rel(maps[0], ref["maps"]), "alm_rel_rms": rel(alm_out[0], ref["alm"])}
+    c, c0 = cl(alm_out[0]), cl(ref["alm"])
+    out["cl_max_rel_err"] = float(((c - c0).abs() / c0)[:, 2:].max().item())
+    p = sht.Plan(args.nside, L, 2, 1, precision=prec)
+    rt = torch.empty_like(maps[:1])
+    p.alm2map(alm_out[:1], rt)
+    p.sync()
+    p.close()
+    out["roundtrip_residual"] = rel(rt[0], maps[0])
+    return {k: float(f"{v:.3e}") for k, v in out.items()}
+
+
 def run_precision(sht, args, prec, alm, maps, alm_out):
     import torch
     nside, lmax, n = args.nside, args.lmax, args.nmaps
@@ -196,7 +241,14 @@ def cpu_baseline(args):
     m = synth.white_maps(12 * args.nside ** 2, 1, 3, workload=3)[0]
     t_a2m, t_m2a = oracle.timing_sample_iqu(args.nside, args.lmax, a, m, stride)
     sec_per_triple = stride * (t_a2m + t_m2a)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": round(1.0 / sec_per_triple, 6), "unit": "IQU map triples/s", "cores": oracle.num_threads(),
+            "cpu_model": model, "nproc": os.cpu_count(),
             "kind": "oracle",
             "sample": (f"1 IQU triple at nside {args.nside}, lmax {args.lmax}: alm2map on every {stride}th ring, "
                        f"map2alm on every {stride}th m ({t_a2m + t_m2a:.1f} s measured), scaled by {stride}"),
@@ -207,8 +259,8 @@ def iteration_leg(args):
     """Config 4: map2alm_iter with N_iter = 3 on nside 1024, lmax 2047, 200 IQU
     triples (Gaussian a_lm synthesised in FP64 plus white noise at 1e-2 of each
     map's RMS), contraction in each requested precision, residual in FP64.  Reports
-    seconds per run at N_iter 0 and 3, the per-iteration cost, triples/s and the
-    RMS residual after every iteration."""
+    seconds per run at N_iter 0, 3 and 9 with the fit of t0 + (2 N_iter + 1) t1,
+    the per-iteration cost, triples/s and the RMS residual after every iteration."""
     import torch
     from paper_2208_10154_amd import sht
     nside, n, niter = args.iter_nside, args.iter_nmaps, 3
@@ -234,18 +286,28 @@ def iteration_leg(args):
         p.set_precision(prec)
         p.map2alm_iter(maps, out, 0)  # warm-up (work lists, iteration buffers)
         torch.cuda.synchronize()
-        times = {}
-        for k in (0, niter):
+        times, resid = {}, {}
+        for k in (0, 9, niter):  # the N_iter = 3 run last, so `out` holds its result
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            r = p.map2alm_iter(maps, out, k, residuals=True)
+            resid[k] = p.map2alm_iter(maps, out, k, residuals=True)
             e1.record(stream)
             torch.cuda.synchronize()
             times[k] = e0.elapsed_time(e1) / 1e3
         err = float(((out - alm).norm() / alm.norm()).item())
+        # the paper's cost model t = t0 + (2 N_iter + 1) t1 (Appendix B), least squares over N_iter 0, 3, 9
+        ks = sorted(times)
+        xs = [2 * k + 1 for k in ks]
+        xm, ym = sum(xs) / 3, sum(times[k] for k in ks) / 3
+        t1 = sum((x - xm) * (times[k] - ym) for x, k in zip(xs, ks)) / sum((x - xm) ** 2 for x in xs)
+        t0 = ym - t1 * xm
         res[prec] = {"s_niter0": round(times[0], 3), f"s_niter{niter}": round(times[niter], 3),
+                     "s_niter9": round(times[9], 3),
                      "s_per_iteration": round((times[niter] - times[0]) / niter, 3),
-                     "triples_per_s": round(n / times[niter], 2), "residual_rms": [float(f"{x:.6e}") for x in r],
+                     "fit_t0_s": round(t0, 4), "fit_t1_s": round(t1, 4),
+                     "triples_per_s": round(n / times[niter], 2),
+                     "residual_rms": [float(f"{x:.6e}") for x in resid[niter]],
+                     "residual_rms_niter9": [float(f"{x:.6e}") for x in resid[9]],
                      "rel_err_vs_input_alm": float(f"{err:.4e}")}
         log(f"iteration {prec}: {res[prec]}")
     p.close()
@@ -373,9 +435,17 @@ def main():
     alm_out = torch.empty_like(alm)
     torch.cuda.synchronize()
     log(f"inputs resident: {(alm.numel() * 2 + maps.numel()) * 8 / 1e9:.1f} GB")
-    results = {}
-    for prec in args.precisions.split(","):
+    results, ref, acc = {}, None, {}
+    precs = args.precisions.split(",")
+    precs = (["fp64"] if "fp64" in precs else []) + [q for q in precs if q != "fp64"]
+    for prec in precs:
         results[prec] = run_precision(sht, args, prec, alm, maps, alm_out)
+        if prec == "fp64":
+            ref = {"maps": maps[0].clone(), "alm": alm_out[0].clone()}
+            acc[prec] = accuracy(sht, args, prec, alm, maps, alm_out, ref)
+        elif ref is not None:
+            acc[prec] = accuracy(sht, args, prec, alm, maps, alm_out, ref)
+        log(f"{prec}: accuracy {acc.get(prec)}")
     head = "fp64" if "fp64" in results else list(results)[0]
     r = results[head]
     line = {
@@ -387,7 +457,9 @@ def main():
                    "map_triples": n, "spin": 2, "chunk": args.chunk, "step": "alm2map+map2alm"},
         "by_precision": {k: {"value": round(v["value"], 3), "ms_per_step": round(v["ms_per_step"], 3),
                              "plan_init_s": round(v["init_s"], 2),
-                             "stages_ms_per_step": {s: round(t / args.steps, 3) for s, (t, c) in v["stages"].items() if c}}
+                             "component_maps_per_s": round(3 * v["value"], 2),
+                             "stages_ms_per_step": {s: round(t / args.steps, 3) for s, (t, c) in v["stages"].items() if c},
+                             **({"accuracy_vs_fp64": acc[k]} if k in acc else {})}
                          for k, v in results.items()},
         "roofline": roofline(args, head, r),
         "paper_form_tflops_equiv": round(2 * paper_form_flops(args.nside, L) * n / (r["ms_per_step"] * 1e-3) / 1e12, 2),
