@@ -162,6 +162,47 @@ def run_precision(sht, args, prec, alm, maps, alm_out):
     return {"ms_per_step": per_step, "value": n * 1000.0 / per_step, "init_s": init_s, "stages": prof}
 
 
+def eb_leg(sht, args, precs, alm, maps, alm_out):
+    """Separate E / B transforms and pixel-domain E/B separation on the first
+    `--eb-nmaps` triples of the resident workload: eb_split throughput per
+    precision, and the spin-2 contraction time of E-only against E and B
+    (one profiled call each of alm2map_sel and map2alm_sel)."""
+    import torch
+    ne = min(args.eb_nmaps, args.nmaps)
+    x, a = maps[:ne], alm_out[:ne]
+    me, mb = torch.empty_like(x), torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    out = {"map_triples": ne, "chunk": args.chunk}
+    for prec in precs:
+        p = sht.Plan(args.nside, args.lmax, 2, ne, precision=prec, chunk=args.chunk)
+        p.eb_split(x, a, me, mb, stream)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            p.eb_split(x, a, me, mb, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        p.set_profiling(True)
+        half = {}
+        for name, fn, src, dst, stage in (("alm2map", p.alm2map_sel, alm[:ne], me, "a2m_spin2"),
+                                          ("map2alm", p.map2alm_sel, x, a, "m2a_spin2")):
+            t = {}
+            for sel in ("EB", "E", "B"):
+                p.profile(reset=True)
+                fn(sel, src, dst, stream)
+                t[sel] = p.profile(reset=True)[stage][0]
+            half[name] = {"spin2_contraction_ms": {k: round(v, 2) for k, v in t.items()},
+                          "e_only_over_eb": round(t["E"] / t["EB"], 3)}
+        p.close()
+        out[prec] = {"eb_split_ms": round(ms, 2), "eb_split_triples_per_s": round(ne * 1000.0 / ms, 2), **half}
+        log(f"{prec}: eb_split {ms:.1f} ms for {ne} triples; E-only/EB contraction "
+            f"{half['alm2map']['e_only_over_eb']} (alm2map), {half['map2alm']['e_only_over_eb']} (map2alm)")
+    del me, mb
+    return out
+
+
 LEG_SOURCES = ["paper_2208_10154_amd/csrc/k_leg.hip", "paper_2208_10154_amd/csrc/k_leg_bf16.hip",
                "paper_2208_10154_amd/csrc/leg_rec.h", "paper_2208_10154_amd/csrc/leg_common.h",
                "paper_2208_10154_amd/csrc/sht_internal.h"]
@@ -399,6 +440,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg (config 5)")
     ap.add_argument("--no-iter", action="store_true", help="skip the iteration leg (config 4)")
+    ap.add_argument("--no-eb", action="store_true", help="skip the E/B leg")
+    ap.add_argument("--eb-nmaps", type=int, default=250, help="IQU triples of the E/B leg")
     ap.add_argument("--iter-nside", type=int, default=1024)
     ap.add_argument("--iter-nmaps", type=int, default=200)
     ap.add_argument("--iter-chunk", type=int, default=64)
@@ -470,6 +513,8 @@ def main():
         for k in results:
             if k != head:
                 line["by_precision"][k]["roofline"] = roofline(args, k, results[k])
+    if not args.no_eb:
+        line["eb"] = eb_leg(sht, args, precs, alm, maps, alm_out)
     del alm, maps, alm_out
     torch.cuda.empty_cache()
     if not args.no_iter:

@@ -116,6 +116,44 @@ int sht_map2alm(sht_plan plan, const double* map, double* alm);
  * synchronises the stream. */
 int sht_map2alm_iter(sht_plan plan, const double* map, double* alm, int niter, double* resid);
 
+/* Components of the selective transforms (bit mask). */
+enum sht_comp {
+    SHT_COMP_T = 1,   /* temperature / intensity: the spin-0 part */
+    SHT_COMP_E = 2,   /* E mode of a spin-2 plan */
+    SHT_COMP_B = 4,   /* B mode of a spin-2 plan */
+    SHT_COMP_ALL = 7
+};
+
+/* Backward transform of the selected components only: the coefficients of the
+ * components left out are not read (they act as zero), so the maps hold the
+ * synthesis of the selected ones; a map component with nothing selected (I when
+ * T is left out, Q and U when E and B are) is written as zero.  With E or B alone
+ * the spin-2 contraction keeps one half of the 0/1 diagonal selector lambda^{E,B}
+ * of Sec. 2.3 and does half of its products (the separate E / B transforms of
+ * Sec. 3.1, "support forward and backward transforms of E and B separately").
+ * comps: nonzero mask of enum sht_comp; a spin-0 plan accepts only SHT_COMP_T.
+ * SHT_ERR_ARG otherwise.  sht_alm2map is this call with every component. */
+int sht_alm2map_sel(sht_plan plan, int comps, const double* alm, double* map);
+
+/* Forward transform of the selected components only: the coefficients of the
+ * components left out are written as zero, and only the map components the
+ * selection needs are read (I for T, Q and U for E or B).  Same comps rules as
+ * sht_alm2map_sel; sht_map2alm is this call with every component. */
+int sht_map2alm_sel(sht_plan plan, int comps, const double* map, double* alm);
+
+/* Pixel-domain E/B separation of IQU map triples, S^{E,B} = F^t lambda^{E,B} F S
+ * (Sec. 2.3, the block-matrix form with the 0/1 diagonal selector):
+ *   alm   <- map2alm(map) (T, E, B; as sht_map2alm),
+ *   map_e <- alm2map of (T, E, 0): Q/U are the E-mode part of the polarisation,
+ *            I is the band-limited intensity,
+ *   map_b <- alm2map of (0, 0, B): Q/U are the B-mode part, I is zero,
+ * so map_e + map_b = alm2map(alm).  The coefficient rows are laid out once and
+ * the E and B syntheses each run the half-block contraction.  Spin-2 plans only;
+ * map_e and map_b must be distinct and must not overlap alm or map (map_e may be
+ * map itself: each chunk is read before it is overwritten).  Device pointers,
+ * layouts as above. */
+int sht_eb_split(sht_plan plan, const double* map, double* alm, double* map_e, double* map_b);
+
 /* Stages timed by the optional profiler. */
 enum sht_stage {
     SHT_STAGE_FFT_FWD = 0,     /* ring FFT + m-unfold (maps -> ring coefficients) */

@@ -191,6 +191,38 @@ def map2alm_iqu(nside: int, lmax: int, maps: np.ndarray) -> np.ndarray:
     return out
 
 
+_COMP = {"T": 0, "E": 1, "B": 2}
+
+
+def _keep(alm: np.ndarray, comps: str) -> np.ndarray:
+    """Copy of complex IQU coefficients [n, 3, L+1, L+1] with the components not
+    named in comps (letters of "TEB") set to zero: the 0/1 diagonal selector
+    lambda^{E,B} of Sec. 2.3, extended by T."""
+    out = np.zeros_like(alm)
+    for c in comps:
+        out[:, _COMP[c]] = alm[:, _COMP[c]]
+    return out
+
+
+def alm2map_sel(nside: int, lmax: int, alm: np.ndarray, comps: str) -> np.ndarray:
+    """Backward IQU transform of the named components only (the separate E / B
+    transforms of Sec. 3.1): the others' coefficients are treated as zero."""
+    return alm2map_iqu(nside, lmax, _keep(alm, comps))
+
+
+def map2alm_sel(nside: int, lmax: int, maps: np.ndarray, comps: str) -> np.ndarray:
+    """Forward IQU transform keeping only the named components (others zero)."""
+    return _keep(map2alm_iqu(nside, lmax, maps), comps)
+
+
+def eb_split(nside: int, lmax: int, maps: np.ndarray):
+    """Pixel-domain E/B separation of Sec. 2.3, S^{E,B} = F^t lambda^{E,B} F S:
+    analyse the IQU maps, then synthesise once from (T, E) and once from B alone.
+    Returns (alm, maps_e, maps_b); maps_e + maps_b = alm2map_iqu(alm)."""
+    a = map2alm_iqu(nside, lmax, maps)
+    return a, alm2map_iqu(nside, lmax, _keep(a, "TE")), alm2map_iqu(nside, lmax, _keep(a, "B"))
+
+
 def synth(nside, lmax, alm, pol):
     return alm2map_iqu(nside, lmax, alm) if pol else alm2map(nside, lmax, alm)
 

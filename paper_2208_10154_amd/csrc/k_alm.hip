@@ -9,6 +9,8 @@
 // both sides are read and written in contiguous runs.  They also carry the scalar
 // work of the boundary: dsigma and accumulation for map2alm (the paper's GEMM
 // alpha/beta, Sec. 3.1 item 7) and the B <-> iB change of variable of Sec. 2.3.
+#include <algorithm>
+
 #include "sht_internal.h"
 
 namespace sht {
@@ -138,7 +140,26 @@ __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
     }
 }
 
+// Zero len doubles at base + i*stride for i < rows (components a selective
+// transform leaves out); a kernel rather than a memset so the call may be captured.
+__global__ __launch_bounds__(NT) void k_zero_strided(double* base, int rows, int64_t stride, int64_t len)
+{
+    for (int i = blockIdx.y; i < rows; i += gridDim.y) {
+        double* r = base + (int64_t)i * stride;
+        for (int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x; j < len; j += (int64_t)gridDim.x * NT) r[j] = 0.0;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_zero_strided(double* base, int rows, int64_t stride, int64_t len, hipStream_t st)
+{
+    if (rows <= 0 || len <= 0) return hipSuccess;
+    const int64_t bx = std::min<int64_t>((len + NT - 1) / NT, 1024);
+    const dim3 grid((unsigned)bx, (unsigned)std::min(rows, 1024));
+    hipLaunchKernelGGL(k_zero_strided, grid, dim3(NT), 0, st, base, rows, stride, len);
+    return hipGetLastError();
+}
 
 hipError_t launch_alm_to_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st)
 {

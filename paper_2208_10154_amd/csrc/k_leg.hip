@@ -185,9 +185,10 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
 //   even l-m: A_E = F+ SX + F- DY,  iA_B = F+ SY + F- DX
 //   odd  l-m: A_E = F+ DX + F- SY,  iA_B = F+ DY + F- SX
 // X = Q coefficients, Y = iU; S/D = north +- south.  Tile 64 l x 64*NU columns,
-// rings in chunks of 32; wave w owns NU column tiles of 16.
+// rings in chunks of 32; wave w owns NU column tiles of 16.  EB = 1 (E only) or
+// 2 (B only) computes one block row of the transform; the other stays zero.
 // ============================================================================
-template <typename T, int NU>
+template <typename T, int NU, int EB>
 __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
 {
     constexpr int RS = HALF + 1;
@@ -296,17 +297,25 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
                     const T sy = flip((T)(d[2][u] + d[3][u]), ysg), dy = flip((T)(d[2][u] - d[3][u]), ysg);
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
-                        accE[0][t][u] = MF::run(fp[0][t], sx, accE[0][t][u]);
-                        accB[0][t][u] = MF::run(fp[0][t], sy, accB[0][t][u]);
-                        accE[1][t][u] = MF::run(fp[1][t], dx, accE[1][t][u]);
-                        accB[1][t][u] = MF::run(fp[1][t], dy, accB[1][t][u]);
+                        if constexpr (EB != 2) {
+                            accE[0][t][u] = MF::run(fp[0][t], sx, accE[0][t][u]);
+                            accE[1][t][u] = MF::run(fp[1][t], dx, accE[1][t][u]);
+                        }
+                        if constexpr (EB != 1) {
+                            accB[0][t][u] = MF::run(fp[0][t], sy, accB[0][t][u]);
+                            accB[1][t][u] = MF::run(fp[1][t], dy, accB[1][t][u]);
+                        }
                     }
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
-                        accE[0][t][u] = MF::run(fm[0][t], dy, accE[0][t][u]);
-                        accB[0][t][u] = MF::run(fm[0][t], dx, accB[0][t][u]);
-                        accE[1][t][u] = MF::run(fm[1][t], sy, accE[1][t][u]);
-                        accB[1][t][u] = MF::run(fm[1][t], sx, accB[1][t][u]);
+                        if constexpr (EB != 2) {
+                            accE[0][t][u] = MF::run(fm[0][t], dy, accE[0][t][u]);
+                            accE[1][t][u] = MF::run(fm[1][t], sy, accE[1][t][u]);
+                        }
+                        if constexpr (EB != 1) {
+                            accB[0][t][u] = MF::run(fm[0][t], dx, accB[0][t][u]);
+                            accB[1][t][u] = MF::run(fm[1][t], sx, accB[1][t][u]);
+                        }
                     }
                 }
                 if (filler) rec_group<ks, RPK>(f, cp, cnt, em);
@@ -494,7 +503,9 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
 // ============================================================================
 constexpr int A2_TR = 32;
 
-template <typename T, int NU>
+// EB = 1 (E only) or 2 (B only) drops the other block's loads and products:
+// the half-block transforms of pixel-domain E/B separation (Sec. 2.3).
+template <typename T, int NU, int EB>
 __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
 {
     constexpr int RS = A2_TR + 1;
@@ -553,10 +564,18 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
             const int64_t oo = (int64_t)(min(lc + (po ^ 1), L) - lb) * a.ldx;
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
-                d[0][u] = AE[oe + 16 * u];
-                d[1][u] = AE[oo + 16 * u];
-                d[2][u] = AB[oe + 16 * u];
-                d[3][u] = AB[oo + 16 * u];
+                if constexpr (EB != 2) {
+                    d[0][u] = AE[oe + 16 * u];
+                    d[1][u] = AE[oo + 16 * u];
+                } else {
+                    d[0][u] = d[1][u] = T(0);
+                }
+                if constexpr (EB != 1) {
+                    d[2][u] = AB[oe + 16 * u];
+                    d[3][u] = AB[oo + 16 * u];
+                } else {
+                    d[2][u] = d[3][u] = T(0);
+                }
             }
         };
 
@@ -601,17 +620,25 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
                     const T me = fb[FOFF + o], mo = fb[FOFF + CLS + o];
 #pragma unroll
                     for (int u = 0; u < NU; ++u) {
-                        u1[t][u] = MF::run(pe, d[0][u], u1[t][u]);
-                        u2[t][u] = MF::run(pd, d[1][u], u2[t][u]);
-                        v1[t][u] = MF::run(pe, d[2][u], v1[t][u]);
-                        v2[t][u] = MF::run(pd, d[3][u], v2[t][u]);
+                        if constexpr (EB != 2) {
+                            u1[t][u] = MF::run(pe, d[0][u], u1[t][u]);
+                            u2[t][u] = MF::run(pd, d[1][u], u2[t][u]);
+                        }
+                        if constexpr (EB != 1) {
+                            v1[t][u] = MF::run(pe, d[2][u], v1[t][u]);
+                            v2[t][u] = MF::run(pd, d[3][u], v2[t][u]);
+                        }
                     }
 #pragma unroll
                     for (int u = 0; u < NU; ++u) {
-                        u1[t][u] = MF::run(mo, d[3][u], u1[t][u]);
-                        u2[t][u] = MF::run(me, d[2][u], u2[t][u]);
-                        v1[t][u] = MF::run(mo, d[1][u], v1[t][u]);
-                        v2[t][u] = MF::run(me, d[0][u], v2[t][u]);
+                        if constexpr (EB != 2) {
+                            v1[t][u] = MF::run(mo, d[1][u], v1[t][u]);
+                            v2[t][u] = MF::run(me, d[0][u], v2[t][u]);
+                        }
+                        if constexpr (EB != 1) {
+                            u1[t][u] = MF::run(mo, d[3][u], u1[t][u]);
+                            u2[t][u] = MF::run(me, d[2][u], u2[t][u]);
+                        }
                     }
                 }
                 if (filler) rec_group<ks, RPK>(f, cp, cnt, em);
@@ -674,8 +701,16 @@ hipError_t launch_m2a_t(const LegArgs& a, hipStream_t st)
     } else {
         const int nu = pick_nu(2, a.ldx);
         b.ctiles = (int)(a.ldx / (64 * nu));
-        if (nu == 2) hipLaunchKernelGGL((k_m2a_spin2<T, 2>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
-        else hipLaunchKernelGGL((k_m2a_spin2<T, 1>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
+        const dim3 grid(b.ntiles * b.ctiles);
+        if (nu == 2) {
+            if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2<T, 2, 1>), grid, blk, 0, st, b);
+            else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2<T, 2, 2>), grid, blk, 0, st, b);
+            else hipLaunchKernelGGL((k_m2a_spin2<T, 2, 0>), grid, blk, 0, st, b);
+        } else {
+            if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2<T, 1, 1>), grid, blk, 0, st, b);
+            else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2<T, 1, 2>), grid, blk, 0, st, b);
+            else hipLaunchKernelGGL((k_m2a_spin2<T, 1, 0>), grid, blk, 0, st, b);
+        }
     }
     return hipGetLastError();
 }
@@ -702,8 +737,15 @@ hipError_t launch_a2m_t(const LegArgs& a, hipStream_t st)
         const int nu = pick_nu(2, a.ldx);
         b.ctiles = (int)(a.ldx / (64 * nu));
         const dim3 grid((a.lmax + 1) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR));
-        if (nu == 2) hipLaunchKernelGGL((k_a2m_spin2<T, 2>), grid, blk, 0, st, b);
-        else hipLaunchKernelGGL((k_a2m_spin2<T, 1>), grid, blk, 0, st, b);
+        if (nu == 2) {
+            if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2<T, 2, 1>), grid, blk, 0, st, b);
+            else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2<T, 2, 2>), grid, blk, 0, st, b);
+            else hipLaunchKernelGGL((k_a2m_spin2<T, 2, 0>), grid, blk, 0, st, b);
+        } else {
+            if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2<T, 1, 1>), grid, blk, 0, st, b);
+            else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2<T, 1, 2>), grid, blk, 0, st, b);
+            else hipLaunchKernelGGL((k_a2m_spin2<T, 1, 0>), grid, blk, 0, st, b);
+        }
     }
     return hipGetLastError();
 }

@@ -273,10 +273,10 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
 }
 
 // ============================================================================
-// map2alm, spin 2 (see k_m2a_spin2 in k_leg.hip for the block form).
+// map2alm, spin 2 (see k_m2a_spin2 in k_leg.hip for the block form and EB).
 // LDS: [buffer][hi, lo][F+, F-][parity class][class row][ring (K)].
 // ============================================================================
-template <int NU>
+template <int NU, int EB>
 __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
 {
     constexpr int CLS = HALF * KP, FOFF = 2 * CLS, HL = 2 * FOFF, BUF = 2 * HL;
@@ -411,10 +411,14 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
                     constexpr int X1 = cls ? 1 : 0, Y1 = cls ? 3 : 2, X2 = cls ? 0 : 1, Y2 = cls ? 2 : 3;
 #pragma unroll
                     for (int u = 0; u < NU; ++u) {
-                        accE[cls][t][u] = mfma3(ph_, pl, bh[X1][u], bl[X1][u], accE[cls][t][u]);
-                        accB[cls][t][u] = mfma3(ph_, pl, bh[Y1][u], bl[Y1][u], accB[cls][t][u]);
-                        accE[cls][t][u] = mfma3(mh, ml, bh[Y2][u], bl[Y2][u], accE[cls][t][u]);
-                        accB[cls][t][u] = mfma3(mh, ml, bh[X2][u], bl[X2][u], accB[cls][t][u]);
+                        if constexpr (EB != 2) {
+                            accE[cls][t][u] = mfma3(ph_, pl, bh[X1][u], bl[X1][u], accE[cls][t][u]);
+                            accE[cls][t][u] = mfma3(mh, ml, bh[Y2][u], bl[Y2][u], accE[cls][t][u]);
+                        }
+                        if constexpr (EB != 1) {
+                            accB[cls][t][u] = mfma3(ph_, pl, bh[Y1][u], bl[Y1][u], accB[cls][t][u]);
+                            accB[cls][t][u] = mfma3(mh, ml, bh[X2][u], bl[X2][u], accB[cls][t][u]);
+                        }
                     }
                 }
                 if (filler) rec_group<P, RPP>(f, cp, cnt, em);
@@ -597,7 +601,8 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
 // ============================================================================
 constexpr int A2_TR = 32;
 
-template <int NU>
+// EB = 1 (E only) or 2 (B only): the half-block transforms, as in k_leg.hip
+template <int NU, int EB>
 __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
 {
     constexpr int CLS = A2_TR * KP, FOFF = 2 * CLS, HL = 2 * FOFF, BUF = 2 * HL;
@@ -656,10 +661,18 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
                 const int lc = lfirst + TL * c + 2 * (k0 + e);
                 const int64_t oe = (int64_t)(min(lc + po, L) - lb) * a.ldx + 16 * u;
                 const int64_t oo = (int64_t)(min(lc + (po ^ 1), L) - lb) * a.ldx + 16 * u;
-                ar[0][u][e] = AE[oe];
-                ar[1][u][e] = AE[oo];
-                ar[2][u][e] = AB[oe];
-                ar[3][u][e] = AB[oo];
+                if constexpr (EB != 2) {
+                    ar[0][u][e] = AE[oe];
+                    ar[1][u][e] = AE[oo];
+                } else {
+                    ar[0][u][e] = ar[1][u][e] = 0u;
+                }
+                if constexpr (EB != 1) {
+                    ar[2][u][e] = AB[oe];
+                    ar[3][u][e] = AB[oo];
+                } else {
+                    ar[2][u][e] = ar[3][u][e] = 0u;
+                }
             }
         };
 
@@ -713,18 +726,26 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
                         // F+ terms: U1 += F+e E_e, U2 += F+o E_o, V1 += F+e B'_e, V2 += F+o B'_o
                         const v8bf eh = lds8(q), el = lds8(q + HL);
                         const v8bf oh = lds8(q + CLS), ol = lds8(q + CLS + HL);
-                        u1[t][u] = mfma3(eh, el, bh[0], bl[0], u1[t][u]);
-                        u2[t][u] = mfma3(oh, ol, bh[1], bl[1], u2[t][u]);
-                        v1[t][u] = mfma3(eh, el, bh[2], bl[2], v1[t][u]);
-                        v2[t][u] = mfma3(oh, ol, bh[3], bl[3], v2[t][u]);
+                        if constexpr (EB != 2) {
+                            u1[t][u] = mfma3(eh, el, bh[0], bl[0], u1[t][u]);
+                            u2[t][u] = mfma3(oh, ol, bh[1], bl[1], u2[t][u]);
+                        }
+                        if constexpr (EB != 1) {
+                            v1[t][u] = mfma3(eh, el, bh[2], bl[2], v1[t][u]);
+                            v2[t][u] = mfma3(oh, ol, bh[3], bl[3], v2[t][u]);
+                        }
                     } else {
                         // F- terms: U1 += F-o B'_o, U2 += F-e B'_e, V1 += F-o E_o, V2 += F-e E_e
                         const v8bf eh = lds8(q + FOFF), el = lds8(q + FOFF + HL);
                         const v8bf oh = lds8(q + FOFF + CLS), ol = lds8(q + FOFF + CLS + HL);
-                        u1[t][u] = mfma3(oh, ol, bh[3], bl[3], u1[t][u]);
-                        u2[t][u] = mfma3(eh, el, bh[2], bl[2], u2[t][u]);
-                        v1[t][u] = mfma3(oh, ol, bh[1], bl[1], v1[t][u]);
-                        v2[t][u] = mfma3(eh, el, bh[0], bl[0], v2[t][u]);
+                        if constexpr (EB != 1) {
+                            u1[t][u] = mfma3(oh, ol, bh[3], bl[3], u1[t][u]);
+                            u2[t][u] = mfma3(eh, el, bh[2], bl[2], u2[t][u]);
+                        }
+                        if constexpr (EB != 2) {
+                            v1[t][u] = mfma3(oh, ol, bh[1], bl[1], v1[t][u]);
+                            v2[t][u] = mfma3(eh, el, bh[0], bl[0], v2[t][u]);
+                        }
                     }
                 }
                 if (filler) rec_group<P, RPP>(f, cp, cnt, em);
@@ -776,7 +797,10 @@ hipError_t launch_leg_m2a_bf16(const LegArgs& a, hipStream_t st)
         }
     } else {
         b.ctiles = (int)(a.ldx / 64);
-        hipLaunchKernelGGL((k_m2a_spin2_bf<1>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
+        const dim3 grid(b.ntiles * b.ctiles);
+        if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 1>), grid, blk, 0, st, b);
+        else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 2>), grid, blk, 0, st, b);
+        else hipLaunchKernelGGL((k_m2a_spin2_bf<1, 0>), grid, blk, 0, st, b);
     }
     return hipGetLastError();
 }
@@ -794,7 +818,9 @@ hipError_t launch_leg_a2m_bf16(const LegArgs& a, hipStream_t st)
     } else {
         b.ctiles = (int)(a.ldx / 64);
         const dim3 grid((a.lmax + 1) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR));
-        hipLaunchKernelGGL((k_a2m_spin2_bf<1>), grid, blk, 0, st, b);
+        if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2_bf<1, 1>), grid, blk, 0, st, b);
+        else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2_bf<1, 2>), grid, blk, 0, st, b);
+        else hipLaunchKernelGGL((k_a2m_spin2_bf<1, 0>), grid, blk, 0, st, b);
     }
     return hipGetLastError();
 }

@@ -653,53 +653,120 @@ int use_width(sht_plan p, int nm)
     return build_items(p, (int)(p->ldx_cur / 4));
 }
 
-int run_a2m(sht_plan p, const double* alm, int nm)
+// Component selection (enum sht_comp bits) of the selective transforms.  The
+// spin-2 block row kept by E-only / B-only (Sec. 2.3: the 0/1 diagonal selector
+// lambda^{E,B}) goes to the Legendre kernels as LegArgs::eb.
+bool sel_t(int sel) { return (sel & SHT_COMP_T) != 0; }
+bool sel_pol(sht_plan p, int sel) { return p->spin == 2 && (sel & (SHT_COMP_E | SHT_COMP_B)) != 0; }
+int sel_eb(int sel)
 {
-    {
-        StageTimer t(p, SHT_STAGE_ALM_LAYOUT);
+    const int eb = sel & (SHT_COMP_E | SHT_COMP_B);
+    return eb == SHT_COMP_E ? 1 : eb == SHT_COMP_B ? 2 : 0;
+}
+
+int valid_sel(sht_plan p, int sel)
+{
+    if (sel == 0 || (sel & ~SHT_COMP_ALL)) return fail(SHT_ERR_ARG, "component selection must be a nonzero mask of SHT_COMP_T/E/B");
+    if (p->spin == 0 && sel != SHT_COMP_T) return fail(SHT_ERR_ARG, "a spin-0 plan has only the T component");
+    return SHT_OK;
+}
+
+// compact alm -> m-major operand rows for the selected components
+int run_to_mmajor(sht_plan p, const double* alm, int nm, int sel)
+{
+    StageTimer t(p, SHT_STAGE_ALM_LAYOUT);
+    if (sel_t(sel)) {
         AlmArgs t0 = alm_args(p, p->s0, nm);
         t0.alm_in = alm;
         HIPCHK(launch_alm_to_mmajor(t0, 1, p->prec, p->stream));
-        if (p->spin == 2) {
-            AlmArgs t2 = alm_args(p, p->s2, nm);
-            t2.alm_in = alm;
-            HIPCHK(launch_alm_to_mmajor(t2, 2, p->prec, p->stream));
-        }
     }
-    {
-        StageTimer t(p, SHT_STAGE_A2M_SPIN0);
-        HIPCHK(launch_leg_a2m(leg_args(p, p->s0), p->prec, p->stream));
-    }
-    if (p->spin == 2) {
-        StageTimer t(p, SHT_STAGE_A2M_SPIN2);
-        HIPCHK(launch_leg_a2m(leg_args(p, p->s2), p->prec, p->stream));
+    if (sel_pol(p, sel)) {
+        AlmArgs t2 = alm_args(p, p->s2, nm);
+        t2.alm_in = alm;
+        const int eb = sel_eb(sel);
+        if (eb == 2) t2.comp0 = 2;
+        HIPCHK(launch_alm_to_mmajor(t2, eb ? 1 : 2, p->prec, p->stream));
     }
     return SHT_OK;
 }
 
-int run_m2a(sht_plan p, double* alm, int nm, int accumulate)
+// m-major rows -> ring Fourier coefficients of the selected components
+int run_leg_a2m(sht_plan p, int sel)
+{
+    if (sel_t(sel)) {
+        StageTimer t(p, SHT_STAGE_A2M_SPIN0);
+        HIPCHK(launch_leg_a2m(leg_args(p, p->s0), p->prec, p->stream));
+    }
+    if (sel_pol(p, sel)) {
+        StageTimer t(p, SHT_STAGE_A2M_SPIN2);
+        LegArgs a = leg_args(p, p->s2);
+        a.eb = sel_eb(sel);
+        HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
+    }
+    return SHT_OK;
+}
+
+int run_a2m(sht_plan p, const double* alm, int nm, int sel = SHT_COMP_ALL)
+{
+    int rc = run_to_mmajor(p, alm, nm, sel);
+    return rc ? rc : run_leg_a2m(p, sel);
+}
+
+// Inverse ring FFTs of the selected components into maps; components left out
+// are written as zero.
+int run_fft_inv(sht_plan p, double* maps, int nm, int sel)
+{
+    FftArgs f = fft_args(p, nm);
+    f.maps_out = maps;
+    const bool t = sel_t(sel), pol = sel_pol(p, sel);
+    const int64_t mstride = (int64_t)p->ncomp * p->npix;
+    int ncompl = p->ncomp;
+    if (p->spin == 2 && !(t && pol)) {
+        f.comp0 = t ? 0 : 1;
+        ncompl = t ? 1 : 2;
+        double* zb = t ? maps + p->npix : maps;
+        HIPCHK(launch_zero_strided(zb, nm, mstride, (int64_t)(3 - ncompl) * p->npix, p->stream));
+    }
+    StageTimer tm(p, SHT_STAGE_FFT_INV);
+    HIPCHK(launch_fft_inverse(f, p->classes.data(), (int)p->classes.size(), ncompl, p->stream));
+    return SHT_OK;
+}
+
+int run_m2a(sht_plan p, double* alm, int nm, int accumulate, int sel = SHT_COMP_ALL)
 {
     const double dsig = 4.0 * M_PI / (double)p->npix;
-    {
-        StageTimer t(p, SHT_STAGE_M2A_SPIN0);
+    const bool t = sel_t(sel), pol = sel_pol(p, sel);
+    if (t) {
+        StageTimer tm(p, SHT_STAGE_M2A_SPIN0);
         HIPCHK(launch_leg_m2a(leg_args(p, p->s0), p->prec, p->stream));
     }
-    if (p->spin == 2) {
-        StageTimer t(p, SHT_STAGE_M2A_SPIN2);
-        HIPCHK(launch_leg_m2a(leg_args(p, p->s2), p->prec, p->stream));
+    if (pol) {
+        StageTimer tm(p, SHT_STAGE_M2A_SPIN2);
+        LegArgs a = leg_args(p, p->s2);
+        a.eb = sel_eb(sel);
+        HIPCHK(launch_leg_m2a(a, p->prec, p->stream));
     }
-    StageTimer t(p, SHT_STAGE_ALM_LAYOUT);
-    AlmArgs t0 = alm_args(p, p->s0, nm);
-    t0.alm_out = alm;
-    t0.scale = dsig;
-    t0.accumulate = accumulate;
-    HIPCHK(launch_alm_from_mmajor(t0, 1, p->prec, p->stream));
-    if (p->spin == 2) {
+    StageTimer tm(p, SHT_STAGE_ALM_LAYOUT);
+    const int64_t csz = (int64_t)(p->lmax + 1) * (p->lmax + 1);
+    const int64_t astride = (int64_t)p->ncomp * csz;
+    if (t) {
+        AlmArgs t0 = alm_args(p, p->s0, nm);
+        t0.alm_out = alm;
+        t0.scale = dsig;
+        t0.accumulate = accumulate;
+        HIPCHK(launch_alm_from_mmajor(t0, 1, p->prec, p->stream));
+    } else if (!accumulate) {
+        HIPCHK(launch_zero_strided(alm, nm, astride, csz, p->stream));
+    }
+    if (pol) {
+        // with E or B alone the kernel leaves the other block's rows zero
         AlmArgs t2 = alm_args(p, p->s2, nm);
         t2.alm_out = alm;
         t2.scale = dsig;
         t2.accumulate = accumulate;
         HIPCHK(launch_alm_from_mmajor(t2, 2, p->prec, p->stream));
+    } else if (p->spin == 2 && !accumulate) {
+        HIPCHK(launch_zero_strided(alm + csz, nm, astride, 2 * csz, p->stream));
     }
     return SHT_OK;
 }
@@ -841,31 +908,69 @@ int sht_plan_set_workspace(sht_plan p, void* ptr, size_t bytes)
     return SHT_OK;
 }
 
-int sht_alm2map(sht_plan p, const double* alm, double* map)
+int sht_alm2map_sel(sht_plan p, int comps, const double* alm, double* map)
 {
     int rc = check_ready(p);
     if (rc) return rc;
     if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
+    if ((rc = valid_sel(p, comps))) return rc;
     if ((rc = prep(p))) return rc;
     const int64_t astride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
     const int64_t mstride = (int64_t)p->ncomp * p->npix;
     for (int k0 = 0; k0 < p->nmaps; k0 += p->chunk) {
         int nm = std::min(p->chunk, p->nmaps - k0);
         if ((rc = use_width(p, nm))) return rc;
-        if ((rc = run_a2m(p, alm + k0 * astride, nm))) return rc;
+        if ((rc = run_a2m(p, alm + k0 * astride, nm, comps))) return rc;
+        if ((rc = run_fft_inv(p, map + k0 * mstride, nm, comps))) return rc;
+    }
+    return SHT_OK;
+}
+
+int sht_alm2map(sht_plan p, const double* alm, double* map)
+{
+    return sht_alm2map_sel(p, p && p->spin == 0 ? SHT_COMP_T : SHT_COMP_ALL, alm, map);
+}
+
+int sht_map2alm_sel(sht_plan p, int comps, const double* map, double* alm)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
+    if ((rc = valid_sel(p, comps))) return rc;
+    if ((rc = prep(p))) return rc;
+    const int64_t astride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
+    const int64_t mstride = (int64_t)p->ncomp * p->npix;
+    for (int k0 = 0; k0 < p->nmaps; k0 += p->chunk) {
+        int nm = std::min(p->chunk, p->nmaps - k0);
+        if ((rc = use_width(p, nm))) return rc;
         FftArgs f = fft_args(p, nm);
-        f.maps_out = map + k0 * mstride;
-        StageTimer t(p, SHT_STAGE_FFT_INV);
-        HIPCHK(launch_fft_inverse(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+        f.maps_in = map + k0 * mstride;
+        int ncompl = p->ncomp;
+        if (p->spin == 2 && !(sel_t(comps) && sel_pol(p, comps))) {
+            f.comp0 = sel_t(comps) ? 0 : 1;
+            ncompl = sel_t(comps) ? 1 : 2;
+        }
+        {
+            StageTimer t(p, SHT_STAGE_FFT_FWD);
+            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), ncompl, p->stream));
+        }
+        if ((rc = run_m2a(p, alm + k0 * astride, nm, 0, comps))) return rc;
     }
     return SHT_OK;
 }
 
 int sht_map2alm(sht_plan p, const double* map, double* alm)
 {
+    return sht_map2alm_sel(p, p && p->spin == 0 ? SHT_COMP_T : SHT_COMP_ALL, map, alm);
+}
+
+int sht_eb_split(sht_plan p, const double* map, double* alm, double* map_e, double* map_b)
+{
     int rc = check_ready(p);
     if (rc) return rc;
-    if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
+    if (!map || !alm || !map_e || !map_b) return fail(SHT_ERR_ARG, "null data pointer");
+    if (p->spin != 2) return fail(SHT_ERR_ARG, "E/B separation needs a spin-2 plan");
+    if (map_e == map_b) return fail(SHT_ERR_ARG, "map_e and map_b must be distinct arrays");
     if ((rc = prep(p))) return rc;
     const int64_t astride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
     const int64_t mstride = (int64_t)p->ncomp * p->npix;
@@ -878,7 +983,14 @@ int sht_map2alm(sht_plan p, const double* map, double* alm)
             StageTimer t(p, SHT_STAGE_FFT_FWD);
             HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
         }
-        if ((rc = run_m2a(p, alm + k0 * astride, nm, 0))) return rc;
+        double* a = alm + k0 * astride;
+        if ((rc = run_m2a(p, a, nm, 0))) return rc;
+        // the rows of T, E and iB are laid out once for both syntheses
+        if ((rc = run_to_mmajor(p, a, nm, SHT_COMP_ALL))) return rc;
+        if ((rc = run_leg_a2m(p, SHT_COMP_T | SHT_COMP_E))) return rc;
+        if ((rc = run_fft_inv(p, map_e + k0 * mstride, nm, SHT_COMP_T | SHT_COMP_E))) return rc;
+        if ((rc = run_leg_a2m(p, SHT_COMP_B))) return rc;
+        if ((rc = run_fft_inv(p, map_b + k0 * mstride, nm, SHT_COMP_B))) return rc;
     }
     return SHT_OK;
 }

@@ -125,9 +125,10 @@ struct LegArgs {
     // (2 doubles a row), spin 2 {alpha, beta, gamma, 0} (4 doubles); TL zero rows
     // follow the last m so that a segment may run past lmax
     const double* coef;
-    int64_t ldx;            // columns of X and A (2 * padded map sets, multiple of 128)
+    int64_t ldx;            // columns of X and A (2 * padded map sets, multiple of 64)
     int lmax, rn, nring, spin;
     int ctiles;             // column tiles
+    int eb;                 // spin-2 alm2map: 0 E and B, 1 E only, 2 B only (the other block skipped)
 };
 
 // Layout change compact alm <-> m-major rows (one spin's components per launch).
@@ -149,6 +150,8 @@ struct AlmArgs {
 };
 hipError_t launch_alm_to_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
 hipError_t launch_alm_from_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
+// base[i*stride + j] = 0 for i < rows, j < len
+hipError_t launch_zero_strided(double* base, int rows, int64_t stride, int64_t len, hipStream_t st);
 
 // Folded m order 0, lmax, 1, lmax-1, ...: work per m falls linearly with m, so any
 // run of consecutive folded indices carries about the same work per index.  Each

@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": SHT_FP64, "fp32": SHT_FP32, "bf16x3": SHT_BF16X3}
 EXPORTS = ["sht_plan_create", "sht_plan_destroy", "sht_plan_set_precision", "sht_plan_set_stream",
            "sht_plan_set_nmaps", "sht_plan_set_chunk", "sht_plan_workspace_bytes", "sht_plan_table_bytes",
            "sht_plan_set_workspace", "sht_alm2map", "sht_map2alm", "sht_map2alm_iter", "sht_plan_sync",
-           "sht_last_error", "sht_plan_set_profiling", "sht_plan_get_profile"]
+           "sht_last_error", "sht_plan_set_profiling", "sht_plan_get_profile", "sht_alm2map_sel",
+           "sht_map2alm_sel", "sht_eb_split"]
 
 STAGES = ["fft_fwd", "fft_inv", "residual", "m2a_spin0", "m2a_spin2", "a2m_spin0", "a2m_spin2", "alm_layout"]
 
@@ -58,6 +59,9 @@ def lib() -> ctypes.CDLL:
         L.sht_alm2map.argtypes = [P, V, V]
         L.sht_map2alm.argtypes = [P, V, V]
         L.sht_map2alm_iter.argtypes = [P, V, V, I, D]
+        L.sht_alm2map_sel.argtypes = [P, I, V, V]
+        L.sht_map2alm_sel.argtypes = [P, I, V, V]
+        L.sht_eb_split.argtypes = [P, V, V, V, V]
         L.sht_plan_sync.argtypes = [P]
         L.sht_last_error.restype = ctypes.c_char_p
         L.sht_plan_set_profiling.argtypes = [P, I]
@@ -72,6 +76,20 @@ def lib() -> ctypes.CDLL:
 def _check(rc: int) -> None:
     if rc != SHT_OK:
         raise ShtError(rc, lib().sht_last_error().decode())
+
+
+COMP_T, COMP_E, COMP_B = 1, 2, 4
+
+
+def comp_mask(comps: str) -> int:
+    """Bit mask of enum sht_comp for a string of component letters ("T", "EB", ...)."""
+    bits = {"T": COMP_T, "E": COMP_E, "B": COMP_B}
+    if not comps or any(c not in bits for c in comps.upper()):
+        raise ValueError(f"components must be letters of 'TEB', got {comps!r}")
+    mask = 0
+    for c in comps.upper():
+        mask |= bits[c]
+    return mask
 
 
 def npix(nside: int) -> int:
@@ -151,6 +169,30 @@ class Plan:
         self._stream(stream)
         _check(lib().sht_map2alm(self._h, self._ptr(maps, self.map_shape(), "maps"), self._ptr(alm, self.alm_shape(), "alm")))
         return alm
+
+    def alm2map_sel(self, comps: str, alm, maps, stream=None):
+        """Backward transform of the components named in comps ("T", "E", "B" or a
+        combination such as "TE"); see sht_alm2map_sel."""
+        self._stream(stream)
+        _check(lib().sht_alm2map_sel(self._h, comp_mask(comps), self._ptr(alm, self.alm_shape(), "alm"),
+                                     self._ptr(maps, self.map_shape(), "maps")))
+        return maps
+
+    def map2alm_sel(self, comps: str, maps, alm, stream=None):
+        """Forward transform of the components named in comps; the others are zeroed."""
+        self._stream(stream)
+        _check(lib().sht_map2alm_sel(self._h, comp_mask(comps), self._ptr(maps, self.map_shape(), "maps"),
+                                     self._ptr(alm, self.alm_shape(), "alm")))
+        return alm
+
+    def eb_split(self, maps, alm, maps_e, maps_b, stream=None):
+        """Pixel-domain E/B separation (spin-2 plans): alm = map2alm(maps),
+        maps_e = alm2map(T, E, 0), maps_b = alm2map(0, 0, B)."""
+        self._stream(stream)
+        shp = self.map_shape()
+        _check(lib().sht_eb_split(self._h, self._ptr(maps, shp, "maps"), self._ptr(alm, self.alm_shape(), "alm"),
+                                  self._ptr(maps_e, shp, "maps_e"), self._ptr(maps_b, shp, "maps_b")))
+        return maps_e, maps_b
 
     def map2alm_iter(self, maps, alm, niter: int, residuals: bool = False, stream=None):
         self._stream(stream)

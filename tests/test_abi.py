@@ -48,6 +48,16 @@ def test_null_plan_calls_fail_cleanly():
     assert L.sht_alm2map(None, None, None) == sht.SHT_ERR_ARG
     assert L.sht_map2alm(None, None, None) == sht.SHT_ERR_ARG
     assert L.sht_map2alm_iter(None, None, None, 1, None) == sht.SHT_ERR_ARG
+    assert L.sht_alm2map_sel(None, sht.COMP_E, None, None) == sht.SHT_ERR_ARG
+    assert L.sht_map2alm_sel(None, sht.COMP_B, None, None) == sht.SHT_ERR_ARG
+    assert L.sht_eb_split(None, None, None, None, None) == sht.SHT_ERR_ARG
     assert L.sht_plan_set_precision(None, 0) == sht.SHT_ERR_ARG
     assert L.sht_plan_destroy(None) == sht.SHT_OK
     assert L.sht_plan_workspace_bytes(None) == 0
+
+
+def test_component_masks():
+    assert sht.comp_mask("T") == 1 and sht.comp_mask("eb") == 6 and sht.comp_mask("TEB") == 7
+    for bad in ("", "X", "TQ"):
+        with pytest.raises(ValueError):
+            sht.comp_mask(bad)

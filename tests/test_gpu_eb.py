@@ -1,0 +1,155 @@
+"""GPU parity of the selective transforms (T / E / B components on their own, the
+separate E and B transforms) and of the pixel-domain E/B separation, through the
+C ABI, against the oracle's compositions (pinned in test_oracle_pins.py).
+
+Bars as in test_gpu_parity.py: FP64 <= 1e-10 relative RMS per map and
+component, FP32 and BF16x3 <= 1e-5.  Components a selection leaves out must be
+exactly zero, and map components a forward selection does not need are not read
+(they hold NaN here).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_10154_amd import synth
+
+from .gpu_util import alm_inputs, from_dev, note, rel_rms, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
+SELS = ["T", "E", "B", "TE", "TB", "EB"]
+CASES = [
+    # nside, lmax, nmaps, chunk
+    (16, 47, 3, None),
+    (11, 32, 4, 3),     # Bluestein equator, 2 chunks, ragged last chunk
+    (24, 71, 2, None),  # aliased rows in the power-of-two and Bluestein ring kernels
+]
+
+
+@pytest.fixture(scope="module")
+def sht():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2208_10154_amd import sht as mod
+    mod.lib()
+    return mod
+
+
+def _maps_in(nside, lmax, nmaps, workload):
+    a, _ = alm_inputs(lmax, nmaps, True, workload=workload)
+    maps = oracle.alm2map_iqu(nside, lmax, a)
+    return maps + synth.white_noise_like(maps, 1e-3, workload=workload)
+
+
+def _map_comps(sel):
+    """Map components a selection produces (I from T, Q and U from E or B)."""
+    return [0] * ("T" in sel) + [1, 2] * ("E" in sel or "B" in sel)
+
+
+@pytest.mark.parametrize("nside,lmax,nmaps,chunk", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_alm2map_selected_components(sht, nside, lmax, nmaps, chunk, prec):
+    import torch
+    a, c = alm_inputs(lmax, nmaps, True, workload=11)
+    p = sht.Plan(nside, lmax, 2, nmaps, precision=prec, chunk=chunk)
+    alm = to_dev(c)
+    for sel in SELS:
+        note(f"alm2map_sel {sel} nside={nside} lmax={lmax} nmaps={nmaps} chunk={chunk} {prec}")
+        ref = oracle.alm2map_sel(nside, lmax, a, sel)
+        maps = torch.full(p.map_shape(), np.nan, dtype=torch.float64, device="cuda")
+        p.alm2map_sel(sel, alm, maps)
+        p.sync()
+        got = from_dev(maps)
+        on = _map_comps(sel)
+        off = [k for k in range(3) if k not in on]
+        assert np.all(got[:, off] == 0), sel
+        err = rel_rms(got[:, on], ref[:, on])
+        assert np.all(err <= TOL[prec]), (sel, err)
+    p.close()
+
+
+@pytest.mark.parametrize("nside,lmax,nmaps,chunk", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_map2alm_selected_components(sht, nside, lmax, nmaps, chunk, prec):
+    import torch
+    maps_np = _maps_in(nside, lmax, nmaps, workload=12)
+    p = sht.Plan(nside, lmax, 2, nmaps, precision=prec, chunk=chunk)
+    for sel in SELS:
+        note(f"map2alm_sel {sel} nside={nside} lmax={lmax} nmaps={nmaps} chunk={chunk} {prec}")
+        ref = oracle.to_compact(oracle.map2alm_sel(nside, lmax, maps_np, sel))
+        x = maps_np.copy()
+        unread = [k for k in range(3) if k not in _map_comps(sel)]
+        x[:, unread] = np.nan
+        alm = torch.full(p.alm_shape(), np.nan, dtype=torch.float64, device="cuda")
+        p.map2alm_sel(sel, to_dev(x), alm)
+        p.sync()
+        got = from_dev(alm)
+        assert np.all(np.isfinite(got)), sel
+        on = [k for k, ch in enumerate("TEB") if ch in sel]
+        off = [k for k in range(3) if k not in on]
+        assert np.all(got[:, off] == 0), sel
+        err = rel_rms(got[:, on], ref[:, on])
+        assert np.all(err <= TOL[prec]), (sel, err)
+    p.close()
+
+
+@pytest.mark.parametrize("nside,lmax,nmaps,chunk", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_eb_split(sht, nside, lmax, nmaps, chunk, prec):
+    import torch
+    note(f"eb_split nside={nside} lmax={lmax} nmaps={nmaps} chunk={chunk} {prec}")
+    maps_np = _maps_in(nside, lmax, nmaps, workload=13)
+    ra, re, rb = oracle.eb_split(nside, lmax, maps_np)
+    p = sht.Plan(nside, lmax, 2, nmaps, precision=prec, chunk=chunk)
+    maps = to_dev(maps_np)
+    alm = torch.full(p.alm_shape(), np.nan, dtype=torch.float64, device="cuda")
+    me = torch.full(p.map_shape(), np.nan, dtype=torch.float64, device="cuda")
+    mb = torch.full(p.map_shape(), np.nan, dtype=torch.float64, device="cuda")
+    p.eb_split(maps, alm, me, mb)
+    full = torch.full(p.map_shape(), np.nan, dtype=torch.float64, device="cuda")
+    p.alm2map(alm, full)
+    p.sync()
+    got_a, got_e, got_b, got_full = (from_dev(t) for t in (alm, me, mb, full))
+    assert np.all(rel_rms(got_a, oracle.to_compact(ra)) <= TOL[prec])
+    assert np.all(got_b[:, 0] == 0)
+    # the syntheses alone, from the coefficients this call produced
+    own = oracle.from_compact(got_a, lmax)
+    assert np.all(rel_rms(got_e, oracle.alm2map_sel(nside, lmax, own, "TE")) <= TOL[prec])
+    assert np.all(rel_rms(got_b[:, 1:], oracle.alm2map_sel(nside, lmax, own, "B")[:, 1:]) <= TOL[prec])
+    # the whole split (an analysis followed by a synthesis): to first order the
+    # relative errors of the two transforms add, so the mixed-precision bar doubles
+    bar2 = TOL[prec] if prec == "fp64" else 2 * TOL[prec]
+    assert np.all(rel_rms(got_e, re) <= bar2)
+    assert np.all(rel_rms(got_b[:, 1:], rb[:, 1:]) <= bar2)
+    # lambda^E + lambda^B = I: the two halves add up to the full synthesis of alm
+    bar = 1e-12 if prec == "fp64" else TOL[prec]
+    assert np.all(rel_rms(got_e + got_b, got_full) <= bar)
+    # in place: map_e may be the input array itself
+    p.eb_split(maps, alm, maps, mb)
+    p.sync()
+    assert np.all(rel_rms(from_dev(maps), got_e) <= 1e-13)
+    p.close()
+
+
+def test_selection_arguments_rejected(sht):
+    import torch
+    p0 = sht.Plan(8, 16, 0, 1)
+    p2 = sht.Plan(8, 16, 2, 1)
+    a0 = torch.zeros(p0.alm_shape(), dtype=torch.float64, device="cuda")
+    m0 = torch.zeros(p0.map_shape(), dtype=torch.float64, device="cuda")
+    a2 = torch.zeros(p2.alm_shape(), dtype=torch.float64, device="cuda")
+    m2 = torch.zeros(p2.map_shape(), dtype=torch.float64, device="cuda")
+    lib = sht.lib()
+    import ctypes
+    for bad in (0, 8, 15):
+        assert lib.sht_alm2map_sel(p2._h, bad, ctypes.c_void_p(a2.data_ptr()), ctypes.c_void_p(m2.data_ptr())) == -1
+    assert lib.sht_map2alm_sel(p0._h, sht.COMP_E, ctypes.c_void_p(m0.data_ptr()), ctypes.c_void_p(a0.data_ptr())) == -1
+    with pytest.raises(sht.ShtError):
+        p0.eb_split(m0, a0, m0.clone(), m0.clone())
+    with pytest.raises(sht.ShtError):
+        p2.eb_split(m2, a2, m2, m2)
+    with pytest.raises(ValueError):
+        p2.alm2map_sel("X", a2, m2)
+    p0.close()
+    p2.close()

@@ -189,6 +189,56 @@ def test_spin2_bruteforce_both_directions(nside):
     np.testing.assert_allclose(B[0], Bb, atol=1e-13)
 
 
+# ----------------------------------------------------------------------------- E/B separation
+def test_eb_split_of_pure_modes():
+    """Pins oracle.eb_split and the selective transforms on the closed-form pure
+    modes (l = 2, m = 0): the polarisation pattern Q = -f(theta), U = 0 is pure E,
+    and Q = 0, U = -f pure B (the maps of test_spin2_closed_form_maps).  The other
+    mode's coefficients vanish to rounding at m = 0 (F- has no m = 0 term) and at
+    every m that is not a multiple of 4 (an axisymmetric map has no such ring
+    coefficient on any HEALPix ring); the rest is quadrature aliasing of the
+    4-pixel polar rings, far below the mode itself.  A split that swapped or mixed
+    the two halves of lambda^{E,B} fails the bounds below by orders of magnitude."""
+    nside, L = 8, 10
+    th, _ = oracle.pixel_angles(nside)
+    f = math.sqrt(15 / (32 * math.pi)) * np.sin(th) ** 2
+    pure_e = np.zeros((1, 3, th.size)); pure_e[0, 1] = -f
+    pure_b = np.zeros((1, 3, th.size)); pure_b[0, 2] = -f
+    exact = np.array([[m == 0 or m % 4 != 0 for m in range(L + 1)]] * (L + 1))
+    for pure, keep, other in ((pure_e, 1, 2), (pure_b, 2, 1)):
+        a, me, mb = oracle.eb_split(nside, L, pure)
+        kept, lost = (me, mb) if keep == 1 else (mb, me)
+        assert np.max(np.abs(a[0, other][exact])) < 1e-15
+        assert abs(a[0, keep, 2, 0] - 1.0) < 2e-3
+        assert np.max(np.abs(lost)) < 1e-3 * np.max(f)
+        assert np.max(np.abs(kept - pure)) < 1e-2 * np.max(f)
+    # the selective forms agree with the split on the same input
+    sel = oracle.map2alm_sel(nside, L, pure_b, "B")
+    assert np.all(sel[:, :2] == 0)
+    np.testing.assert_allclose(sel[:, 2], a[:, 2], atol=1e-15)
+    np.testing.assert_allclose(oracle.alm2map_sel(nside, L, a, "B"), mb, atol=1e-15)
+    np.testing.assert_allclose(oracle.alm2map_sel(nside, L, a, "TE"), me, atol=1e-15)
+
+
+def test_eb_split_swaps_under_45_degree_rotation():
+    """Rotating every polarisation vector by 45 degrees, (Q, U) -> (-U, Q), turns E
+    into B and B into -E exactly (P = Q + iU goes to iP, so the spin +-2
+    coefficients pick up +-i): the E part of the rotated maps is the rotated B
+    part of the originals and vice versa, with I untouched."""
+    nside, L = 4, 11
+    w = synth.white_maps(12 * nside * nside, 2, 3, workload=94)
+    rot = np.stack([w[:, 0], -w[:, 2], w[:, 1]], axis=1)
+    a, me, mb = oracle.eb_split(nside, L, w)
+    ar, mer, mbr = oracle.eb_split(nside, L, rot)
+    R = lambda x: np.stack([-x[:, 2], x[:, 1]], axis=1)
+    np.testing.assert_allclose(mer[:, 1:], R(mb), atol=1e-12)
+    np.testing.assert_allclose(mbr[:, 1:], R(me), atol=1e-12)
+    np.testing.assert_allclose(mer[:, 0], me[:, 0], atol=1e-12)
+    np.testing.assert_allclose(ar[:, 1], -a[:, 2], atol=1e-13)
+    np.testing.assert_allclose(ar[:, 2], a[:, 1], atol=1e-13)
+    np.testing.assert_allclose(me + mb, oracle.alm2map_iqu(nside, L, a), atol=1e-12)
+
+
 # ----------------------------------------------------------------------------- identities
 def _wdot(a, b):
     """sum_l sum_{m>=0} w_m Re(a conj b), w_0 = 1, w_{m>0} = 2."""
