@@ -339,8 +339,9 @@ __device__ __forceinline__ void unfold_store(const FftArgs& a, const double2* bu
     const int col = 4 * (pair0 + sq) + 2 * part;
     const int64_t xstep = (int64_t)dm * a.nring * a.ldx;
     int64_t xi = xidx(a, comp, m0, ring, col);
+    const int mtop = min(a.lmax, a.rings[ring].mcut);
     MWalk w(m0, dm, n, s);
-    for (int mb = m0; mb <= a.lmax; mb += MB * dm) {
+    for (int mb = m0; mb <= mtop; mb += MB * dm) {
         double2 t[MB];
         int jj[MB];
 #pragma unroll
@@ -351,7 +352,7 @@ __device__ __forceinline__ void unfold_store(const FftArgs& a, const double2* bu
         }
 #pragma unroll
         for (int u = 0; u < MB; ++u) {
-            if (mb + u * dm <= a.lmax) {
+            if (mb + u * dm <= mtop) {
                 const int j = jj[u], jn = j ? n - j : 0;
                 const double2 z = buf[P(sq, j, ls)], y = buf[P(sq, jn, ls)];
                 const double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
@@ -385,11 +386,12 @@ __device__ __forceinline__ void fold_load(const FftArgs& a, double2* buf, const 
     const int m0 = (int)threadIdx.x >> (1 + L->lgseq), dm = NT >> (1 + L->lgseq);
     const int col = 4 * (pair0 + sq) + 2 * part;
     const int64_t xstep = (int64_t)dm * a.nring * a.ldx;
-    const int64_t xlast = xidx(a, comp, a.lmax, ring, col);
+    const int mtop = min(a.lmax, a.rings[ring].mcut);  // rows past the ring's cutoff are zero
+    const int64_t xlast = xidx(a, comp, mtop, ring, col);
     int64_t xi = xidx(a, comp, m0, ring, col);
     const double sg = CONJ ? -1.0 : 1.0;
     MWalk w(m0, dm, n, s);
-    for (int mb = m0; mb <= a.lmax; mb += MB * dm) {
+    for (int mb = m0; mb <= mtop; mb += MB * dm) {
         double2 tv[MB], t[MB];
         int jj[MB];
 #pragma unroll
@@ -412,7 +414,7 @@ __device__ __forceinline__ void fold_load(const FftArgs& a, double2* buf, const 
             const double2 c = cmul(ph, tv[u]);  // c_m of this lane's map
             // the map-b lane's term, received by the map-a lane (lanes differ in bit 0)
             const double cbx = __shfl_xor(c.x, 1), cby = __shfl_xor(c.y, 1);
-            if (part == 0 && mm <= a.lmax) {
+            if (part == 0 && mm <= mtop) {
                 const double2 ca = c, cb = make_double2(cbx, cby);
                 double* p1 = reinterpret_cast<double*>(buf + P(sq, jj[u], ls));
                 atomicAdd(p1, ca.x - cb.y);

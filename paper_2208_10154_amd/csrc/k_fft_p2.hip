@@ -273,15 +273,15 @@ __device__ __forceinline__ void fwd_item(const FftArgs& a, const Item it, double
     const double2* zs = lds + sq * C::SEQ;
     XT* X = static_cast<XT*>(a.X) + (int64_t)it.comp * a.xcomp + (int64_t)it.ring * a.ldx + 4 * (it.pair0 + sq) + 2 * part;
     const int64_t mrow = (int64_t)a.nring * a.ldx;
-    const int s = rg.s;
-    for (int m0 = mi; m0 <= a.lmax; m0 += MB * MSTEP) {
+    const int s = rg.s, mtop = min(a.lmax, rg.mcut);
+    for (int m0 = mi; m0 <= mtop; m0 += MB * MSTEP) {
         double2 ph[MB];
 #pragma unroll
         for (int u = 0; u < MB; ++u) ph[u] = tw[((m0 + u * MSTEP) * s) & (2 * N - 1)];
 #pragma unroll
         for (int u = 0; u < MB; ++u) {
             const int m = m0 + u * MSTEP;
-            if (m <= a.lmax) {
+            if (m <= mtop) {
                 const int j = m & (N - 1), jn = (N - j) & (N - 1);
                 const double2 z = zs[j], y = zs[jn];
                 const double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
@@ -311,7 +311,7 @@ __device__ __forceinline__ void inv_item(const FftArgs& a, const Item it, double
     constexpr int MSTEP = C::NTH >> C::LOGS;  // = T
     const RingDev rg = a.rings[it.ring];
     const double2* tw = a.tw + a.lens[rg.len].tw;
-    const int s = rg.s, lmax = a.lmax;
+    const int s = rg.s, lmax = min(a.lmax, rg.mcut);  // rows past the ring's cutoff are zero
 
     // Fold: C_j = sum_{m = j} c_m + sum_{m >= 1, -m = j} conj(c_m) of both maps,
     // Z = C^a + i C^b, into LDS in natural order.  Lanes run over (m, pair) so a
@@ -559,7 +559,8 @@ __device__ __forceinline__ void fwd_item_blue(const FftArgs& a, const Item it, d
     XT* X = static_cast<XT*>(a.X) + (int64_t)it.comp * a.xcomp + (int64_t)it.ring * a.ldx + 4 * (it.pair0 + sq) + 2 * part;
     const int64_t mrow = (int64_t)a.nring * a.ldx;
     MStep ws(mi, MSTEP, n, rg.s);
-    for (int m0 = mi; m0 <= a.lmax; m0 += MB * MSTEP) {
+    const int mtop = min(a.lmax, rg.mcut);
+    for (int m0 = mi; m0 <= mtop; m0 += MB * MSTEP) {
         double2 ph[MB];
         int jj[MB];
 #pragma unroll
@@ -571,7 +572,7 @@ __device__ __forceinline__ void fwd_item_blue(const FftArgs& a, const Item it, d
 #pragma unroll
         for (int q = 0; q < MB; ++q) {
             const int m = m0 + q * MSTEP;
-            if (m <= a.lmax) {
+            if (m <= mtop) {
                 const int j = jj[q], jn = j ? n - j : 0;
                 const double2 z = zs[j], y = zs[jn];
                 const double2 Fa = make_double2(0.5 * (z.x + y.x), 0.5 * (z.y - y.y));
@@ -593,7 +594,7 @@ __device__ __forceinline__ void inv_item_blue(const FftArgs& a, const Item it, d
     constexpr int T = C::T, S = C::S;
     const RingDev rg = a.rings[it.ring];
     const FftLen* L = a.lens + rg.len;
-    const int n = rg.n, lmax = a.lmax;
+    const int n = rg.n, lmax = min(a.lmax, rg.mcut);  // rows past the ring's cutoff are zero
     const double2* twn = a.tw + L->tw;
     const double2* twM = a.tw + L->twm;
     const double2* chirp = a.tw + L->chirp;

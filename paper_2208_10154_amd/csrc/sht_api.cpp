@@ -170,6 +170,7 @@ void build_rings(sht_plan p)
         }
         r.z = (double)z;
         r.sth = (double)sth;
+        r.mcut = p->lmax;  // narrowed by build_mcut once the skip tables exist
         p->rings[i - 1] = r;
     }
 }
@@ -498,6 +499,34 @@ int build_seeds(sht_plan p, SeedSet& S, int spin)
     (void)hipFree(d_startk);
     HIPCHK(e);
     HIPCHK(e2);
+    return SHT_OK;
+}
+
+// Ring optimisation in the FFT mapping (Sec. 3.1 item 10): the Legendre kernels
+// skip ring chunks whose values are all negligible for an m, and map2alm reads a
+// ring chunk c for m only from the first significant chunk of that m on, so rows
+// (m, ring) past mcut(c) = max{m : first significant chunk of m <= c} are never
+// read, and alm2map leaves them exactly zero (negligible values are emitted as
+// zeros).  The ring FFTs therefore unfold and fold only m <= mcut of the ring's
+// chunk, the larger of the two spins' bounds.
+int build_mcut(sht_plan p)
+{
+    const int L = p->lmax, nrc = p->nrc;
+    std::vector<int> mcut(nrc, 0), lsig((size_t)(L + 1) * nrc);
+    for (SeedSet* S : {&p->s0, &p->s2}) {
+        if (!S->lsig.p) continue;
+        HIPCHK(hipMemcpy(lsig.data(), S->lsig.p, lsig.size() * sizeof(int), hipMemcpyDeviceToHost));
+        for (int m = 0; m <= L; ++m) {
+            int c = 0;
+            while (c < nrc && lsig[(size_t)m * nrc + c] > L) ++c;
+            for (int cc = c; cc < nrc; ++cc) mcut[cc] = std::max(mcut[cc], m);
+        }
+    }
+    for (int r = 0; r < p->nring; ++r) {
+        const int rn = std::min(r, p->nring - 1 - r);
+        p->rings[r].mcut = mcut[rn / RCHUNK];
+    }
+    HIPCHK(hipMemcpy(p->d_rings, p->rings.data(), p->rings.size() * sizeof(RingDev), hipMemcpyHostToDevice));
     return SHT_OK;
 }
 
@@ -840,6 +869,7 @@ int sht_plan_create(sht_plan* out, int nside, int lmax, int spin, int nmaps)
     int rc = build_fft(p);
     if (!rc) rc = build_seeds(p, p->s0, 0);
     if (!rc && spin == 2) rc = build_seeds(p, p->s2, 2);
+    if (!rc) rc = build_mcut(p);
     if (!rc) {
         p->chunk = default_chunk(p);
         rc = prep(p);

@@ -68,7 +68,8 @@ struct RingDev {
     int n;                  // pixels
     int s;                  // phase shift: first pixel at phi = pi s / n
     int len;                // index into FftLen table
-    int pad;
+    int mcut;               // highest m whose Legendre rows on this ring are not all
+                            // negligible (ring skip table); the FFT mapping stops there
 };
 
 struct FftItem {
