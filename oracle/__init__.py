@@ -11,7 +11,10 @@ arXiv:2208.10154) and adds, in plain numpy:
 * the conversion between complex (l, m) coefficients and the paper's compact real
   (lmax+1)^2 storage (Appendix A.2, "new storage scheme"), and
 * the "traditional" Jacobi iteration of Sec. 4 / Algorithm 2, written in the pixel
-  domain: a_0 = A m, a_n = a_{n-1} + A (m - Y a_{n-1}).
+  domain: a_0 = A m, a_n = a_{n-1} + A (m - Y a_{n-1}), and the "immediate" mode of
+  Algorithm 3 as a Gauss-Seidel sweep over m, and
+* the selective (T / E / B) transforms and the pixel-domain E/B separation of
+  Sec. 2.3.
 
 Complex coefficient arrays have shape ``[..., lmax+1, lmax+1]`` indexed ``[l, m]``
 (m <= l used, m >= 0 only).  Maps are float64 ``[..., 12 nside^2]`` in RING order.
@@ -243,6 +246,28 @@ def map2alm_iter(nside: int, lmax: int, maps: np.ndarray, niter: int, pol: bool 
         if it == niter:
             break
         a = a + analyse(nside, lmax, r, pol)
+    return a, np.array(res)
+
+
+def map2alm_immediate(nside: int, lmax: int, maps: np.ndarray, niter: int, pol: bool = False):
+    """Sec. 4, Algorithm 3 ("immediate" iteration): the coefficients of each m are
+    updated inside the m-loop, so every later m already sees them.  Read as a
+    Gauss-Seidel sweep over m in increasing order, in the pixel domain: start from
+    a = A m and the residual r = m - Y a; then, per sweep and per m = 0 .. lmax,
+    take the order-m part of A r as the update of a_m and subtract its synthesis
+    from r at once.  Returns (alm, residual_norms) as map2alm_iter does
+    (residual_norms[n] = ||r||_2 after sweep n, n = 0 .. niter)."""
+    a = analyse(nside, lmax, maps, pol)
+    r = maps - synth(nside, lmax, a, pol)
+    res = [float(np.sqrt(np.sum(r * r)))]
+    for _ in range(niter):
+        for m in range(lmax + 1):
+            d = analyse(nside, lmax, r, pol)
+            da = np.zeros_like(d)
+            da[..., :, m] = d[..., :, m]
+            a = a + da
+            r = r - synth(nside, lmax, da, pol)
+        res.append(float(np.sqrt(np.sum(r * r))))
     return a, np.array(res)
 
 

@@ -239,6 +239,73 @@ def test_eb_split_swaps_under_45_degree_rotation():
     np.testing.assert_allclose(me + mb, oracle.alm2map_iqu(nside, L, a), atol=1e-12)
 
 
+# ----------------------------------------------------------------------------- immediate iteration
+def _band_limited(nside, L, nmaps, pol, workload):
+    a = synth.gaussian_alm(L, nmaps, pol, workload) * oracle._tri_mask(L)
+    if pol:
+        a[:, 1:, :2] = 0
+        return a, oracle.alm2map_iqu(nside, L, a)
+    return a, oracle.alm2map(nside, L, a)
+
+
+def test_immediate_iteration_first_mode_and_zero_sweeps():
+    """No sweep is the plain analysis; in the first sweep m = 0 comes first, so
+    its update sees the initial residual exactly as the Jacobi update does, while
+    later m differ (they see the m = 0 correction already)."""
+    nside, L = 8, 23
+    _, maps = _band_limited(nside, L, 2, True, 95)
+    a0, r0 = oracle.map2alm_immediate(nside, L, maps, 0, pol=True)
+    np.testing.assert_allclose(a0, oracle.map2alm_iqu(nside, L, maps), atol=1e-15)
+    aj, _ = oracle.map2alm_iter(nside, L, maps, 1, pol=True)
+    ag, _ = oracle.map2alm_immediate(nside, L, maps, 1, pol=True)
+    np.testing.assert_allclose(ag[..., 0], aj[..., 0], atol=1e-13)
+    assert np.max(np.abs(ag[..., 1:] - aj[..., 1:])) > 1e-6
+
+
+def test_immediate_iteration_beats_traditional_on_band_limited_maps():
+    """The comparison of Sec. 4 (Fig. 3): for maps band limited to lmax < 3 nside,
+    three immediate sweeps leave a smaller coefficient error and residual than
+    three traditional iterations, and the residual falls every sweep."""
+    for nside, pol in ((8, True), (16, False)):
+        L = 3 * nside - 1
+        at, maps = _band_limited(nside, L, 2, pol, 96)
+        aj, rj = oracle.map2alm_iter(nside, L, maps, 3, pol=pol)
+        ag, rg = oracle.map2alm_immediate(nside, L, maps, 3, pol=pol)
+        err = lambda a: np.sqrt(np.sum(np.abs(a - at) ** 2) / np.sum(np.abs(at) ** 2))
+        assert err(ag) < 0.7 * err(aj), (err(ag), err(aj))
+        assert rg[-1] < 0.5 * rj[-1]
+        assert np.all(np.diff(rg) < 0)
+
+
+def test_immediate_iteration_brute_force():
+    """The sweep written out literally for a tiny map: every (l, m) update as a
+    pixel sum with scipy's Y_lm, the residual corrected pixel by pixel after each
+    m (including the a_{l,-m} partner of every m > 0)."""
+    nside, L, niter = 2, 5, 2
+    th, ph = brute.healpix_centres(nside)
+    dsig = 4 * math.pi / th.size
+    at = synth.gaussian_alm(L, 1, False, 97)[0, 0] * oracle._tri_mask(L)
+    t = brute.synth0(nside, at).real
+    a = np.zeros((L + 1, L + 1), dtype=complex)
+    r = t.copy()
+    for l in range(L + 1):
+        for m in range(l + 1):
+            a[l, m] = dsig * np.sum(r * np.conj(brute.y_lm(l, m, th, ph)))
+    for l in range(L + 1):
+        for m in range(l + 1):
+            y = brute.y_lm(l, m, th, ph)
+            r = r - (a[l, m] * y).real * (2 if m else 1)
+    for _ in range(niter):
+        for m in range(L + 1):
+            d = {l: dsig * np.sum(r * np.conj(brute.y_lm(l, m, th, ph))) for l in range(m, L + 1)}
+            for l, v in d.items():
+                a[l, m] += v
+                r = r - (v * brute.y_lm(l, m, th, ph)).real * (2 if m else 1)
+    got, res = oracle.map2alm_immediate(nside, L, t[None], niter)
+    np.testing.assert_allclose(got[0], a, atol=1e-12)
+    assert abs(res[-1] - np.sqrt(np.sum(r * r))) < 1e-12
+
+
 # ----------------------------------------------------------------------------- identities
 def _wdot(a, b):
     """sum_l sum_{m>=0} w_m Re(a conj b), w_0 = 1, w_{m>0} = 2."""
