@@ -358,6 +358,56 @@ def iteration_leg(args):
             "chunk": args.iter_chunk, "noise": "white, 1e-2 of each map's RMS", "by_precision": res}
 
 
+def immediate_leg(args):
+    """Immediate iteration (Sec. 4, Algorithm 3) against the traditional one on the
+    comparison of Fig. 3: maps band limited to lmax = 3 nside - 1 (Gaussian a_lm
+    synthesised in FP64, no noise), nside 512, lmax 1535, `--imm-nmaps` IQU
+    triples in one chunk, N_iter = 3.  Reports seconds per run, the RMS residual
+    after every round and the relative error against the input a_lm for both
+    modes, and the immediate run's stage times."""
+    import torch
+    from paper_2208_10154_amd import sht
+    nside, n, niter = args.nside, args.imm_nmaps, 3
+    L = 3 * nside - 1
+    p = sht.Plan(nside, L, 2, n, chunk=n)
+    alm = torch.empty((n, 3, (L + 1) ** 2), dtype=torch.float64, device="cuda")
+    fill_alm(alm, L, seed=220810154 + 6)
+    maps = torch.empty((n, 3, 12 * nside * nside), dtype=torch.float64, device="cuda")
+    p.alm2map(alm, maps)
+    out = torch.empty_like(alm)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for prec in args.imm_precisions.split(","):
+        p.set_precision(prec)
+        p.map2alm_immediate(maps, out, 1)  # warm-up (schedule, work lists, iteration buffers)
+        torch.cuda.synchronize()
+        r = {}
+        for mode, fn in (("traditional", p.map2alm_iter), ("immediate", p.map2alm_immediate)):
+            p.set_profiling(mode == "immediate")
+            p.profile(reset=True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rr = fn(maps, out, niter, residuals=True)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            prof = p.profile(reset=True)
+            p.set_profiling(False)
+            err = float(((out - alm).norm() / alm.norm()).item())
+            r[mode] = {"s": round(e0.elapsed_time(e1) / 1e3, 3), "residual_rms": [float(f"{x:.6e}") for x in rr],
+                       "rel_err_vs_input_alm": float(f"{err:.4e}")}
+            if mode == "immediate":
+                r[mode]["stages_ms"] = {k: round(v[0], 2) for k, v in prof.items() if v[1]}
+                r[mode]["launches"] = int(sum(v[1] for v in prof.values()))
+        r["residual_ratio_immediate_over_traditional"] = round(r["immediate"]["residual_rms"][-1] /
+                                                               r["traditional"]["residual_rms"][-1], 4)
+        res[prec] = r
+        log(f"immediate {prec}: {r}")
+    p.close()
+    del alm, maps, out
+    torch.cuda.empty_cache()
+    return {"workload": f"healpix_iqu_nside{nside}_lmax{L}_x{n}_bandlimited_iter{niter}", "by_precision": res}
+
+
 def serving(args):
     """Config 5: a seeded mix of requests (nside 64..1024, lmax = 3 nside - 1, T or
     IQU, both directions, FP64 or BF16x3, log-normal map counts) through the
@@ -441,6 +491,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg (config 5)")
     ap.add_argument("--no-iter", action="store_true", help="skip the iteration leg (config 4)")
     ap.add_argument("--no-eb", action="store_true", help="skip the E/B leg")
+    ap.add_argument("--no-imm", action="store_true", help="skip the immediate-iteration leg")
+    ap.add_argument("--imm-nmaps", type=int, default=64, help="IQU triples of the immediate-iteration leg")
+    ap.add_argument("--imm-precisions", default="fp64,bf16x3")
     ap.add_argument("--eb-nmaps", type=int, default=250, help="IQU triples of the E/B leg")
     ap.add_argument("--iter-nside", type=int, default=1024)
     ap.add_argument("--iter-nmaps", type=int, default=200)
@@ -519,6 +572,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_iter:
         line["iteration"] = iteration_leg(args)
+    if not args.no_imm:
+        line["immediate"] = immediate_leg(args)
     if not args.no_serve:
         line["serve"] = serving(args)
     if not args.no_cpu_baseline:

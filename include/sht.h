@@ -116,6 +116,18 @@ int sht_map2alm(sht_plan plan, const double* map, double* alm);
  * synchronises the stream. */
 int sht_map2alm_iter(sht_plan plan, const double* map, double* alm, int niter, double* resid);
 
+/* Iterative forward transform in the "immediate" mode of Sec. 4 / Algorithm 3:
+ * after a_0 = A m, each of the niter >= 0 sweeps updates the coefficients m by m
+ * in increasing m, each update computed from the residual that already holds
+ * the updates of the earlier m (a Gauss-Seidel sweep; the traditional mode of
+ * sht_map2alm_iter is the Jacobi form).  The residual is kept as FP64 ring
+ * spectra; m that share no ring bin run together, in schedule levels built once
+ * per plan, which leaves the result of the sweep unchanged.  resid as for
+ * sht_map2alm_iter (RMS over all pixels after estimate n, n = 0 .. niter; the
+ * call then synchronises the stream).  Same layouts and errors as
+ * sht_map2alm_iter. */
+int sht_map2alm_immediate(sht_plan plan, const double* map, double* alm, int niter, double* resid);
+
 /* Components of the selective transforms (bit mask). */
 enum sht_comp {
     SHT_COMP_T = 1,   /* temperature / intensity: the spin-0 part */

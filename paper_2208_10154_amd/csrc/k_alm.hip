@@ -27,16 +27,17 @@ __device__ __forceinline__ int64_t calm(int L, int l, int m, int part)
     return (int64_t)(L + 1 - m) * (L + 1) + (l - m);
 }
 
-__device__ __forceinline__ void decode(const int* off, int lmax, int C, int g, int& m, int& lt, int& kb)
+__device__ __forceinline__ void decode(const int* off, int lmax, const int* mlist, int nlist, int C, int g, int& m,
+                                       int& lt, int& kb)
 {
-    int lo = 0, hi = lmax + 1;
+    int lo = 0, hi = mlist ? nlist : lmax + 1;
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
         if (off[mid] * C <= g) lo = mid; else hi = mid;
     }
-    m = lo;
-    int r = g - off[m] * C;
-    int nlt = off[m + 1] - off[m];
+    m = mlist ? mlist[lo] : lo;
+    int r = g - off[lo] * C;
+    int nlt = off[lo + 1] - off[lo];
     kb = r / nlt;
     lt = r - kb * nlt;
 }
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
     const int comp = a.comp0 + blockIdx.y;
     const int kind = (a.spin == 2 && comp == 2) ? 1 : 0;
     int m, lt, kb;
-    decode(a.tileoff, a.lmax, a.kblocks, blockIdx.x, m, lt, kb);
+    decode(a.tileoff, a.lmax, a.mlist, a.nlist, a.kblocks, blockIdx.x, m, lt, kb);
     const int L = a.lmax;
     const int lb = lbase(a.spin, m);
     const int l0 = lb + lt * TLB;
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
     const int comp = a.comp0 + blockIdx.y;
     const int kind = (a.spin == 2 && comp == 2) ? 1 : 0;
     int m, lt, kb;
-    decode(a.tileoff, a.lmax, a.kblocks, blockIdx.x, m, lt, kb);
+    decode(a.tileoff, a.lmax, a.mlist, a.nlist, a.kblocks, blockIdx.x, m, lt, kb);
     const int L = a.lmax;
     const int lb = lbase(a.spin, m);
     const int l0 = lb + lt * TLB;
@@ -140,6 +141,37 @@ __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
     }
 }
 
+// Immediate iteration: the map2alm rows of the listed m become the alm2map
+// operand of the update, scale * A, in place.  The parts the compact storage has
+// no slot for (Im of T and E at m = 0, Re of B' = i a_B at m = 0) and the padding
+// maps are zeroed, so the synthesis sees exactly the update the compact alm got.
+// TI: element type written by map2alm; TO: read by alm2map (split-BF16 words
+// for BF16x3, same size as the FP32 rows they replace).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(NT) void k_level_rows(AlmArgs a)
+{
+    const int comp = a.comp0 + blockIdx.y;
+    const int kind = (a.spin == 2 && comp == 2) ? 1 : 0;
+    int m, lt, kb;
+    decode(a.tileoff, a.lmax, a.mlist, a.nlist, a.kblocks, blockIdx.x, m, lt, kb);
+    const int L = a.lmax;
+    const int lb = lbase(a.spin, m);
+    const int l0 = lb + lt * TLB;
+    const int64_t o0 = comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
+    const TI* in = static_cast<const TI*>(a.A) + o0;
+    TO* out = static_cast<TO*>(a.A) + o0;
+    const int drop = (m == 0) ? (kind == 0 ? 1 : 0) : -1;  // part without a compact slot
+    for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+        const int li = e / (2 * TK), c = e % (2 * TK);
+        if (l0 + li > L) continue;
+        const int64_t o = (int64_t)li * a.ldx + c;
+        const bool keep = (c & 1) != drop && kb * TK + (c >> 1) < a.nmaps;
+        const double v = keep ? a.scale * (double)in[o] : 0.0;
+        if constexpr (__is_same(TO, uint32_t)) out[o] = pack_bf16_pair((float)v);
+        else out[o] = (TO)v;
+    }
+}
+
 // Zero len doubles at base + i*stride for i < rows (components a selective
 // transform leaves out); a kernel rather than a memset so the call may be captured.
 __global__ __launch_bounds__(NT) void k_zero_strided(double* base, int rows, int64_t stride, int64_t len)
@@ -158,6 +190,15 @@ hipError_t launch_zero_strided(double* base, int rows, int64_t stride, int64_t l
     const int64_t bx = std::min<int64_t>((len + NT - 1) / NT, 1024);
     const dim3 grid((unsigned)bx, (unsigned)std::min(rows, 1024));
     hipLaunchKernelGGL(k_zero_strided, grid, dim3(NT), 0, st, base, rows, stride, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_rows(const AlmArgs& a, int ncompl, int prec, hipStream_t st)
+{
+    dim3 grid(a.ntiles * a.kblocks, ncompl);
+    if (prec == 0) hipLaunchKernelGGL((k_level_rows<double, double>), grid, dim3(NT), 0, st, a);
+    else if (prec == 2) hipLaunchKernelGGL((k_level_rows<float, uint32_t>), grid, dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL((k_level_rows<float, float>), grid, dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 

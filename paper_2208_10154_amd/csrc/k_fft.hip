@@ -631,6 +631,26 @@ __global__ __launch_bounds__(NT, ELEMS == 16 ? 2 : 4) void k_residual(FftArgs a,
         const bool live = (int)threadIdx.x + q * NT < tot;
         ssa[q] = live ? (Ra.x * Ra.x + Ra.y * Ra.y) / dnn : 0.0;
         ssb[q] = live ? (Rb.x * Rb.x + Rb.y * Rb.y) / dnn : 0.0;
+        if (a.store_res) {
+            // R over F in place: only the thread of the stored bin (2j <= n) writes
+            // (it read that slot itself); the mirror bin's thread may then read R
+            // instead of F, so its values are dropped and the norms count the stored
+            // bins with the Hermitian weight instead.
+            const bool own = live && 2 * j <= n;
+            const double w = own ? ((j == 0 || 2 * j == n) ? 1.0 : 2.0) : 0.0;
+            ssa[q] = w * (Ra.x * Ra.x + Ra.y * Ra.y) / dnn;
+            ssb[q] = w * (Rb.x * Rb.x + Rb.y * Rb.y) / dnn;
+            const int ir = hc_re(n, j), ii = hc_im(n, j);
+            double* f0 = const_cast<double*>(fbase) + (int64_t)k * mstride;
+            if (own && k < a.nmaps) {
+                f0[ir] = Ra.x;
+                if (ii >= 0) f0[ii] = Ra.y;
+            }
+            if (own && k + 1 < a.nmaps) {
+                f0[mstride + ir] = Rb.x;
+                if (ii >= 0) f0[mstride + ii] = Rb.y;
+            }
+        }
         res[q] = make_double2(Ra.x - Rb.y, Ra.y + Rb.x);  // pack as Ra + i Rb
     }
     __syncthreads();

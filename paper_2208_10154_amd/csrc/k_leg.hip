@@ -61,7 +61,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
     __shared__ T lam[2 * BUF];          // [buffer][parity class][ring][row/2]
 
     int m, lt, ct;
-    decode_tiles(a.tiles, a.lmax, a.ctiles, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    decode_tiles(a, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
     const int L = a.lmax, lb = m;
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int lane = threadIdx.x & 63, wave = wave_index();
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
     __shared__ T fpm[2 * BUF];  // [buffer][F+ / F-][parity class][ring][row/2]
 
     int m, lt, ct;
-    decode_tiles(a.tiles, a.lmax, a.ctiles, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    decode_tiles(a, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
     const int L = a.lmax, lb = lbase(2, m);
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int po = (lb - m) & 1;
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
     const int nrt = (a.rn + A0_TR - 1) / A0_TR;
     const int g = xcd_remap(blockIdx.x, gridDim.x);
     const int mi = g / (a.ctiles * nrt);
-    const int m = mfold(mi, a.lmax);
+    const int m = a.mlist ? a.mlist[mi] : mfold(mi, a.lmax);
     const int rem = g - mi * a.ctiles * nrt;
     const int ct = rem / nrt, rt = rem - ct * nrt;
     const int L = a.lmax, lb = m;
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
     const int nrt = (a.rn + A2_TR - 1) / A2_TR;
     const int g = xcd_remap(blockIdx.x, gridDim.x);
     const int mi = g / (a.ctiles * nrt);
-    const int m = mfold(mi, a.lmax);
+    const int m = a.mlist ? a.mlist[mi] : mfold(mi, a.lmax);
     const int rem = g - mi * a.ctiles * nrt;
     const int ct = rem / nrt, rt = rem - ct * nrt;
     const int L = a.lmax, lb = lbase(2, m);
@@ -724,7 +724,7 @@ hipError_t launch_a2m_t(const LegArgs& a, hipStream_t st)
     if (a.spin == 0) {
         const int nu = pick_nu(F64 ? 2 : 4, a.ldx);
         b.ctiles = (int)(a.ldx / (64 * nu));
-        const dim3 grid((a.lmax + 1) * b.ctiles * ((a.rn + A0_TR - 1) / A0_TR));
+        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A0_TR - 1) / A0_TR));
         if constexpr (!F64) {
             if (nu == 4) {
                 hipLaunchKernelGGL((k_a2m_spin0<T, 4>), grid, blk, 0, st, b);
@@ -736,7 +736,7 @@ hipError_t launch_a2m_t(const LegArgs& a, hipStream_t st)
     } else {
         const int nu = pick_nu(2, a.ldx);
         b.ctiles = (int)(a.ldx / (64 * nu));
-        const dim3 grid((a.lmax + 1) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR));
+        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR));
         if (nu == 2) {
             if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2<T, 2, 1>), grid, blk, 0, st, b);
             else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2<T, 2, 2>), grid, blk, 0, st, b);

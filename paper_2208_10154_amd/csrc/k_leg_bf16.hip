@@ -137,7 +137,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
     __shared__ __attribute__((aligned(16))) __bf16 lam[2 * BUF];
 
     int m, lt, ct;
-    decode_tiles(a.tiles, a.lmax, a.ctiles, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    decode_tiles(a, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
     const int L = a.lmax, lb = m;
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int lane = threadIdx.x & 63, wave = wave_index();
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
     __shared__ __attribute__((aligned(16))) __bf16 fpm[2 * BUF];
 
     int m, lt, ct;
-    decode_tiles(a.tiles, a.lmax, a.ctiles, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    decode_tiles(a, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
     const int L = a.lmax, lb = lbase(2, m);
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int po = (lb - m) & 1;
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
     const int nrt = (a.rn + A0_TR - 1) / A0_TR;
     const int g = xcd_remap(blockIdx.x, gridDim.x);
     const int mi = g / (a.ctiles * nrt);
-    const int m = mfold(mi, a.lmax);
+    const int m = a.mlist ? a.mlist[mi] : mfold(mi, a.lmax);
     const int rem = g - mi * a.ctiles * nrt;
     const int ct = rem / nrt, rt = rem - ct * nrt;
     const int L = a.lmax, lb = m;
@@ -612,7 +612,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
     const int nrt = (a.rn + A2_TR - 1) / A2_TR;
     const int g = xcd_remap(blockIdx.x, gridDim.x);
     const int mi = g / (a.ctiles * nrt);
-    const int m = mfold(mi, a.lmax);
+    const int m = a.mlist ? a.mlist[mi] : mfold(mi, a.lmax);
     const int rem = g - mi * a.ctiles * nrt;
     const int ct = rem / nrt, rt = rem - ct * nrt;
     const int L = a.lmax, lb = lbase(2, m);
@@ -812,12 +812,12 @@ hipError_t launch_leg_a2m_bf16(const LegArgs& a, hipStream_t st)
     if (a.spin == 0) {
         const int nu = a.ldx % 128 == 0 ? 2 : 1;
         b.ctiles = (int)(a.ldx / (64 * nu));
-        const dim3 grid((a.lmax + 1) * b.ctiles * ((a.rn + A0_TR - 1) / A0_TR));
+        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A0_TR - 1) / A0_TR));
         if (nu == 2) hipLaunchKernelGGL((k_a2m_spin0_bf<2>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_a2m_spin0_bf<1>), grid, blk, 0, st, b);
     } else {
         b.ctiles = (int)(a.ldx / 64);
-        const dim3 grid((a.lmax + 1) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR));
+        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR));
         if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2_bf<1, 1>), grid, blk, 0, st, b);
         else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2_bf<1, 2>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_a2m_spin2_bf<1, 0>), grid, blk, 0, st, b);

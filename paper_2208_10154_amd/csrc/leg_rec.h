@@ -222,19 +222,24 @@ __device__ __forceinline__ T* aptr(const LegArgs& a, int comp)
 
 // m2a work decode: logical g -> (m, lt, ct); off[i] = l tiles of the first i m in
 // folded order.
-__device__ __forceinline__ void decode_tiles(const int* off, int lmax, int C, int g, int& m, int& lt, int& ct)
+__device__ __forceinline__ void decode_tiles(const LegArgs& a, int g, int& m, int& lt, int& ct)
 {
-    int lo = 0, hi = lmax + 1;
+    const int* off = a.tiles;
+    const int C = a.ctiles;
+    int lo = 0, hi = a.mlist ? a.nlist : a.lmax + 1;
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
         if (off[mid] * C <= g) lo = mid; else hi = mid;
     }
-    m = mfold(lo, lmax);
+    m = a.mlist ? a.mlist[lo] : mfold(lo, a.lmax);
     int r = g - off[lo] * C;
     int nlt = off[lo + 1] - off[lo];
     ct = r / nlt;
     lt = r - ct * nlt;
 }
+
+// m values an alm2map launch covers (all, or the listed ones)
+__host__ __device__ inline int nm_rows(const LegArgs& a) { return a.mlist ? a.nlist : a.lmax + 1; }
 
 // first ring chunk whose significance bound reaches an l <= lend
 __device__ __forceinline__ int first_chunk(const LegArgs& a, int m, int nchunk, int lend)

@@ -89,6 +89,16 @@ struct sht_plan_s {
     double* norms = nullptr;
     size_t table_bytes = 0;
 
+    // ring skip bound per m (first ring chunk where either spin's Legendre values
+    // of m are significant), and the immediate-iteration schedule built from it
+    std::vector<int> cmin;
+    struct Levels {
+        bool built = false;
+        std::vector<int> start, len;           // per level: first entry in mlist, entries
+        std::vector<int> ntiles0, ntiles2;     // per level: l tiles of the listed m per spin
+        Dev mlist, pref0, pref2, cmin;         // device: m per entry; per-level tile prefix sums
+    } lev;
+
     // optional per-stage profiling
     bool profiling = false;
     struct Rec { int stage; hipEvent_t a, b; };
@@ -513,6 +523,7 @@ int build_mcut(sht_plan p)
 {
     const int L = p->lmax, nrc = p->nrc;
     std::vector<int> mcut(nrc, 0), lsig((size_t)(L + 1) * nrc);
+    p->cmin.assign(L + 1, nrc);
     for (SeedSet* S : {&p->s0, &p->s2}) {
         if (!S->lsig.p) continue;
         HIPCHK(hipMemcpy(lsig.data(), S->lsig.p, lsig.size() * sizeof(int), hipMemcpyDeviceToHost));
@@ -520,6 +531,7 @@ int build_mcut(sht_plan p)
             int c = 0;
             while (c < nrc && lsig[(size_t)m * nrc + c] > L) ++c;
             for (int cc = c; cc < nrc; ++cc) mcut[cc] = std::max(mcut[cc], m);
+            p->cmin[m] = std::min(p->cmin[m], c);
         }
     }
     for (int r = 0; r < p->nring; ++r) {
@@ -800,6 +812,116 @@ int run_m2a(sht_plan p, double* alm, int nm, int accumulate, int sel = SHT_COMP_
     return SHT_OK;
 }
 
+// Schedule of the immediate iteration (Sec. 4, Algorithm 3): a Gauss-Seidel
+// sweep over m in increasing order.  The update of m changes the residual only in
+// bins m mod n and -m mod n of the rings where m carries data, and the analysis
+// of m reads only those bins, so m depends on exactly the earlier m that share
+// such a bin on such a ring.  Level(m) = 1 + the highest level among them: the m
+// of one level are independent and run together, and running the levels in
+// order gives the sweep's result (up to the order of floating-point additions).
+int build_levels(sht_plan p)
+{
+    auto& V = p->lev;
+    if (V.built) return SHT_OK;
+    const int L = p->lmax, rn = p->rn;
+    std::vector<int64_t> off(rn + 1, 0);  // per north ring: slots for bins 0 .. n/2
+    for (int r = 0; r < rn; ++r) off[r + 1] = off[r] + p->rings[r].n / 2 + 1;
+    std::vector<int> last(off[rn], 0), level(L + 1, 0);
+    int depth = 0;
+    for (int m = 0; m <= L; ++m) {
+        const int r0 = std::min(rn, p->cmin[m] * RCHUNK);
+        int lv = 0;
+        for (int r = r0; r < rn; ++r) {
+            const int n = p->rings[r].n, j = m % n;
+            lv = std::max(lv, last[off[r] + std::min(j, n - j)]);
+        }
+        level[m] = ++lv;
+        depth = std::max(depth, lv);
+        for (int r = r0; r < rn; ++r) {
+            const int n = p->rings[r].n, j = m % n;
+            last[off[r] + std::min(j, n - j)] = lv;
+        }
+    }
+    std::vector<std::vector<int>> by(depth);
+    for (int m = 0; m <= L; ++m) by[level[m] - 1].push_back(m);
+    std::vector<int> mlist, pref0, pref2;
+    auto ntl = [&](int spin, int m) { const int lb = lbase(spin, m); return lb > L ? 0 : (L - lb + TL) / TL; };
+    for (int d = 0; d < depth; ++d) {
+        V.start.push_back((int)mlist.size());
+        V.len.push_back((int)by[d].size());
+        int t0 = 0, t2 = 0;
+        pref0.push_back(0);
+        pref2.push_back(0);
+        for (int m : by[d]) {
+            mlist.push_back(m);
+            pref0.push_back(t0 += ntl(0, m));
+            pref2.push_back(t2 += ntl(2, m));
+        }
+        V.ntiles0.push_back(t0);
+        V.ntiles2.push_back(t2);
+    }
+    int rc;
+    if ((rc = upload(p, V.mlist, mlist))) return rc;
+    if ((rc = upload(p, V.pref0, pref0))) return rc;
+    if ((rc = upload(p, V.pref2, pref2))) return rc;
+    if ((rc = upload(p, V.cmin, p->cmin))) return rc;
+    V.built = true;
+    return SHT_OK;
+}
+
+// One level of an immediate sweep on the chunk's residual spectra (in p->F):
+// unfold R for the listed m, analyse, add dsigma times the result to alm, turn
+// the rows into the synthesis operand of the update, synthesise, fold back.
+int run_level(sht_plan p, double* alm, int nm, int d)
+{
+    auto& V = p->lev;
+    const int* ml = (const int*)V.mlist.p + V.start[d];
+    const int nl = V.len[d];
+    const double dsig = 4.0 * M_PI / (double)p->npix;
+    FftArgs f = fft_args(p, nm);
+    f.F = p->F;
+    {
+        StageTimer t(p, SHT_STAGE_RESIDUAL);
+        HIPCHK(launch_level_unfold(f, ml, nl, (const int*)V.cmin.p, p->ncomp, p->stream));
+    }
+    for (int spin : {0, 2}) {
+        if (spin == 2 && p->spin != 2) break;
+        SeedSet& S = spin == 0 ? p->s0 : p->s2;
+        const int* pref = (const int*)(spin == 0 ? V.pref0.p : V.pref2.p) + V.start[d] + d;
+        const int nt = spin == 0 ? V.ntiles0[d] : V.ntiles2[d];
+        LegArgs a = leg_args(p, S);
+        a.mlist = ml;
+        a.nlist = nl;
+        a.tiles = pref;
+        a.ntiles = nt;
+        {
+            StageTimer t(p, spin == 0 ? SHT_STAGE_M2A_SPIN0 : SHT_STAGE_M2A_SPIN2);
+            HIPCHK(launch_leg_m2a(a, p->prec, p->stream));
+        }
+        {
+            StageTimer t(p, SHT_STAGE_ALM_LAYOUT);
+            AlmArgs b = alm_args(p, S, nm);
+            b.mlist = ml;
+            b.nlist = nl;
+            b.tileoff = pref;
+            b.ntiles = nt;
+            b.alm_out = alm;
+            b.scale = dsig;
+            b.accumulate = 1;
+            const int ncompl = spin == 0 ? 1 : 2;
+            HIPCHK(launch_alm_from_mmajor(b, ncompl, p->prec, p->stream));
+            HIPCHK(launch_level_rows(b, ncompl, p->prec, p->stream));
+        }
+        {
+            StageTimer t(p, spin == 0 ? SHT_STAGE_A2M_SPIN0 : SHT_STAGE_A2M_SPIN2);
+            HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
+        }
+    }
+    StageTimer t(p, SHT_STAGE_RESIDUAL);
+    HIPCHK(launch_level_fold(f, ml, nl, (const int*)V.cmin.p, p->ncomp, p->stream));
+    return SHT_OK;
+}
+
 int check_ready(sht_plan p)
 {
     if (!p) return fail(SHT_ERR_ARG, "null plan");
@@ -1068,6 +1190,71 @@ int sht_map2alm_iter(sht_plan p, const double* map, double* alm, int niter, doub
             }
             if (it <= niter)
                 if ((rc = run_m2a(p, a, nm, 1))) return rc;
+        }
+    }
+    if (resid) {
+        double cnt = (double)p->nmaps * p->ncomp * (double)p->npix;
+        for (int n = 0; n <= niter; ++n) resid[n] = std::sqrt(sums[n] / cnt);
+    }
+    return SHT_OK;
+}
+
+int sht_map2alm_immediate(sht_plan p, const double* map, double* alm, int niter, double* resid)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
+    if (niter < 0) return fail(SHT_ERR_ARG, "niter must be >= 0");
+    if ((rc = prep(p))) return rc;
+    if ((rc = ensure_iter_buffers(p))) return rc;
+    if ((rc = build_levels(p))) return rc;
+    const int64_t astride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
+    const int64_t mstride = (int64_t)p->ncomp * p->npix;
+    const int depth = (int)p->lev.len.size();
+    std::vector<double> sums(niter + 1, 0.0), hn;
+    auto collect = [&](int n, int nm) -> int {
+        hn.resize((size_t)nm * p->ncomp);
+        HIPCHK(hipMemcpyAsync(hn.data(), p->norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        for (double v : hn) sums[n] += v;
+        return SHT_OK;
+    };
+    for (int k0 = 0; k0 < p->nmaps; k0 += p->chunk) {
+        int nm = std::min(p->chunk, p->nmaps - k0);
+        if ((rc = use_width(p, nm))) return rc;
+        double* a = alm + k0 * astride;
+        FftArgs f = fft_args(p, nm);
+        f.maps_in = map + k0 * mstride;
+        f.F = p->F;
+        {
+            StageTimer t(p, SHT_STAGE_FFT_FWD);
+            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+        }
+        if ((rc = run_m2a(p, a, nm, 0))) return rc;
+        if (niter == 0 && !resid) continue;
+        // residual spectra of the first estimate, R = F - n C, over F
+        if ((rc = run_a2m(p, a, nm))) return rc;
+        FftArgs r = fft_args(p, nm);
+        r.F = p->F;
+        r.store_res = 1;
+        r.norms = resid ? p->norms : nullptr;
+        if (resid) HIPCHK(hipMemsetAsync(p->norms, 0, (size_t)nm * p->ncomp * sizeof(double), p->stream));
+        {
+            StageTimer t(p, SHT_STAGE_RESIDUAL);
+            HIPCHK(launch_residual(r, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
+        }
+        if (resid && (rc = collect(0, nm))) return rc;
+        for (int it = 1; it <= niter; ++it) {
+            for (int d = 0; d < depth; ++d)
+                if ((rc = run_level(p, a, nm, d))) return rc;
+            if (resid) {
+                HIPCHK(hipMemsetAsync(p->norms, 0, (size_t)nm * p->ncomp * sizeof(double), p->stream));
+                FftArgs q = fft_args(p, nm);
+                q.F = p->F;
+                q.norms = p->norms;
+                HIPCHK(launch_hc_norms(q, p->ncomp, p->stream));
+                if ((rc = collect(it, nm))) return rc;
+            }
         }
     }
     if (resid) {

@@ -102,6 +102,7 @@ struct FftArgs {
     int64_t xcomp;          // element stride between the X arrays of consecutive components
     int x32;                // X stored as float
     int iteration_sub;      // K_RES: subtract N*C from F into X
+    int store_res;          // K_RES: write the residual spectrum back over F (halfcomplex)
 };
 
 struct LegArgs {
@@ -130,6 +131,11 @@ struct LegArgs {
     int lmax, rn, nring, spin;
     int ctiles;             // column tiles
     int eb;                 // spin-2 alm2map: 0 E and B, 1 E only, 2 B only (the other block skipped)
+    // optional list of m values to transform instead of all m (immediate-mode
+    // iteration); tiles then holds the prefix sums over the list entries and
+    // ntiles their total
+    const int* mlist;
+    int nlist;
 };
 
 // Layout change compact alm <-> m-major rows (one spin's components per launch).
@@ -148,11 +154,23 @@ struct AlmArgs {
     int comp0;              // first component of the launch (blockIdx.y adds)
     double scale;           // from m-major: alm = scale * A
     int accumulate;         // from m-major: alm += scale * A
+    const int* mlist;       // optional m list (tileoff then over the list entries, ntiles its total)
+    int nlist;
 };
 hipError_t launch_alm_to_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
 hipError_t launch_alm_from_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
 // base[i*stride + j] = 0 for i < rows, j < len
 hipError_t launch_zero_strided(double* base, int rows, int64_t stride, int64_t len, hipStream_t st);
+// immediate iteration: A rows of the listed m (m2a output) -> scale * rows in the
+// alm2map operand format, with the parts the compact storage lacks (m = 0) zeroed
+hipError_t launch_level_rows(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
+
+// immediate iteration, Fourier side (k_iter.hip).  F holds the residual spectra
+// R (halfcomplex per ring, [map-set][comp][npix]); cmin[m] is the first ring chunk
+// where some Legendre value of m is significant (rings before it carry no data for m).
+hipError_t launch_level_unfold(const FftArgs& a, const int* mlist, int nlist, const int* cmin, int ncompl, hipStream_t st);
+hipError_t launch_level_fold(const FftArgs& a, const int* mlist, int nlist, const int* cmin, int ncompl, hipStream_t st);
+hipError_t launch_hc_norms(const FftArgs& a, int ncompl, hipStream_t st);
 
 // Folded m order 0, lmax, 1, lmax-1, ...: work per m falls linearly with m, so any
 // run of consecutive folded indices carries about the same work per index.  Each

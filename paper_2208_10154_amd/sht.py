@@ -24,7 +24,7 @@ EXPORTS = ["sht_plan_create", "sht_plan_destroy", "sht_plan_set_precision", "sht
            "sht_plan_set_nmaps", "sht_plan_set_chunk", "sht_plan_workspace_bytes", "sht_plan_table_bytes",
            "sht_plan_set_workspace", "sht_alm2map", "sht_map2alm", "sht_map2alm_iter", "sht_plan_sync",
            "sht_last_error", "sht_plan_set_profiling", "sht_plan_get_profile", "sht_alm2map_sel",
-           "sht_map2alm_sel", "sht_eb_split"]
+           "sht_map2alm_sel", "sht_eb_split", "sht_map2alm_immediate"]
 
 STAGES = ["fft_fwd", "fft_inv", "residual", "m2a_spin0", "m2a_spin2", "a2m_spin0", "a2m_spin2", "alm_layout"]
 
@@ -62,6 +62,7 @@ def lib() -> ctypes.CDLL:
         L.sht_alm2map_sel.argtypes = [P, I, V, V]
         L.sht_map2alm_sel.argtypes = [P, I, V, V]
         L.sht_eb_split.argtypes = [P, V, V, V, V]
+        L.sht_map2alm_immediate.argtypes = [P, V, V, I, D]
         L.sht_plan_sync.argtypes = [P]
         L.sht_last_error.restype = ctypes.c_char_p
         L.sht_plan_set_profiling.argtypes = [P, I]
@@ -200,6 +201,15 @@ class Plan:
         _check(lib().sht_map2alm_iter(self._h, self._ptr(maps, self.map_shape(), "maps"),
                                       self._ptr(alm, self.alm_shape(), "alm"), int(niter),
                                       ctypes.cast(res, ctypes.POINTER(ctypes.c_double)) if res is not None else None))
+        return list(res) if res is not None else None
+
+    def map2alm_immediate(self, maps, alm, niter: int, residuals: bool = False, stream=None):
+        """Immediate-mode iteration (Gauss-Seidel sweeps over m); see sht_map2alm_immediate."""
+        self._stream(stream)
+        res = (ctypes.c_double * (niter + 1))() if residuals else None
+        _check(lib().sht_map2alm_immediate(self._h, self._ptr(maps, self.map_shape(), "maps"),
+                                           self._ptr(alm, self.alm_shape(), "alm"), int(niter),
+                                           ctypes.cast(res, ctypes.POINTER(ctypes.c_double)) if res is not None else None))
         return list(res) if res is not None else None
 
     def set_profiling(self, enable: bool) -> None:
