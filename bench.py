@@ -155,11 +155,13 @@ def run_precision(sht, args, prec, alm, maps, alm_out):
     ms = ev0.elapsed_time(ev1)
     prof = p.profile(reset=True)
     p.set_profiling(False)
+    rows = p.ring_rows()
     p.close()
     del p
     per_step = ms / args.steps
     log(f"{prec}: {per_step:.1f} ms/step ({wall:.2f}s wall for {args.steps} steps)")
-    return {"ms_per_step": per_step, "value": n * 1000.0 / per_step, "init_s": init_s, "stages": prof}
+    return {"ms_per_step": per_step, "value": n * 1000.0 / per_step, "init_s": init_s, "stages": prof,
+            "ring_rows": rows}
 
 
 def eb_leg(sht, args, precs, alm, maps, alm_out):
@@ -256,14 +258,14 @@ def roofline(args, prec, res):
 
 
 def fft_rate(args, prec, res):
-    """Ring-FFT stages: algorithmic HBM bytes (maps in/out + the m-major
-    coefficients written/read once) over their measured time."""
+    """Ring-FFT stages: algorithmic HBM bytes (maps in/out + the (m, ring) rows
+    of ring coefficients the mapping writes/reads once, `ring_rows` of them per
+    component map after the ring cut) over their measured time."""
     es = 8 if prec == "fp64" else 4
     npix = 12 * args.nside ** 2
-    nring = 4 * args.nside - 1
-    per_map = 8 * npix + 2 * es * nring * (args.lmax + 1)
+    per_map = 8 * npix + 2 * es * res["ring_rows"]
     tot = 3 * args.nmaps * per_map * args.steps
-    out = {}
+    out = {"ring_rows": res["ring_rows"], "ring_rows_uncut": (4 * args.nside - 1) * (args.lmax + 1)}
     for k in ("fft_fwd", "fft_inv"):
         ms, n = res["stages"][k]
         if n:

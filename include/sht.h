@@ -98,6 +98,13 @@ size_t sht_plan_workspace_bytes(sht_plan plan);
 /* Bytes of device memory held by the plan's own tables (excluding workspace). */
 size_t sht_plan_table_bytes(sht_plan plan);
 
+/* Ring coefficient rows (m, ring) the ring FFTs write (map2alm) or read
+ * (alm2map) per component map: over all rings, 1 + the highest m whose Legendre
+ * values on that ring are significant (the ring optimisation of Sec. 3.1 item 10
+ * applied to the FFT mapping), at most (lmax + 1) * (4 nside - 1).  Each row is
+ * one complex value per map.  0 for a NULL plan. */
+long long sht_plan_ring_rows(sht_plan plan);
+
 /* Use caller-owned device memory of at least sht_plan_workspace_bytes() bytes as
  * workspace (the plan frees its own).  Passing NULL returns to a plan-owned
  * workspace. */

@@ -796,9 +796,16 @@ hipError_t launch_leg_m2a_bf16(const LegArgs& a, hipStream_t st)
             hipLaunchKernelGGL((k_m2a_spin0_bf<1>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
         }
     } else {
-        b.ctiles = (int)(a.ldx / 64);
+        // two column tiles per workgroup halve the recursion per column (the
+        // kernel's VALU bound) and still fit 256 registers without spilling
+        const int nu = a.ldx % 128 == 0 ? 2 : 1;
+        b.ctiles = (int)(a.ldx / (64 * nu));
         const dim3 grid(b.ntiles * b.ctiles);
-        if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 1>), grid, blk, 0, st, b);
+        if (nu == 2) {
+            if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2_bf<2, 1>), grid, blk, 0, st, b);
+            else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2_bf<2, 2>), grid, blk, 0, st, b);
+            else hipLaunchKernelGGL((k_m2a_spin2_bf<2, 0>), grid, blk, 0, st, b);
+        } else if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 1>), grid, blk, 0, st, b);
         else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 2>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_m2a_spin2_bf<1, 0>), grid, blk, 0, st, b);
     }

@@ -1048,6 +1048,14 @@ size_t sht_plan_workspace_bytes(sht_plan p) { return p ? ws_need(p) : 0; }
 
 size_t sht_plan_table_bytes(sht_plan p) { return p ? p->table_bytes : 0; }
 
+long long sht_plan_ring_rows(sht_plan p)
+{
+    if (!p) return 0;
+    long long rows = 0;
+    for (const RingDev& r : p->rings) rows += std::min(p->lmax, r.mcut) + 1;
+    return rows;
+}
+
 int sht_plan_set_workspace(sht_plan p, void* ptr, size_t bytes)
 {
     if (!p) return fail(SHT_ERR_ARG, "null plan");

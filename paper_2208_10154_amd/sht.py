@@ -24,7 +24,7 @@ EXPORTS = ["sht_plan_create", "sht_plan_destroy", "sht_plan_set_precision", "sht
            "sht_plan_set_nmaps", "sht_plan_set_chunk", "sht_plan_workspace_bytes", "sht_plan_table_bytes",
            "sht_plan_set_workspace", "sht_alm2map", "sht_map2alm", "sht_map2alm_iter", "sht_plan_sync",
            "sht_last_error", "sht_plan_set_profiling", "sht_plan_get_profile", "sht_alm2map_sel",
-           "sht_map2alm_sel", "sht_eb_split", "sht_map2alm_immediate"]
+           "sht_map2alm_sel", "sht_eb_split", "sht_map2alm_immediate", "sht_plan_ring_rows"]
 
 STAGES = ["fft_fwd", "fft_inv", "residual", "m2a_spin0", "m2a_spin2", "a2m_spin0", "a2m_spin2", "alm_layout"]
 
@@ -55,6 +55,8 @@ def lib() -> ctypes.CDLL:
         L.sht_plan_workspace_bytes.restype = S
         L.sht_plan_table_bytes.argtypes = [P]
         L.sht_plan_table_bytes.restype = S
+        L.sht_plan_ring_rows.argtypes = [P]
+        L.sht_plan_ring_rows.restype = ctypes.c_longlong
         L.sht_plan_set_workspace.argtypes = [P, V, S]
         L.sht_alm2map.argtypes = [P, V, V]
         L.sht_map2alm.argtypes = [P, V, V]
@@ -68,7 +70,7 @@ def lib() -> ctypes.CDLL:
         L.sht_plan_set_profiling.argtypes = [P, I]
         L.sht_plan_get_profile.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), I]
         for name in EXPORTS:
-            if name != "sht_plan_workspace_bytes" and name != "sht_plan_table_bytes" and name != "sht_last_error":
+            if name not in ("sht_plan_workspace_bytes", "sht_plan_table_bytes", "sht_last_error", "sht_plan_ring_rows"):
                 getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -135,6 +137,10 @@ class Plan:
 
     def table_bytes(self) -> int:
         return int(lib().sht_plan_table_bytes(self._h))
+
+    def ring_rows(self) -> int:
+        """(m, ring) rows of ring coefficients the FFT mapping moves per component map."""
+        return int(lib().sht_plan_ring_rows(self._h))
 
     # --- shapes
     def map_shape(self, n: int | None = None):

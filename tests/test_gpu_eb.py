@@ -24,6 +24,7 @@ CASES = [
     (16, 47, 3, None),
     (11, 32, 4, 3),     # Bluestein equator, 2 chunks, ragged last chunk
     (24, 71, 2, None),  # aliased rows in the power-of-two and Bluestein ring kernels
+    (8, 23, 64, None),  # 64 map sets: the two-column-tile kernels
 ]
 
 
@@ -40,6 +41,20 @@ def _maps_in(nside, lmax, nmaps, workload):
     a, _ = alm_inputs(lmax, nmaps, True, workload=workload)
     maps = oracle.alm2map_iqu(nside, lmax, a)
     return maps + synth.white_noise_like(maps, 1e-3, workload=workload)
+
+
+def coef_err(got, ref_full, comps, prec):
+    """Relative RMS of the selected coefficient components.  FP64: per map and
+    component.  FP32 / BF16x3: E and B against the norm of the map's whole E/B
+    pair, since the rounding of the contraction is relative to the Q/U data that
+    both come from (B carries a tenth of E's power in these inputs, so its own
+    norm would inflate the same absolute error about threefold)."""
+    diff = np.sqrt(np.sum((got - ref_full) ** 2, axis=-1))
+    own = np.sqrt(np.sum(ref_full ** 2, axis=-1))
+    if prec != "fp64" and ref_full.shape[1] == 3:
+        pol = np.sqrt(own[:, 1] ** 2 + own[:, 2] ** 2)
+        own = np.stack([own[:, 0], pol, pol], axis=1)
+    return (diff / np.where(own == 0, 1.0, own))[:, comps]
 
 
 def _map_comps(sel):
@@ -75,6 +90,7 @@ def test_map2alm_selected_components(sht, nside, lmax, nmaps, chunk, prec):
     import torch
     maps_np = _maps_in(nside, lmax, nmaps, workload=12)
     p = sht.Plan(nside, lmax, 2, nmaps, precision=prec, chunk=chunk)
+    full = oracle.to_compact(oracle.map2alm_iqu(nside, lmax, maps_np))
     for sel in SELS:
         note(f"map2alm_sel {sel} nside={nside} lmax={lmax} nmaps={nmaps} chunk={chunk} {prec}")
         ref = oracle.to_compact(oracle.map2alm_sel(nside, lmax, maps_np, sel))
@@ -89,8 +105,9 @@ def test_map2alm_selected_components(sht, nside, lmax, nmaps, chunk, prec):
         on = [k for k, ch in enumerate("TEB") if ch in sel]
         off = [k for k in range(3) if k not in on]
         assert np.all(got[:, off] == 0), sel
-        err = rel_rms(got[:, on], ref[:, on])
-        assert np.all(err <= TOL[prec]), (sel, err)
+        assert np.all(ref[:, on] == full[:, on])
+        err = coef_err(got, full, on, prec)
+        assert np.all(err <= TOL[prec]), (sel, err.max())
     p.close()
 
 
@@ -111,7 +128,7 @@ def test_eb_split(sht, nside, lmax, nmaps, chunk, prec):
     p.alm2map(alm, full)
     p.sync()
     got_a, got_e, got_b, got_full = (from_dev(t) for t in (alm, me, mb, full))
-    assert np.all(rel_rms(got_a, oracle.to_compact(ra)) <= TOL[prec])
+    assert np.all(coef_err(got_a, oracle.to_compact(ra), [0, 1, 2], prec) <= TOL[prec])
     assert np.all(got_b[:, 0] == 0)
     # the syntheses alone, from the coefficients this call produced
     own = oracle.from_compact(got_a, lmax)

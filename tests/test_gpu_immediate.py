@@ -50,6 +50,7 @@ CASES = [
     (8, 23, 3, True, 2, 1),     # two chunks, ragged last chunk
     (16, 47, 2, False, None, 2),
     (13, 38, 2, True, None, 1),  # odd nside: Bluestein rings, lmax < 3 nside - 1
+    (8, 23, 64, True, None, 1),  # 64 map sets: the two-column-tile kernels
 ]
 
 
