@@ -148,8 +148,8 @@ enum sht_comp {
  * synthesis of the selected ones; a map component with nothing selected (I when
  * T is left out, Q and U when E and B are) is written as zero.  With E or B alone
  * the spin-2 contraction keeps one half of the 0/1 diagonal selector lambda^{E,B}
- * of Sec. 2.3 and does half of its products (the separate E / B transforms of
- * Sec. 3.1, "support forward and backward transforms of E and B separately").
+ * of Sec. 2.3 and does half of its products (Sec. 3.1 asks for E and B to be
+ * transformable on their own, in both directions).
  * comps: nonzero mask of enum sht_comp; a spin-0 plan accepts only SHT_COMP_T.
  * SHT_ERR_ARG otherwise.  sht_alm2map is this call with every component. */
 int sht_alm2map_sel(sht_plan plan, int comps, const double* alm, double* map);
