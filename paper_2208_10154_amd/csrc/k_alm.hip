@@ -146,7 +146,8 @@ __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
 // no slot for (Im of T and E at m = 0, Re of B' = i a_B at m = 0) and the padding
 // maps are zeroed, so the synthesis sees exactly the update the compact alm got.
 // TI: element type written by map2alm; TO: read by alm2map (split-BF16 words
-// for BF16x3, same size as the FP32 rows they replace).
+// for BF16x3, same size as the FP32 rows they replace).  scale = 0 clears the
+// rows without reading them (before a split map2alm adds into them).
 template <typename TI, typename TO>
 __global__ __launch_bounds__(NT) void k_level_rows(AlmArgs a)
 {
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(NT) void k_level_rows(AlmArgs a)
         if (l0 + li > L) continue;
         const int64_t o = (int64_t)li * a.ldx + c;
         const bool keep = (c & 1) != drop && kb * TK + (c >> 1) < a.nmaps;
-        const double v = keep ? a.scale * (double)in[o] : 0.0;
+        const double v = (keep && a.scale != 0.0) ? a.scale * (double)in[o] : 0.0;
         if constexpr (__is_same(TO, uint32_t)) out[o] = pack_bf16_pair((float)v);
         else out[o] = (TO)v;
     }

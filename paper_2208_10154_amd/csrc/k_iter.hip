@@ -105,6 +105,20 @@ __global__ __launch_bounds__(NT) void k_level_fold(FftArgs a, const int* mlist, 
     }
 }
 
+// clear the X rows of the listed m before a split alm2map adds into them
+template <typename XT>
+__global__ __launch_bounds__(NT) void k_level_zero(FftArgs a, const int* mlist)
+{
+    const int i = blockIdx.x / a.nring;
+    const int ring = blockIdx.x - i * a.nring;
+    const int k = blockIdx.z * NT + threadIdx.x;
+    if (2 * k >= a.ldx) return;
+    XT* X = static_cast<XT*>(a.X) + (int64_t)(a.comp0 + blockIdx.y) * a.xcomp +
+            ((int64_t)mlist[i] * a.nring + ring) * a.ldx + 2 * k;
+    X[0] = XT(0);
+    X[1] = XT(0);
+}
+
 // sum over the ring of |r|^2 = (1/n) sum_j |R_j|^2 from the halfcomplex spectra
 // (bins 0 and n/2 once, the others twice), per map and component.
 // grid: x = ring, y = component
@@ -155,6 +169,14 @@ hipError_t launch_level_fold(const FftArgs& a, const int* mlist, int nlist, cons
     if (nlist <= 0) return hipSuccess;
     if (a.x32) hipLaunchKernelGGL(k_level_fold<float>, level_grid(a, nlist, ncompl), dim3(NT), 0, st, a, mlist, cmin);
     else hipLaunchKernelGGL(k_level_fold<double>, level_grid(a, nlist, ncompl), dim3(NT), 0, st, a, mlist, cmin);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_zero(const FftArgs& a, const int* mlist, int nlist, int ncompl, hipStream_t st)
+{
+    if (nlist <= 0) return hipSuccess;
+    if (a.x32) hipLaunchKernelGGL(k_level_zero<float>, level_grid(a, nlist, ncompl), dim3(NT), 0, st, a, mlist);
+    else hipLaunchKernelGGL(k_level_zero<double>, level_grid(a, nlist, ncompl), dim3(NT), 0, st, a, mlist);
     return hipGetLastError();
 }
 

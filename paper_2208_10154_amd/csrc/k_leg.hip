@@ -61,7 +61,9 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
     __shared__ T lam[2 * BUF];          // [buffer][parity class][ring][row/2]
 
     int m, lt, ct;
-    decode_tiles(a, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    int g = xcd_remap(blockIdx.x, gridDim.x);
+    const int sk = split_part(a, g);
+    decode_tiles(a, g, m, lt, ct);
     const int L = a.lmax, lb = m;
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int lane = threadIdx.x & 63, wave = wave_index();
@@ -91,8 +93,9 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
 #pragma unroll
             for (int u = 0; u < NU; ++u) acc[p][t][u] = typename MF::acc{0, 0, 0, 0};
 
-    const int nchunk = (a.rn + M_TR - 1) / M_TR;
-    const int rc0 = first_chunk(a, m, nchunk, lend);
+    int nchunk = (a.rn + M_TR - 1) / M_TR;
+    int rc0 = first_chunk(a, m, nchunk, lend);
+    split_range(a, sk, rc0, nchunk);
     if (rc0 < nchunk) {
         const T* Xm = xptr<T>(a, 0) + (int64_t)m * a.nring * a.ldx + col;
         auto seed_of = [&](Seed<0>& s, int rc) {
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
                 const int l = l0 + 2 * ci + p;
                 if (l > L) continue;
 #pragma unroll
-                for (int u = 0; u < NU; ++u) A[(int64_t)(l - lb) * a.ldx + col + 16 * u] = (T)acc[p][t][u][v];
+                for (int u = 0; u < NU; ++u) put_out(&A[(int64_t)(l - lb) * a.ldx + col + 16 * u], (T)acc[p][t][u][v], a.ksplit > 1);
             }
 }
 
@@ -196,7 +199,9 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
     __shared__ T fpm[2 * BUF];  // [buffer][F+ / F-][parity class][ring][row/2]
 
     int m, lt, ct;
-    decode_tiles(a, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    int g = xcd_remap(blockIdx.x, gridDim.x);
+    const int sk = split_part(a, g);
+    decode_tiles(a, g, m, lt, ct);
     const int L = a.lmax, lb = lbase(2, m);
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int po = (lb - m) & 1;
@@ -228,8 +233,9 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
 #pragma unroll
             for (int u = 0; u < NU; ++u) accE[p][t][u] = accB[p][t][u] = typename MF::acc{0, 0, 0, 0};
 
-    const int nchunk = (a.rn + M_TR - 1) / M_TR;
-    const int rc0 = first_chunk(a, m, nchunk, lend);
+    int nchunk = (a.rn + M_TR - 1) / M_TR;
+    int rc0 = first_chunk(a, m, nchunk, lend);
+    split_range(a, sk, rc0, nchunk);
     if (rc0 < nchunk) {
         const int64_t xm = (int64_t)m * a.nring * a.ldx;
         const T* XQ = xptr<T>(a, 1) + xm + col;
@@ -338,8 +344,8 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
                     const int64_t o = (int64_t)(l - lb) * a.ldx + col + 16 * u;
-                    AE[o] = (T)accE[p][t][u][v];
-                    AB[o] = (T)accB[p][t][u][v];
+                    put_out(&AE[o], (T)accE[p][t][u][v], a.ksplit > 1);
+                    put_out(&AB[o], (T)accB[p][t][u][v], a.ksplit > 1);
                 }
             }
 }
@@ -360,7 +366,8 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
     __shared__ double ctile[2][CoefTile<2>::N];
 
     const int nrt = (a.rn + A0_TR - 1) / A0_TR;
-    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    int g = xcd_remap(blockIdx.x, gridDim.x);
+    const int sk = split_part(a, g);
     const int mi = g / (a.ctiles * nrt);
     const int m = a.mlist ? a.mlist[mi] : mfold(mi, a.lmax);
     const int rem = g - mi * a.ctiles * nrt;
@@ -380,6 +387,12 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
 
     int lfirst, nch;
     a2m_range(a, m, lb, r0, A0_TR, lfirst, nch);
+    if (a.ksplit > 1) {
+        int c0 = 0, c1 = nch;
+        split_range(a, sk, c0, c1);
+        lfirst += TL * c0;
+        nch = c1 - c0;
+    }
 
     using MF = Mfma<T>;
     typename MF::acc accE[4][NU], accO[4][NU];  // [ring tile][column tile]
@@ -488,8 +501,8 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const T e = accE[t][u][v], o = accO[t][u][v];
-                X[(int64_t)r * a.ldx + 16 * u] = e + o;
-                if (rs != r) X[(int64_t)rs * a.ldx + 16 * u] = e - o;
+                put_out(&X[(int64_t)r * a.ldx + 16 * u], (T)(e + o), a.ksplit > 1);
+                if (rs != r) put_out(&X[(int64_t)rs * a.ldx + 16 * u], (T)(e - o), a.ksplit > 1);
             }
         }
 }
@@ -514,7 +527,8 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
     __shared__ double ctile[2][CoefTile<4>::N];
 
     const int nrt = (a.rn + A2_TR - 1) / A2_TR;
-    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    int g = xcd_remap(blockIdx.x, gridDim.x);
+    const int sk = split_part(a, g);
     const int mi = g / (a.ctiles * nrt);
     const int m = a.mlist ? a.mlist[mi] : mfold(mi, a.lmax);
     const int rem = g - mi * a.ctiles * nrt;
@@ -534,6 +548,12 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
 
     int lfirst, nch;
     a2m_range(a, m, lb, r0, A2_TR, lfirst, nch);
+    if (a.ksplit > 1) {
+        int c0 = 0, c1 = nch;
+        split_range(a, sk, c0, c1);
+        lfirst += TL * c0;
+        nch = c1 - c0;
+    }
 
     using MF = Mfma<T>;
     typename MF::acc u1[2][NU], u2[2][NU], v1[2][NU], v2[2][NU];  // [ring tile][column tile]
@@ -665,11 +685,11 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
             for (int u = 0; u < NU; ++u) {
                 const T U1 = u1[t][u][v], U2 = u2[t][u][v];
                 const T V1 = v1[t][u][v], V2 = v2[t][u][v];
-                XQ[(int64_t)r * a.ldx + 16 * u] = U1 + U2;
-                XU[(int64_t)r * a.ldx + 16 * u] = flip((T)(V1 + V2), usg);
+                put_out(&XQ[(int64_t)r * a.ldx + 16 * u], (T)(U1 + U2), a.ksplit > 1);
+                put_out(&XU[(int64_t)r * a.ldx + 16 * u], flip((T)(V1 + V2), usg), a.ksplit > 1);
                 if (rs != r) {
-                    XQ[(int64_t)rs * a.ldx + 16 * u] = U1 - U2;
-                    XU[(int64_t)rs * a.ldx + 16 * u] = flip((T)(V1 - V2), usg);
+                    put_out(&XQ[(int64_t)rs * a.ldx + 16 * u], (T)(U1 - U2), a.ksplit > 1);
+                    put_out(&XU[(int64_t)rs * a.ldx + 16 * u], flip((T)(V1 - V2), usg), a.ksplit > 1);
                 }
             }
         }
@@ -694,14 +714,14 @@ hipError_t launch_m2a_t(const LegArgs& a, hipStream_t st)
     if (a.spin == 0) {
         const int nu = pick_nu(4, a.ldx);
         b.ctiles = (int)(a.ldx / (64 * nu));
-        const dim3 grid(b.ntiles * b.ctiles);
+        const dim3 grid(b.ntiles * b.ctiles * kparts(a));
         if (nu == 4) hipLaunchKernelGGL((k_m2a_spin0<T, 4>), grid, blk, 0, st, b);
         else if (nu == 2) hipLaunchKernelGGL((k_m2a_spin0<T, 2>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_m2a_spin0<T, 1>), grid, blk, 0, st, b);
     } else {
         const int nu = pick_nu(2, a.ldx);
         b.ctiles = (int)(a.ldx / (64 * nu));
-        const dim3 grid(b.ntiles * b.ctiles);
+        const dim3 grid(b.ntiles * b.ctiles * kparts(a));
         if (nu == 2) {
             if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2<T, 2, 1>), grid, blk, 0, st, b);
             else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2<T, 2, 2>), grid, blk, 0, st, b);
@@ -724,7 +744,7 @@ hipError_t launch_a2m_t(const LegArgs& a, hipStream_t st)
     if (a.spin == 0) {
         const int nu = pick_nu(F64 ? 2 : 4, a.ldx);
         b.ctiles = (int)(a.ldx / (64 * nu));
-        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A0_TR - 1) / A0_TR));
+        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A0_TR - 1) / A0_TR) * kparts(a));
         if constexpr (!F64) {
             if (nu == 4) {
                 hipLaunchKernelGGL((k_a2m_spin0<T, 4>), grid, blk, 0, st, b);
@@ -736,7 +756,7 @@ hipError_t launch_a2m_t(const LegArgs& a, hipStream_t st)
     } else {
         const int nu = pick_nu(2, a.ldx);
         b.ctiles = (int)(a.ldx / (64 * nu));
-        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR));
+        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR) * kparts(a));
         if (nu == 2) {
             if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2<T, 2, 1>), grid, blk, 0, st, b);
             else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2<T, 2, 2>), grid, blk, 0, st, b);

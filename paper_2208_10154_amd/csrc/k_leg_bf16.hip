@@ -137,7 +137,9 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
     __shared__ __attribute__((aligned(16))) __bf16 lam[2 * BUF];
 
     int m, lt, ct;
-    decode_tiles(a, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    int g = xcd_remap(blockIdx.x, gridDim.x);
+    const int sk = split_part(a, g);
+    decode_tiles(a, g, m, lt, ct);
     const int L = a.lmax, lb = m;
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int lane = threadIdx.x & 63, wave = wave_index();
@@ -166,8 +168,9 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
 #pragma unroll
             for (int u = 0; u < NU; ++u) acc[p][t][u] = v4f{0, 0, 0, 0};
 
-    const int nchunk = (a.rn + M_TR - 1) / M_TR;
-    const int rc0 = first_chunk(a, m, nchunk, lend);
+    int nchunk = (a.rn + M_TR - 1) / M_TR;
+    int rc0 = first_chunk(a, m, nchunk, lend);
+    split_range(a, sk, rc0, nchunk);
     if (rc0 < nchunk) {
         const float* Xm = fptr(a.X, 0, a.xcomp) + (int64_t)m * a.nring * a.ldx + col;
         auto seed_of = [&](Seed<0>& s, int rc) {
@@ -268,7 +271,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
                 const int l = l0 + 2 * ci + p;
                 if (l > L) continue;
 #pragma unroll
-                for (int u = 0; u < NU; ++u) A[(int64_t)(l - lb) * a.ldx + col + 16 * u] = acc[p][t][u][v];
+                for (int u = 0; u < NU; ++u) put_out(&A[(int64_t)(l - lb) * a.ldx + col + 16 * u], (float)acc[p][t][u][v], a.ksplit > 1);
             }
 }
 
@@ -283,7 +286,9 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
     __shared__ __attribute__((aligned(16))) __bf16 fpm[2 * BUF];
 
     int m, lt, ct;
-    decode_tiles(a, xcd_remap(blockIdx.x, gridDim.x), m, lt, ct);
+    int g = xcd_remap(blockIdx.x, gridDim.x);
+    const int sk = split_part(a, g);
+    decode_tiles(a, g, m, lt, ct);
     const int L = a.lmax, lb = lbase(2, m);
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int po = (lb - m) & 1;
@@ -315,8 +320,9 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
 #pragma unroll
             for (int u = 0; u < NU; ++u) accE[p][t][u] = accB[p][t][u] = v4f{0, 0, 0, 0};
 
-    const int nchunk = (a.rn + M_TR - 1) / M_TR;
-    const int rc0 = first_chunk(a, m, nchunk, lend);
+    int nchunk = (a.rn + M_TR - 1) / M_TR;
+    int rc0 = first_chunk(a, m, nchunk, lend);
+    split_range(a, sk, rc0, nchunk);
     if (rc0 < nchunk) {
         const int64_t xm = (int64_t)m * a.nring * a.ldx;
         const float* XQ = fptr(a.X, 1, a.xcomp) + xm + col;
@@ -441,8 +447,8 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
                     const int64_t o = (int64_t)(l - lb) * a.ldx + col + 16 * u;
-                    AE[o] = accE[p][t][u][v];
-                    AB[o] = accB[p][t][u][v];
+                    put_out(&AE[o], (float)accE[p][t][u][v], a.ksplit > 1);
+                    put_out(&AB[o], (float)accB[p][t][u][v], a.ksplit > 1);
                 }
             }
 }
@@ -461,7 +467,8 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
     __shared__ double ctile[2][CoefTile<2>::N];
 
     const int nrt = (a.rn + A0_TR - 1) / A0_TR;
-    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    int g = xcd_remap(blockIdx.x, gridDim.x);
+    const int sk = split_part(a, g);
     const int mi = g / (a.ctiles * nrt);
     const int m = a.mlist ? a.mlist[mi] : mfold(mi, a.lmax);
     const int rem = g - mi * a.ctiles * nrt;
@@ -482,6 +489,12 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
 
     int lfirst, nch;
     a2m_range(a, m, lb, r0, A0_TR, lfirst, nch);
+    if (a.ksplit > 1) {
+        int c0 = 0, c1 = nch;
+        split_range(a, sk, c0, c1);
+        lfirst += TL * c0;
+        nch = c1 - c0;
+    }
 
     v4f accE[4][NU], accO[4][NU];  // [ring tile][column tile]
 #pragma unroll
@@ -589,8 +602,8 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const float e = accE[t][u][v], o = accO[t][u][v];
-                X[(int64_t)r * a.ldx + 16 * u] = e + o;
-                if (rs != r) X[(int64_t)rs * a.ldx + 16 * u] = e - o;
+                put_out(&X[(int64_t)r * a.ldx + 16 * u], (float)(e + o), a.ksplit > 1);
+                if (rs != r) put_out(&X[(int64_t)rs * a.ldx + 16 * u], (float)(e - o), a.ksplit > 1);
             }
         }
 }
@@ -610,7 +623,8 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
     __shared__ double ctile[2][CoefTile<4>::N];
 
     const int nrt = (a.rn + A2_TR - 1) / A2_TR;
-    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    int g = xcd_remap(blockIdx.x, gridDim.x);
+    const int sk = split_part(a, g);
     const int mi = g / (a.ctiles * nrt);
     const int m = a.mlist ? a.mlist[mi] : mfold(mi, a.lmax);
     const int rem = g - mi * a.ctiles * nrt;
@@ -632,6 +646,12 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
 
     int lfirst, nch;
     a2m_range(a, m, lb, r0, A2_TR, lfirst, nch);
+    if (a.ksplit > 1) {
+        int c0 = 0, c1 = nch;
+        split_range(a, sk, c0, c1);
+        lfirst += TL * c0;
+        nch = c1 - c0;
+    }
 
     v4f u1[2][NU], u2[2][NU], v1[2][NU], v2[2][NU];
 #pragma unroll
@@ -771,11 +791,11 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
             for (int u = 0; u < NU; ++u) {
                 const float U1 = u1[t][u][v], U2 = u2[t][u][v];
                 const float V1 = v1[t][u][v], V2 = v2[t][u][v];
-                XQ[(int64_t)r * a.ldx + 16 * u] = U1 + U2;
-                XU[(int64_t)r * a.ldx + 16 * u] = flip(V1 + V2, usg);
+                put_out(&XQ[(int64_t)r * a.ldx + 16 * u], (float)(U1 + U2), a.ksplit > 1);
+                put_out(&XU[(int64_t)r * a.ldx + 16 * u], (float)flip(V1 + V2, usg), a.ksplit > 1);
                 if (rs != r) {
-                    XQ[(int64_t)rs * a.ldx + 16 * u] = U1 - U2;
-                    XU[(int64_t)rs * a.ldx + 16 * u] = flip(V1 - V2, usg);
+                    put_out(&XQ[(int64_t)rs * a.ldx + 16 * u], (float)(U1 - U2), a.ksplit > 1);
+                    put_out(&XU[(int64_t)rs * a.ldx + 16 * u], (float)flip(V1 - V2, usg), a.ksplit > 1);
                 }
             }
         }
@@ -790,17 +810,17 @@ hipError_t launch_leg_m2a_bf16(const LegArgs& a, hipStream_t st)
     if (a.spin == 0) {
         if (a.ldx % 128 == 0) {
             b.ctiles = (int)(a.ldx / 128);
-            hipLaunchKernelGGL((k_m2a_spin0_bf<2>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
+            hipLaunchKernelGGL((k_m2a_spin0_bf<2>), dim3(b.ntiles * b.ctiles * kparts(a)), blk, 0, st, b);
         } else {
             b.ctiles = (int)(a.ldx / 64);
-            hipLaunchKernelGGL((k_m2a_spin0_bf<1>), dim3(b.ntiles * b.ctiles), blk, 0, st, b);
+            hipLaunchKernelGGL((k_m2a_spin0_bf<1>), dim3(b.ntiles * b.ctiles * kparts(a)), blk, 0, st, b);
         }
     } else {
         // two column tiles per workgroup halve the recursion per column (the
         // kernel's VALU bound) and still fit 256 registers without spilling
         const int nu = a.ldx % 128 == 0 ? 2 : 1;
         b.ctiles = (int)(a.ldx / (64 * nu));
-        const dim3 grid(b.ntiles * b.ctiles);
+        const dim3 grid(b.ntiles * b.ctiles * kparts(a));
         if (nu == 2) {
             if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2_bf<2, 1>), grid, blk, 0, st, b);
             else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2_bf<2, 2>), grid, blk, 0, st, b);
@@ -819,12 +839,12 @@ hipError_t launch_leg_a2m_bf16(const LegArgs& a, hipStream_t st)
     if (a.spin == 0) {
         const int nu = a.ldx % 128 == 0 ? 2 : 1;
         b.ctiles = (int)(a.ldx / (64 * nu));
-        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A0_TR - 1) / A0_TR));
+        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A0_TR - 1) / A0_TR) * kparts(a));
         if (nu == 2) hipLaunchKernelGGL((k_a2m_spin0_bf<2>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_a2m_spin0_bf<1>), grid, blk, 0, st, b);
     } else {
         b.ctiles = (int)(a.ldx / 64);
-        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR));
+        const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR) * kparts(a));
         if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2_bf<1, 1>), grid, blk, 0, st, b);
         else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2_bf<1, 2>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_a2m_spin2_bf<1, 0>), grid, blk, 0, st, b);

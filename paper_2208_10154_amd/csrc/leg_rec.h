@@ -241,6 +241,35 @@ __device__ __forceinline__ void decode_tiles(const LegArgs& a, int g, int& m, in
 // m values an alm2map launch covers (all, or the listed ones)
 __host__ __device__ inline int nm_rows(const LegArgs& a) { return a.mlist ? a.nlist : a.lmax + 1; }
 
+// workgroups per reduction range (see LegArgs::ksplit)
+__host__ __device__ inline int kparts(const LegArgs& a) { return a.ksplit > 1 ? a.ksplit : 1; }
+
+// part of a split range this workgroup takes; g becomes the unsplit index
+__device__ __forceinline__ int split_part(const LegArgs& a, int& g)
+{
+    if (a.ksplit <= 1) return 0;
+    const int s = g % a.ksplit;
+    g /= a.ksplit;
+    return s;
+}
+
+// narrow [b, e) to part s of the split
+__device__ __forceinline__ void split_range(const LegArgs& a, int s, int& b, int& e)
+{
+    if (a.ksplit <= 1) return;
+    const int len = (e - b + a.ksplit - 1) / a.ksplit;
+    b = min(e, b + s * len);
+    e = min(e, b + len);
+}
+
+// output store, or an atomic add when the reduction is split over workgroups
+template <typename T>
+__device__ __forceinline__ void put_out(T* p, T v, bool add)
+{
+    if (add) atomicAdd(p, v);
+    else *p = v;
+}
+
 // first ring chunk whose significance bound reaches an l <= lend
 __device__ __forceinline__ int first_chunk(const LegArgs& a, int m, int nchunk, int lend)
 {

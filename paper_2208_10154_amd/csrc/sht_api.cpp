@@ -884,36 +884,53 @@ int run_level(sht_plan p, double* alm, int nm, int d)
         StageTimer t(p, SHT_STAGE_RESIDUAL);
         HIPCHK(launch_level_unfold(f, ml, nl, (const int*)V.cmin.p, p->ncomp, p->stream));
     }
+    // A level holds a few m, so its Legendre grids would cover a fraction of the
+    // chip with long serial reductions: split each reduction over several
+    // workgroups (about 1024 per launch) that add into cleared outputs.
+    const int ct = (int)std::max<int64_t>(1, p->ldx_cur / 128);
+    auto parts = [](int64_t wgs) { return (int)std::min<int64_t>(8, std::max<int64_t>(1, 1024 / std::max<int64_t>(1, wgs))); };
     for (int spin : {0, 2}) {
         if (spin == 2 && p->spin != 2) break;
         SeedSet& S = spin == 0 ? p->s0 : p->s2;
         const int* pref = (const int*)(spin == 0 ? V.pref0.p : V.pref2.p) + V.start[d] + d;
         const int nt = spin == 0 ? V.ntiles0[d] : V.ntiles2[d];
+        const int ncompl = spin == 0 ? 1 : 2;
         LegArgs a = leg_args(p, S);
         a.mlist = ml;
         a.nlist = nl;
         a.tiles = pref;
         a.ntiles = nt;
+        AlmArgs b = alm_args(p, S, nm);
+        b.mlist = ml;
+        b.nlist = nl;
+        b.tileoff = pref;
+        b.ntiles = nt;
+        b.alm_out = alm;
+        b.accumulate = 1;
         {
             StageTimer t(p, spin == 0 ? SHT_STAGE_M2A_SPIN0 : SHT_STAGE_M2A_SPIN2);
+            a.ksplit = parts((int64_t)nt * ct);
+            if (a.ksplit > 1) {
+                b.scale = 0.0;  // clear the rows the split map2alm adds into
+                HIPCHK(launch_level_rows(b, ncompl, p->prec, p->stream));
+            }
             HIPCHK(launch_leg_m2a(a, p->prec, p->stream));
         }
         {
             StageTimer t(p, SHT_STAGE_ALM_LAYOUT);
-            AlmArgs b = alm_args(p, S, nm);
-            b.mlist = ml;
-            b.nlist = nl;
-            b.tileoff = pref;
-            b.ntiles = nt;
-            b.alm_out = alm;
             b.scale = dsig;
-            b.accumulate = 1;
-            const int ncompl = spin == 0 ? 1 : 2;
             HIPCHK(launch_alm_from_mmajor(b, ncompl, p->prec, p->stream));
             HIPCHK(launch_level_rows(b, ncompl, p->prec, p->stream));
         }
         {
             StageTimer t(p, spin == 0 ? SHT_STAGE_A2M_SPIN0 : SHT_STAGE_A2M_SPIN2);
+            const int tr = spin == 0 ? 64 : 32;  // rings per alm2map tile
+            a.ksplit = parts((int64_t)nl * ct * ((p->rn + tr - 1) / tr));
+            if (a.ksplit > 1) {  // clear this spin's rows the split alm2map adds into
+                FftArgs z = f;
+                z.comp0 = spin == 0 ? 0 : 1;
+                HIPCHK(launch_level_zero(z, ml, nl, ncompl, p->stream));
+            }
             HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
         }
     }

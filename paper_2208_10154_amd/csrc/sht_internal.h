@@ -136,6 +136,10 @@ struct LegArgs {
     // ntiles their total
     const int* mlist;
     int nlist;
+    // > 1: each workgroup's reduction range (map2alm: ring chunks, alm2map: l
+    // tiles) is split over ksplit workgroups that add into pre-zeroed outputs
+    // (list mode, where one level's grid is too small to fill the chip)
+    int ksplit;
 };
 
 // Layout change compact alm <-> m-major rows (one spin's components per launch).
@@ -171,6 +175,8 @@ hipError_t launch_level_rows(const AlmArgs& a, int ncompl, int prec, hipStream_t
 hipError_t launch_level_unfold(const FftArgs& a, const int* mlist, int nlist, const int* cmin, int ncompl, hipStream_t st);
 hipError_t launch_level_fold(const FftArgs& a, const int* mlist, int nlist, const int* cmin, int ncompl, hipStream_t st);
 hipError_t launch_hc_norms(const FftArgs& a, int ncompl, hipStream_t st);
+// zero the ring coefficient rows of the listed m, every ring and column
+hipError_t launch_level_zero(const FftArgs& a, const int* mlist, int nlist, int ncompl, hipStream_t st);
 
 // Folded m order 0, lmax, 1, lmax-1, ...: work per m falls linearly with m, so any
 // run of consecutive folded indices carries about the same work per index.  Each
