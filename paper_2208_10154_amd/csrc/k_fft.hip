@@ -631,24 +631,17 @@ __global__ __launch_bounds__(NT, ELEMS == 16 ? 2 : 4) void k_residual(FftArgs a,
         const bool live = (int)threadIdx.x + q * NT < tot;
         ssa[q] = live ? (Ra.x * Ra.x + Ra.y * Ra.y) / dnn : 0.0;
         ssb[q] = live ? (Rb.x * Rb.x + Rb.y * Rb.y) / dnn : 0.0;
-        if (a.store_res) {
-            // R over F in place: only the thread of the stored bin (2j <= n) writes
-            // (it read that slot itself); the mirror bin's thread may then read R
-            // instead of F, so its values are dropped and the norms count the stored
-            // bins with the Hermitian weight instead.
-            const bool own = live && 2 * j <= n;
-            const double w = own ? ((j == 0 || 2 * j == n) ? 1.0 : 2.0) : 0.0;
-            ssa[q] = w * (Ra.x * Ra.x + Ra.y * Ra.y) / dnn;
-            ssb[q] = w * (Rb.x * Rb.x + Rb.y * Rb.y) / dnn;
+        if (a.store_res && live && 2 * j <= n) {
+            // the stored bins (2j <= n) of both maps into R, maps contiguous per bin
             const int ir = hc_re(n, j), ii = hc_im(n, j);
-            double* f0 = const_cast<double*>(fbase) + (int64_t)k * mstride;
-            if (own && k < a.nmaps) {
-                f0[ir] = Ra.x;
-                if (ii >= 0) f0[ii] = Ra.y;
+            double* r0 = a.R + ((int64_t)c.comp * a.npix + c.rg.first) * a.nmaps + k;
+            if (k < a.nmaps) {
+                r0[(int64_t)ir * a.nmaps] = Ra.x;
+                if (ii >= 0) r0[(int64_t)ii * a.nmaps] = Ra.y;
             }
-            if (own && k + 1 < a.nmaps) {
-                f0[mstride + ir] = Rb.x;
-                if (ii >= 0) f0[mstride + ii] = Rb.y;
+            if (k + 1 < a.nmaps) {
+                r0[(int64_t)ir * a.nmaps + 1] = Rb.x;
+                if (ii >= 0) r0[(int64_t)ii * a.nmaps + 1] = Rb.y;
             }
         }
         res[q] = make_double2(Ra.x - Rb.y, Ra.y + Rb.x);  // pack as Ra + i Rb

@@ -3,9 +3,10 @@
 //
 // The immediate mode updates the coefficients of each m inside the m-loop, so
 // every later m works on a residual that already holds those updates.  The
-// residual is kept as ring spectra R (halfcomplex per ring, the layout the
-// forward ring FFT writes for the iteration), R = F - n C with C the folded
-// ring coefficients of the current synthesis:
+// residual is kept as ring spectra R (halfcomplex per ring as the forward ring
+// FFT stores spectra, bin-major with the maps of the chunk contiguous, so a wave
+// touches one bin of 64 maps in one run), R = F - n C with C the folded ring
+// coefficients of the current synthesis:
 //   unfold:  T_m(ring) = e^{-i m phi0} R_{m mod n}      (the map2alm input of m)
 //   fold:    R_{m mod n} -= n e^{i m phi0} dS_m,  R_{-m mod n} -= n conj(...)
 // with dS_m the synthesis of the update of m on that ring.  Modes processed
@@ -17,6 +18,7 @@ namespace sht {
 namespace {
 
 constexpr int NT = 256;
+constexpr int RB = NT / 64;  // rings per workgroup in the level kernels: one wave per ring, 64 maps
 
 // halfcomplex position of Re / Im of bin j (j and n - j share one slot; Im is
 // -1 where it is identically zero), as the ring FFT stores the spectra
@@ -36,17 +38,21 @@ struct LevelItem {
     bool live;             // ring carries data for m
 };
 
-// grid: x = list entry * nring + ring, y = component, z = block of 256 maps
+// grid: x = list entry * ring groups + group of RB rings, y = component,
+// z = block of 64 maps; wave w of the workgroup takes ring RB * group + w
+__device__ __forceinline__ int ring_groups(int nring) { return (nring + RB - 1) / RB; }
+
 __device__ __forceinline__ LevelItem level_item(const FftArgs& a, const int* mlist, const int* cmin)
 {
     LevelItem it;
-    const int i = blockIdx.x / a.nring;
-    it.ring = blockIdx.x - i * a.nring;
+    const int ng = ring_groups(a.nring);
+    const int i = blockIdx.x / ng;
+    it.ring = (blockIdx.x - i * ng) * RB + (int)(threadIdx.x >> 6);
     it.m = mlist[i];
     it.comp = a.comp0 + blockIdx.y;
-    it.k = blockIdx.z * NT + threadIdx.x;
+    it.k = blockIdx.z * 64 + (int)(threadIdx.x & 63);
     const int rn = min(it.ring, a.nring - 1 - it.ring);
-    it.live = rn / RCHUNK >= cmin[it.m];
+    it.live = it.ring < a.nring && rn / RCHUNK >= cmin[it.m];
     return it;
 }
 
@@ -68,10 +74,10 @@ __global__ __launch_bounds__(NT) void k_level_unfold(FftArgs a, const int* mlist
     if (it.k < a.nmaps) {
         const RingDev rg = a.rings[it.ring];
         const int n = rg.n, j = it.m % n;
-        const double* R = a.F + ((int64_t)it.k * a.ncomp + it.comp) * a.npix + rg.first;
-        const double re = R[hre(n, j)];
+        const double* R = a.R + ((int64_t)it.comp * a.npix + rg.first) * a.nmaps + it.k;
+        const double re = R[(int64_t)hre(n, j) * a.nmaps];
         const int pi = him(n, j);
-        const double im = pi < 0 ? 0.0 : (2 * j > n ? -R[pi] : R[pi]);
+        const double im = pi < 0 ? 0.0 : (2 * j > n ? -R[(int64_t)pi * a.nmaps] : R[(int64_t)pi * a.nmaps]);
         double c, s;
         phase(it.m, rg.s, n, c, s);
         tr = c * re - s * im;
@@ -95,13 +101,13 @@ __global__ __launch_bounds__(NT) void k_level_fold(FftArgs a, const int* mlist, 
     phase(it.m, rg.s, n, c, s);  // e^{-i m phi0}; the fold takes its conjugate
     const double cr = c * dr + s * di, ci = c * di - s * dr;
     const double dn = (double)n;
-    double* R = a.F + ((int64_t)it.k * a.ncomp + it.comp) * a.npix + rg.first;
+    double* R = a.R + ((int64_t)it.comp * a.npix + rg.first) * a.nmaps + it.k;
     if (j == 0 || 2 * j == n) {
         // the direct and the mirror term meet in a real bin (only c_0 itself at m = 0)
-        R[hre(n, j)] -= (it.m == 0 ? 1.0 : 2.0) * dn * cr;
+        R[(int64_t)hre(n, j) * a.nmaps] -= (it.m == 0 ? 1.0 : 2.0) * dn * cr;
     } else {
-        R[hre(n, j)] -= dn * cr;
-        R[him(n, j)] -= (2 * j > n ? -dn : dn) * ci;
+        R[(int64_t)hre(n, j) * a.nmaps] -= dn * cr;
+        R[(int64_t)him(n, j) * a.nmaps] -= (2 * j > n ? -dn : dn) * ci;
     }
 }
 
@@ -109,10 +115,11 @@ __global__ __launch_bounds__(NT) void k_level_fold(FftArgs a, const int* mlist, 
 template <typename XT>
 __global__ __launch_bounds__(NT) void k_level_zero(FftArgs a, const int* mlist)
 {
-    const int i = blockIdx.x / a.nring;
-    const int ring = blockIdx.x - i * a.nring;
-    const int k = blockIdx.z * NT + threadIdx.x;
-    if (2 * k >= a.ldx) return;
+    const int ng = ring_groups(a.nring);
+    const int i = blockIdx.x / ng;
+    const int ring = (blockIdx.x - i * ng) * RB + (int)(threadIdx.x >> 6);
+    const int k = blockIdx.z * 64 + (int)(threadIdx.x & 63);
+    if (ring >= a.nring || 2 * k >= a.ldx) return;
     XT* X = static_cast<XT*>(a.X) + (int64_t)(a.comp0 + blockIdx.y) * a.xcomp +
             ((int64_t)mlist[i] * a.nring + ring) * a.ldx + 2 * k;
     X[0] = XT(0);
@@ -120,38 +127,37 @@ __global__ __launch_bounds__(NT) void k_level_zero(FftArgs a, const int* mlist)
 }
 
 // sum over the ring of |r|^2 = (1/n) sum_j |R_j|^2 from the halfcomplex spectra
-// (bins 0 and n/2 once, the others twice), per map and component.
-// grid: x = ring, y = component
+// (bins 0 and n/2 once, the others twice), per map and component.  Lanes run
+// over maps, the waves over the ring's slots.
+// grid: x = ring, y = component, z = block of 64 maps
 __global__ __launch_bounds__(NT) void k_hc_norms(FftArgs a)
 {
-    __shared__ double part[NT / 64];
+    __shared__ double part[RB][64];
     const RingDev rg = a.rings[blockIdx.x];
     const int comp = a.comp0 + blockIdx.y, n = rg.n;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k = 0; k < a.nmaps; ++k) {
-        const double* R = a.F + ((int64_t)k * a.ncomp + comp) * a.npix + rg.first;
-        double acc = 0.0;
-        for (int p = threadIdx.x; p < n; p += NT) {
-            const double v = R[p];
+    const int k = blockIdx.z * 64 + lane;
+    double acc = 0.0;
+    if (k < a.nmaps) {
+        const double* R = a.R + ((int64_t)comp * a.npix + rg.first) * a.nmaps + k;
+        for (int p = wave; p < n; p += RB) {
+            const double v = R[(int64_t)p * a.nmaps];
             acc += (p == 0 || p == n - 1 ? 1.0 : 2.0) * v * v;
         }
+    }
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && k < a.nmaps) {
+        double t = 0.0;
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) part[wave] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-#pragma unroll
-            for (int w = 0; w < NT / 64; ++w) t += part[w];
-            atomicAdd(a.norms + (int64_t)k * a.ncomp + comp, t / (double)n);
-        }
-        __syncthreads();
+        for (int w = 0; w < RB; ++w) t += part[w][lane];
+        atomicAdd(a.norms + (int64_t)k * a.ncomp + comp, t / (double)n);
     }
 }
 
 dim3 level_grid(const FftArgs& a, int nlist, int ncompl)
 {
-    return dim3((unsigned)(nlist * a.nring), (unsigned)ncompl, (unsigned)((a.ldx / 2 + NT - 1) / NT));
+    return dim3((unsigned)(nlist * ((a.nring + RB - 1) / RB)), (unsigned)ncompl, (unsigned)((a.ldx / 2 + 63) / 64));
 }
 
 }  // namespace
@@ -182,7 +188,8 @@ hipError_t launch_level_zero(const FftArgs& a, const int* mlist, int nlist, int 
 
 hipError_t launch_hc_norms(const FftArgs& a, int ncompl, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_hc_norms, dim3((unsigned)a.nring, (unsigned)ncompl), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(k_hc_norms, dim3((unsigned)a.nring, (unsigned)ncompl, (unsigned)((a.nmaps + 63) / 64)), dim3(NT), 0,
+                       st, a);
     return hipGetLastError();
 }
 

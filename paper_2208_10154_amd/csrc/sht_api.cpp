@@ -88,6 +88,8 @@ struct sht_plan_s {
     size_t F_bytes = 0;
     double* norms = nullptr;
     size_t table_bytes = 0;
+    double* R = nullptr;  // immediate iteration: residual spectra, bin-major (lazily)
+    size_t R_bytes = 0;
 
     // ring skip bound per m (first ring chunk where either spin's Legendre values
     // of m are significant), and the immediate-iteration schedule built from it
@@ -869,7 +871,7 @@ int build_levels(sht_plan p)
     return SHT_OK;
 }
 
-// One level of an immediate sweep on the chunk's residual spectra (in p->F):
+// One level of an immediate sweep on the chunk's residual spectra (in p->R):
 // unfold R for the listed m, analyse, add dsigma times the result to alm, turn
 // the rows into the synthesis operand of the update, synthesise, fold back.
 int run_level(sht_plan p, double* alm, int nm, int d)
@@ -879,7 +881,7 @@ int run_level(sht_plan p, double* alm, int nm, int d)
     const int nl = V.len[d];
     const double dsig = 4.0 * M_PI / (double)p->npix;
     FftArgs f = fft_args(p, nm);
-    f.F = p->F;
+    f.R = p->R;
     {
         StageTimer t(p, SHT_STAGE_RESIDUAL);
         HIPCHK(launch_level_unfold(f, ml, nl, (const int*)V.cmin.p, p->ncomp, p->stream));
@@ -968,6 +970,7 @@ void destroy_all(sht_plan p)
     if (p->ws && p->ws_owned) (void)hipFree(p->ws);
     if (p->F) (void)hipFree(p->F);
     if (p->norms) (void)hipFree(p->norms);
+    if (p->R) (void)hipFree(p->R);
     delete p;
 }
 
@@ -1233,6 +1236,12 @@ int sht_map2alm_immediate(sht_plan p, const double* map, double* alm, int niter,
     if ((rc = prep(p))) return rc;
     if ((rc = ensure_iter_buffers(p))) return rc;
     if ((rc = build_levels(p))) return rc;
+    if (!p->R || p->R_bytes < p->F_bytes) {
+        if (p->R) (void)hipFree(p->R);
+        p->R = nullptr;
+        HIPCHK(hipMalloc((void**)&p->R, p->F_bytes));
+        p->R_bytes = p->F_bytes;
+    }
     const int64_t astride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
     const int64_t mstride = (int64_t)p->ncomp * p->npix;
     const int depth = (int)p->lev.len.size();
@@ -1257,10 +1266,11 @@ int sht_map2alm_immediate(sht_plan p, const double* map, double* alm, int niter,
         }
         if ((rc = run_m2a(p, a, nm, 0))) return rc;
         if (niter == 0 && !resid) continue;
-        // residual spectra of the first estimate, R = F - n C, over F
+        // residual spectra of the first estimate, R = F - n C
         if ((rc = run_a2m(p, a, nm))) return rc;
         FftArgs r = fft_args(p, nm);
         r.F = p->F;
+        r.R = p->R;
         r.store_res = 1;
         r.norms = resid ? p->norms : nullptr;
         if (resid) HIPCHK(hipMemsetAsync(p->norms, 0, (size_t)nm * p->ncomp * sizeof(double), p->stream));
@@ -1275,7 +1285,7 @@ int sht_map2alm_immediate(sht_plan p, const double* map, double* alm, int niter,
             if (resid) {
                 HIPCHK(hipMemsetAsync(p->norms, 0, (size_t)nm * p->ncomp * sizeof(double), p->stream));
                 FftArgs q = fft_args(p, nm);
-                q.F = p->F;
+                q.R = p->R;
                 q.norms = p->norms;
                 HIPCHK(launch_hc_norms(q, p->ncomp, p->stream));
                 if ((rc = collect(it, nm))) return rc;

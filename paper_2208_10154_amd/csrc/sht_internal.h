@@ -102,7 +102,10 @@ struct FftArgs {
     int64_t xcomp;          // element stride between the X arrays of consecutive components
     int x32;                // X stored as float
     int iteration_sub;      // K_RES: subtract N*C from F into X
-    int store_res;          // K_RES: write the residual spectrum back over F (halfcomplex)
+    int store_res;          // K_RES: write the residual spectra to R
+    // immediate iteration: residual spectra, halfcomplex per ring, bin-major with the
+    // maps of the chunk contiguous: R[(comp * npix + pixel slot) * nmaps + map]
+    double* R;
 };
 
 struct LegArgs {
@@ -169,8 +172,8 @@ hipError_t launch_zero_strided(double* base, int rows, int64_t stride, int64_t l
 // alm2map operand format, with the parts the compact storage lacks (m = 0) zeroed
 hipError_t launch_level_rows(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
 
-// immediate iteration, Fourier side (k_iter.hip).  F holds the residual spectra
-// R (halfcomplex per ring, [map-set][comp][npix]); cmin[m] is the first ring chunk
+// immediate iteration, Fourier side (k_iter.hip), on the residual spectra
+// FftArgs::R; cmin[m] is the first ring chunk
 // where some Legendre value of m is significant (rings before it carry no data for m).
 hipError_t launch_level_unfold(const FftArgs& a, const int* mlist, int nlist, const int* cmin, int ncompl, hipStream_t st);
 hipError_t launch_level_fold(const FftArgs& a, const int* mlist, int nlist, const int* cmin, int ncompl, hipStream_t st);
