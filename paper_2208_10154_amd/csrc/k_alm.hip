@@ -89,7 +89,9 @@ __global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
 // m-major rows -> compact (FP64): alm = scale * A (or alm += scale * A).
 // kind 1 converts B' back: Re a_B = Im B', Im a_B = -Re B'.  Spin-2 components
 // have no l < 2 coefficients: the first tile of m < 2 clears them (store mode).
-template <typename T>
+// TO != void: also rewrite the rows in place as the alm2map operand of the same
+// update, in TO's format (see k_level_rows), from the tile already in LDS.
+template <typename T, typename TO = void>
 __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
 {
     __shared__ double tile[TLB][2 * TK + 1];
@@ -129,6 +131,19 @@ __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
         if (o < 0) continue;
         v *= a.scale;
         if (a.accumulate) base[o] += v; else base[o] = v;
+    }
+    if constexpr (!__is_same(TO, void)) {
+        // tile reads all happened before the barrier above
+        TO* out = static_cast<TO*>(a.A) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
+        const int drop = (m == 0) ? (kind == 0 ? 1 : 0) : -1;
+        for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+            const int li = e / (2 * TK), c = e % (2 * TK);
+            if (l0 + li > L) continue;
+            const bool keep = (c & 1) != drop && kb * TK + (c >> 1) < a.nmaps;
+            const double v = keep ? a.scale * tile[li][c] : 0.0;
+            if constexpr (__is_same(TO, uint32_t)) out[(int64_t)li * a.ldx + c] = pack_bf16_pair((float)v);
+            else out[(int64_t)li * a.ldx + c] = (TO)v;
+        }
     }
     if (a.spin == 2 && !a.accumulate && m < 2 && lt == 0) {
         for (int e = threadIdx.x; e < TK * 2 * 2; e += NT) {
@@ -200,6 +215,15 @@ hipError_t launch_level_rows(const AlmArgs& a, int ncompl, int prec, hipStream_t
     if (prec == 0) hipLaunchKernelGGL((k_level_rows<double, double>), grid, dim3(NT), 0, st, a);
     else if (prec == 2) hipLaunchKernelGGL((k_level_rows<float, uint32_t>), grid, dim3(NT), 0, st, a);
     else hipLaunchKernelGGL((k_level_rows<float, float>), grid, dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_commit(const AlmArgs& a, int ncompl, int prec, hipStream_t st)
+{
+    dim3 grid(a.ntiles * a.kblocks, ncompl);
+    if (prec == 0) hipLaunchKernelGGL((k_from_mmajor<double, double>), grid, dim3(NT), 0, st, a);
+    else if (prec == 2) hipLaunchKernelGGL((k_from_mmajor<float, uint32_t>), grid, dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL((k_from_mmajor<float, float>), grid, dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 

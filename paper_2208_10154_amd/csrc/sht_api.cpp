@@ -921,8 +921,7 @@ int run_level(sht_plan p, double* alm, int nm, int d)
         {
             StageTimer t(p, SHT_STAGE_ALM_LAYOUT);
             b.scale = dsig;
-            HIPCHK(launch_alm_from_mmajor(b, ncompl, p->prec, p->stream));
-            HIPCHK(launch_level_rows(b, ncompl, p->prec, p->stream));
+            HIPCHK(launch_level_commit(b, ncompl, p->prec, p->stream));
         }
         {
             StageTimer t(p, spin == 0 ? SHT_STAGE_A2M_SPIN0 : SHT_STAGE_A2M_SPIN2);

@@ -171,6 +171,9 @@ hipError_t launch_zero_strided(double* base, int rows, int64_t stride, int64_t l
 // immediate iteration: A rows of the listed m (m2a output) -> scale * rows in the
 // alm2map operand format, with the parts the compact storage lacks (m = 0) zeroed
 hipError_t launch_level_rows(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
+// immediate iteration: alm += scale * rows (as launch_alm_from_mmajor with
+// accumulate) and the rows rewritten as launch_level_rows does, in one pass
+hipError_t launch_level_commit(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
 
 // immediate iteration, Fourier side (k_iter.hip), on the residual spectra
 // FftArgs::R; cmin[m] is the first ring chunk
