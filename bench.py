@@ -399,7 +399,7 @@ def immediate_leg(args):
                        "rel_err_vs_input_alm": float(f"{err:.4e}")}
             if mode == "immediate":
                 r[mode]["stages_ms"] = {k: round(v[0], 2) for k, v in prof.items() if v[1]}
-                r[mode]["launches"] = int(sum(v[1] for v in prof.values()))
+                r[mode]["stage_records"] = int(sum(v[1] for v in prof.values()))
         r["residual_ratio_immediate_over_traditional"] = round(r["immediate"]["residual_rms"][-1] /
                                                                r["traditional"]["residual_rms"][-1], 4)
         res[prec] = r
