@@ -360,6 +360,46 @@ def iteration_leg(args):
             "chunk": args.iter_chunk, "noise": "white, 1e-2 of each map's RMS", "by_precision": res}
 
 
+def spin0_leg(args):
+    """Spin-0 workload: nside 128, lmax 383, 1000 T maps, FP64 (Gaussian a_lm with
+    C_l = 1/(l+1)^2, seeded on the device), alm2map + map2alm per step, the whole
+    batch resident in HBM.  Reports T maps/s and the stage times."""
+    import torch
+    from paper_2208_10154_amd import sht
+    nside, L, n = 128, 383, 1000
+    p = sht.Plan(nside, L, 0, n)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(220810154 + 2)
+    alm = compact_scale(L).to("cuda") * torch.randn((n, 1, (L + 1) ** 2), generator=g, device="cuda",
+                                                     dtype=torch.float64)
+    maps = torch.empty((n, 1, 12 * nside * nside), dtype=torch.float64, device="cuda")
+    out = torch.empty_like(alm)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(1, args.warmup)):
+        p.alm2map(alm, maps, stream)
+        p.map2alm(maps, out, stream)
+    torch.cuda.synchronize()
+    p.set_profiling(True)
+    p.profile(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        p.alm2map(alm, maps, stream)
+        p.map2alm(maps, out, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    prof = p.profile(reset=True)
+    p.close()
+    del alm, maps, out
+    torch.cuda.empty_cache()
+    res = {"workload": f"healpix_t_nside{nside}_lmax{L}_x{n}", "dtype": "f64", "ms_per_step": round(ms, 3),
+           "t_maps_per_s": round(n * 1000.0 / ms, 1),
+           "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]}}
+    log(f"spin 0 nside {nside}: {res}")
+    return res
+
+
 def immediate_leg(args):
     """Immediate iteration (Sec. 4, Algorithm 3) against the traditional one on the
     comparison of Fig. 3: maps band limited to lmax = 3 nside - 1 (Gaussian a_lm
@@ -494,6 +534,7 @@ def main():
     ap.add_argument("--no-iter", action="store_true", help="skip the iteration leg (config 4)")
     ap.add_argument("--no-eb", action="store_true", help="skip the E/B leg")
     ap.add_argument("--no-imm", action="store_true", help="skip the immediate-iteration leg")
+    ap.add_argument("--no-spin0", action="store_true", help="skip the spin-0 nside 128 leg")
     ap.add_argument("--imm-nmaps", type=int, default=64, help="IQU triples of the immediate-iteration leg")
     ap.add_argument("--imm-precisions", default="fp64,bf16x3")
     ap.add_argument("--eb-nmaps", type=int, default=250, help="IQU triples of the E/B leg")
@@ -574,6 +615,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_iter:
         line["iteration"] = iteration_leg(args)
+    if not args.no_spin0:
+        line["spin0"] = spin0_leg(args)
     if not args.no_imm:
         line["immediate"] = immediate_leg(args)
     if not args.no_serve:
