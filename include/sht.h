@@ -52,7 +52,7 @@ enum sht_status {
     SHT_ERR_ARG = -1,         /* invalid argument: nothing was done */
     SHT_ERR_NOMEM = -2,       /* device or host allocation failed */
     SHT_ERR_DEVICE = -3,      /* a HIP call or kernel failed */
-    SHT_ERR_UNSUPPORTED = -4  /* valid request outside what this build implements */
+    SHT_ERR_UNSUPPORTED = -4  /* valid request outside what this library implements */
 };
 
 /* Precision of the Legendre contraction.  The recursion (with its exponent
@@ -66,7 +66,7 @@ enum sht_precision {
 /* Create a plan for HEALPix resolution nside, band limit lmax and spin 0 (T maps)
  * or 2 (IQU map triples), for batches of up to nmaps map sets per call.
  * Requires 1 <= nside <= 8192, 0 <= lmax <= 4*nside-1 (spin 2: lmax >= 2),
- * nmaps >= 1 (SHT_ERR_ARG otherwise); this build supports nside <= 1024 and
+ * nmaps >= 1 (SHT_ERR_ARG otherwise); this library supports nside <= 1024 and
  * lmax <= 4094 (SHT_ERR_UNSUPPORTED beyond).  Builds the ring tables, FFT plans and Legendre seed tables on the
  * current HIP device (the paper's once-only initialisation, Sec. 3.3) and
  * allocates the workspace for one chunk of map sets (see sht_plan_set_chunk). */
