@@ -132,7 +132,8 @@ int sht_map2alm_iter(sht_plan plan, const double* map, double* alm, int niter, d
  * per plan, which leaves the result of the sweep unchanged.  resid as for
  * sht_map2alm_iter (RMS over all pixels after estimate n, n = 0 .. niter; the
  * call then synchronises the stream).  Same layouts and errors as
- * sht_map2alm_iter. */
+ * sht_map2alm_iter.  The plan allocates, on the first call, a residual buffer
+ * of the iteration buffer's size (8 * chunk * ncomp * 12 nside^2 bytes). */
 int sht_map2alm_immediate(sht_plan plan, const double* map, double* alm, int niter, double* resid);
 
 /* Components of the selective transforms (bit mask). */
