@@ -164,3 +164,38 @@ def test_nside1024_iteration_converges_and_mixed_agrees(big):
     assert res[1] < 0.5 * res[0] and res[2] < res[1] * 1.01, res
     assert res[-1] <= 1.01 * min(res) and res[-1] < 1e-5, res
     assert rel(mixed, fp64) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_nside1024_largest_band_limit_sampled(prec):
+    """The largest supported band limit at the largest supported nside (1024,
+    lmax 4094, spin 0): starting values λ_mm far below the FP64 range on most of
+    the sphere, one map, sampled pixels of alm2map and sampled a_lm of map2alm
+    against the oracle (long double)."""
+    import torch
+    from paper_2208_10154_amd import sht
+    N, L = 1024, 4094
+    note(f"nside {N} lmax {L} spin 0 sampled {prec}")
+    alm_c = synth.gaussian_alm(L, 1, False, workload=14)
+    alm_c = alm_c[:, 0] if alm_c.ndim == 4 else alm_c
+    maps_np = synth.white_maps(12 * N ** 2, 1, 1, workload=14)
+    p = sht.Plan(N, L, 0, 1, precision=prec)
+    m_out = torch.empty(p.map_shape(), dtype=torch.float64, device="cuda")
+    a_out = torch.empty(p.alm_shape(), dtype=torch.float64, device="cuda")
+    p.alm2map(to_dev(oracle.to_compact(alm_c[:, None])), m_out)
+    p.map2alm(to_dev(maps_np), a_out)
+    p.sync()
+    p.close()
+    rng = np.random.default_rng(14)
+    pix = np.concatenate([[0, 3, 12 * N ** 2 - 1, 6 * N ** 2 + 7], rng.integers(0, 12 * N ** 2, 12)])
+    got = from_dev(m_out[0, 0][pix])
+    ref = oracle.synth_pixels(N, L, alm_c[0], pix)
+    assert rel(got, ref) <= TOL[prec], "alm2map"
+    ls = np.array([0, 7, 1000, 3000, 4094, 4094, 4000, 2500])
+    ms = np.array([0, 2, 999, 2000, 0, 4094, 3999, 17])
+    L1 = L + 1
+    comp = from_dev(a_out[0, 0])
+    ref = oracle.analyze_lm(N, L, maps_np[0, 0], ls, ms)
+    msafe = np.maximum(ms, 1)
+    im = np.where(ms > 0, comp[(L1 - msafe) * L1 + (ls - msafe)], 0.0)
+    assert rel(comp[ms * L1 + ls] + 1j * im, ref) <= TOL[prec], "map2alm"
