@@ -142,17 +142,18 @@ def run_precision(sht, args, prec, alm, maps, alm_out):
         log(f"{prec}: warmup {w + 1}/{args.warmup} done")
     p.set_profiling(True)
     p.profile(reset=True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    ev0.record(stream)
+    evs[0].record(stream)
     for k in range(args.steps):
         p.alm2map(alm, maps, stream)
         p.map2alm(maps, alm_out, stream)
-    ev1.record(stream)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    ms = ev0.elapsed_time(ev1)
+    ms = evs[0].elapsed_time(evs[-1])
+    per = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps))
     prof = p.profile(reset=True)
     p.set_profiling(False)
     rows = p.ring_rows()
@@ -161,7 +162,7 @@ def run_precision(sht, args, prec, alm, maps, alm_out):
     per_step = ms / args.steps
     log(f"{prec}: {per_step:.1f} ms/step ({wall:.2f}s wall for {args.steps} steps)")
     return {"ms_per_step": per_step, "value": n * 1000.0 / per_step, "init_s": init_s, "stages": prof,
-            "ring_rows": rows}
+            "ring_rows": rows, "step_ms": {"median": per[len(per) // 2], "min": per[0], "max": per[-1]}}
 
 
 def eb_leg(sht, args, precs, alm, maps, alm_out):
@@ -521,7 +522,7 @@ def serving(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nside", type=int, default=512)
     ap.add_argument("--lmax", type=int, default=None)
@@ -597,6 +598,7 @@ def main():
         "by_precision": {k: {"value": round(v["value"], 3), "ms_per_step": round(v["ms_per_step"], 3),
                              "plan_init_s": round(v["init_s"], 2),
                              "component_maps_per_s": round(3 * v["value"], 2),
+                             "step_ms_median_min_max": [round(v["step_ms"][q], 3) for q in ("median", "min", "max")],
                              "stages_ms_per_step": {s: round(t / args.steps, 3) for s, (t, c) in v["stages"].items() if c},
                              **({"accuracy_vs_fp64": acc[k]} if k in acc else {})}
                          for k, v in results.items()},
