@@ -128,7 +128,9 @@ __device__ __forceinline__ void dft<4>(double2* v)
 // One radix-R Stockham step over nseq sequences of length n held in LDS, in
 // place: every thread first reads all of its butterfly inputs, then (after a
 // barrier) writes all outputs.  Ns = product of the radices already applied.
-// For radices 2 and 4 the twiddle loads are issued before the LDS reads so that
+// One twiddle load per butterfly (w^k; the higher powers are products: the
+// gathers, not the arithmetic, are the latency).  For radices 2 and 4 the
+// twiddle loads are issued before the LDS reads so that
 // their latency overlaps the reads and the barrier (the odd radices, rarer and
 // with more registers per butterfly, load them after the barrier); butterfly
 // indices past the end are clamped (reads only), so no load sits in a branch.
@@ -152,7 +154,7 @@ __device__ __forceinline__ void stockham_step(double2* buf, int nseq, int n, int
         js[q] = j;
         if (PRE) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) wt[q][r - 1] = tw[r * k * unit];
+            for (int r = 1; r < R; ++r) wt[q][r - 1] = r == 1 ? tw[k * unit] : cmul(wt[q][r - 2], wt[q][0]);
         }
     }
 #pragma unroll
@@ -168,7 +170,7 @@ __device__ __forceinline__ void stockham_step(double2* buf, int nseq, int n, int
             const int k = j - dns.div(j) * Ns;
             if (!PRE) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) wt[q][r - 1] = tw[r * k * unit];
+                for (int r = 1; r < R; ++r) wt[q][r - 1] = r == 1 ? tw[k * unit] : cmul(wt[q][r - 2], wt[q][0]);
             }
 #pragma unroll
             for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], wt[q][r - 1]);
