@@ -231,7 +231,9 @@ class Executor:
             plan.set_nmaps(n)
             fn(slot_in, slot_out, stream=s)
             return
-        # graph per (plan, direction, precision, width) over the whole bucket of slots
+        # graph per (plan, direction, precision, width) over the whole bucket of
+        # slots; a bucket wider than the plan's slots covers just the slots
+        width = min(width, plan.capacity)
         key = (id(plan), direction, precision, width)
         g = self._graphs.get(key)
         if g is None:

@@ -111,6 +111,25 @@ def test_graph_replay_matches_eager(mods):
     s.close()
 
 
+def test_graph_replay_with_slots_off_the_bucket_grid(mods):
+    """40 slots: a batch of 36 map sets falls in the 64-wide bucket, wider than
+    the plan; the graph then covers the 40 slots."""
+    serve, sht, torch = mods
+    note("serve: graph replay, 40 slots")
+    s = serve.Server(20e9, max_slots=40, executor=serve.Executor(nstreams=1, graphs=True))
+    for rnd in range(2):
+        reqs = [make_request(serve, torch, 16, 2, "alm2map", "fp64", 12, 900 + 10 * rnd + i) for i in range(3)]
+        for r in reqs:
+            s.submit(r)
+        s.drain()
+        torch.cuda.synchronize()
+        for r in reqs:
+            assert r.status == 0
+            assert np.all(rel_rms(from_dev(r.out), alone(sht, torch, r)) <= 1e-12), (rnd, r.key)
+    assert any(b[2] == 36 for b in s.batches)
+    s.close()
+
+
 def test_small_budget_evicts_and_serves(mods):
     serve, sht, torch = mods
     note("serve: small budget")
