@@ -97,8 +97,14 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
     int rc0 = first_chunk(a, m, nchunk, lend);
     split_range(a, sk, rc0, nchunk);
     if (rc0 < nchunk) {
+        // Ring chunks run from the equator toward the pole (chunk q of the loop is
+        // rsum - q): every l tile of an m needs the equator chunks, so the
+        // workgroups of one m, launched together, stream the same ring rows in
+        // step and share them in L2 instead of each reading its own from HBM.
+        const int rsum = rc0 + nchunk - 1;
         const T* Xm = xptr<T>(a, 0) + (int64_t)m * a.nring * a.ldx + col;
         auto seed_of = [&](Seed<0>& s, int rc) {
+            rc = rsum - rc;
             const int r = min(rc * M_TR + frl, a.rn - 1);
             seed_load(s, a, sbase + r, r);
         };
@@ -111,6 +117,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
         // ring operands of one K-step: north / south rows
         T xb[2][2][NU];  // [K-step parity][north, south][column tile]
         auto load_x = [&](int rc, int ks, T (&d)[2][NU]) {
+            rc = rsum - rc;
             const int r = min(rc * M_TR + 4 * ks + (lane >> 4), a.rn - 1);
             const T* pn = Xm + (int64_t)r * a.ldx;
             const T* ps = Xm + (int64_t)(a.nring - 1 - r) * a.ldx;
@@ -125,7 +132,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
         Rec<0> f;
         seed_of(sd, rc0);
         if (filler) {
-            f.start(sd, m2a_weight(a, rc0 * M_TR + frl));
+            f.start(sd, m2a_weight(a, (rsum - rc0) * M_TR + frl));
             auto em = emit_to(0);
             rec_all(f, cp, cnt, em);
         }
@@ -135,7 +142,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
         for (int rc = rc0; rc < nchunk; ++rc) {
             const int b = (rc - rc0) & 1;
             const int rcn = min(rc + 1, nchunk - 1);
-            if (filler) f.start(sd, m2a_weight(a, rcn * M_TR + frl));
+            if (filler) f.start(sd, m2a_weight(a, (rsum - rcn) * M_TR + frl));
             auto em = emit_to(b ^ 1);
             const T* lb_ = lam + b * BUF;
             static_for<0, KS>([&](auto ki) {
@@ -237,10 +244,16 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
     int rc0 = first_chunk(a, m, nchunk, lend);
     split_range(a, sk, rc0, nchunk);
     if (rc0 < nchunk) {
+        // Ring chunks run from the equator toward the pole (chunk q of the loop is
+        // rsum - q): every l tile of an m needs the equator chunks, so the
+        // workgroups of one m, launched together, stream the same ring rows in
+        // step and share them in L2 instead of each reading its own from HBM.
+        const int rsum = rc0 + nchunk - 1;
         const int64_t xm = (int64_t)m * a.nring * a.ldx;
         const T* XQ = xptr<T>(a, 1) + xm + col;
         const T* XU = xptr<T>(a, 2) + xm + pcol;
         auto seed_of = [&](Seed<2>& s, int rc) {
+            rc = rsum - rc;
             const int r = min(rc * M_TR + frl, a.rn - 1);
             seed_load(s, a, sbase + r, r);
         };
@@ -252,6 +265,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
         };
         T xb[2][4][NU];  // [K-step parity][Q_N, Q_S, U_N, U_S (partner column)][column tile]
         auto load_x = [&](int rc, int ks, T (&d)[4][NU]) {
+            rc = rsum - rc;
             const int r = min(rc * M_TR + 4 * ks + (lane >> 4), a.rn - 1);
             const int64_t on = (int64_t)r * a.ldx, os = (int64_t)(a.nring - 1 - r) * a.ldx;
 #pragma unroll
@@ -267,7 +281,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
         Rec<2> f;
         seed_of(sd, rc0);
         if (filler) {
-            f.start(sd, m2a_weight(a, rc0 * M_TR + frl));
+            f.start(sd, m2a_weight(a, (rsum - rc0) * M_TR + frl));
             auto em = emit_to(0);
             rec_all(f, cp, cnt, em);
         }
@@ -277,7 +291,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
         for (int rc = rc0; rc < nchunk; ++rc) {
             const int b = (rc - rc0) & 1;
             const int rcn = min(rc + 1, nchunk - 1);
-            if (filler) f.start(sd, m2a_weight(a, rcn * M_TR + frl));
+            if (filler) f.start(sd, m2a_weight(a, (rsum - rcn) * M_TR + frl));
             auto em = emit_to(b ^ 1);
             const T* fb = fpm + b * BUF;
             static_for<0, KS>([&](auto ki) {

@@ -172,8 +172,14 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
     int rc0 = first_chunk(a, m, nchunk, lend);
     split_range(a, sk, rc0, nchunk);
     if (rc0 < nchunk) {
+        // Ring chunks run from the equator toward the pole (chunk q of the loop is
+        // rsum - q): every l tile of an m needs the equator chunks, so the
+        // workgroups of one m, launched together, stream the same ring rows in
+        // step and share them in L2 instead of each reading its own from HBM.
+        const int rsum = rc0 + nchunk - 1;
         const float* Xm = fptr(a.X, 0, a.xcomp) + (int64_t)m * a.nring * a.ldx + col;
         auto seed_of = [&](Seed<0>& s, int rc) {
+            rc = rsum - rc;
             const int r = min(rc * M_TR + frl, a.rn - 1);
             seed_load(s, a, sbase + r, r);
         };
@@ -187,6 +193,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
         const Rows xb(static_cast<const float*>(a.X) + (int64_t)m * a.nring * a.ldx, (int64_t)a.nring * a.ldx * 4);
         const int rstep = (int)a.ldx * 4;
         auto load_x = [&](int rc) {
+            rc = rsum - rc;
             if (xb.ok && (rc + 1) * M_TR <= a.rn) {  // whole chunk inside the hemisphere
                 const int vn = ((rc * M_TR + k0) * (int)a.ldx + col) * 4;
                 const int vs = ((a.nring - 1 - (rc * M_TR + k0 + 7)) * (int)a.ldx + col) * 4;
@@ -216,7 +223,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
         Rec<0> f;
         seed_of(sd, rc0);
         if (filler) {
-            f.start(sd, m2a_weight(a, rc0 * M_TR + frl));
+            f.start(sd, m2a_weight(a, (rsum - rc0) * M_TR + frl));
             auto em = emit_to(0);
             rec_all(f, cp, cnt, em);
         }
@@ -226,7 +233,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
         for (int rc = rc0; rc < nchunk; ++rc) {
             const int b = (rc - rc0) & 1;
             const int rcn = min(rc + 1, nchunk - 1);
-            if (filler) f.start(sd, m2a_weight(a, rcn * M_TR + frl));
+            if (filler) f.start(sd, m2a_weight(a, (rsum - rcn) * M_TR + frl));
             // operands of this chunk: north + south and north - south, split
             v8bf bh[2][NU], bl[2][NU];
 #pragma unroll
@@ -324,10 +331,16 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
     int rc0 = first_chunk(a, m, nchunk, lend);
     split_range(a, sk, rc0, nchunk);
     if (rc0 < nchunk) {
+        // Ring chunks run from the equator toward the pole (chunk q of the loop is
+        // rsum - q): every l tile of an m needs the equator chunks, so the
+        // workgroups of one m, launched together, stream the same ring rows in
+        // step and share them in L2 instead of each reading its own from HBM.
+        const int rsum = rc0 + nchunk - 1;
         const int64_t xm = (int64_t)m * a.nring * a.ldx;
         const float* XQ = fptr(a.X, 1, a.xcomp) + xm + col;
         const float* XU = fptr(a.X, 2, a.xcomp) + xm + pcol;
         auto seed_of = [&](Seed<2>& s, int rc) {
+            rc = rsum - rc;
             const int r = min(rc * M_TR + frl, a.rn - 1);
             seed_load(s, a, sbase + r, r);
         };
@@ -343,6 +356,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
         const Rows ub(static_cast<const float*>(a.X) + 2 * a.xcomp + xm, xblk * 4);
         const int rstep = (int)a.ldx * 4;
         auto load_x = [&](int rc) {
+            rc = rsum - rc;
             if (qb.ok && (rc + 1) * M_TR <= a.rn) {  // whole chunk inside the hemisphere
                 const int rn0 = (rc * M_TR + k0) * (int)a.ldx * 4;
                 const int rs0 = (a.nring - 1 - (rc * M_TR + k0 + 7)) * (int)a.ldx * 4;
@@ -375,7 +389,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
         Rec<2> f;
         seed_of(sd, rc0);
         if (filler) {
-            f.start(sd, m2a_weight(a, rc0 * M_TR + frl));
+            f.start(sd, m2a_weight(a, (rsum - rc0) * M_TR + frl));
             auto em = emit_to(0);
             rec_all(f, cp, cnt, em);
         }
@@ -385,7 +399,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
         for (int rc = rc0; rc < nchunk; ++rc) {
             const int b = (rc - rc0) & 1;
             const int rcn = min(rc + 1, nchunk - 1);
-            if (filler) f.start(sd, m2a_weight(a, rcn * M_TR + frl));
+            if (filler) f.start(sd, m2a_weight(a, (rsum - rcn) * M_TR + frl));
             // SX, DX, SY, DY split
             v8bf bh[4][NU], bl[4][NU];
 #pragma unroll
