@@ -551,8 +551,8 @@ def main():
                     help="run one plain device copy of this many GiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU split "
-              "(map batch or m-range per GPU) is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the split over several GPUs "
+              "(map batch or m range per GPU) is not built.", file=sys.stderr)
         sys.exit(2)
     if args.lmax is None:
         args.lmax = 3 * args.nside - 1
