@@ -106,8 +106,13 @@ size_t sht_plan_table_bytes(sht_plan plan);
 long long sht_plan_ring_rows(sht_plan plan);
 
 /* Use caller-owned device memory of at least sht_plan_workspace_bytes() bytes as
- * workspace (the plan frees its own).  Passing NULL returns to a plan-owned
- * workspace. */
+ * workspace (the plan frees its own).  dev_ptr must be 256-byte aligned, as
+ * hipMalloc returns it: the operand rows inside are laid out for aligned vector
+ * access.  A misaligned or too small buffer gives SHT_ERR_ARG and leaves the plan
+ * as it was.  The buffer must stay allocated while the plan uses it; a later
+ * sht_plan_set_chunk or sht_plan_set_precision that needs more gives SHT_ERR_ARG
+ * and keeps the old setting.
+ * Passing NULL returns to a plan-owned workspace. */
 int sht_plan_set_workspace(sht_plan plan, void* dev_ptr, size_t bytes);
 
 /* Backward transform (alm -> maps) of the current batch.  Device pointers. */

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -1036,8 +1037,14 @@ int sht_plan_set_precision(sht_plan p, int prec)
 {
     if (!p) return fail(SHT_ERR_ARG, "null plan");
     if (prec != SHT_FP64 && prec != SHT_FP32 && prec != SHT_BF16X3) return fail(SHT_ERR_ARG, "unknown precision");
+    const int old = p->prec;
     p->prec = prec;
-    return prep(p);
+    const int rc = prep(p);
+    if (rc != SHT_OK) {  // as in sht_plan_set_chunk: keep what the workspace was sized for
+        p->prec = old;
+        (void)prep(p);
+    }
+    return rc;
 }
 
 int sht_plan_set_stream(sht_plan p, void* s)
@@ -1059,8 +1066,16 @@ int sht_plan_set_chunk(sht_plan p, int c)
 {
     if (!p) return fail(SHT_ERR_ARG, "null plan");
     if (c < 1) return fail(SHT_ERR_ARG, "chunk must be >= 1");
+    const int old = p->chunk;
     p->chunk = std::min(c, p->cap);
-    return prep(p);
+    const int rc = prep(p);
+    if (rc != SHT_OK) {
+        // keep the chunk the workspace was sized for (a caller workspace too small
+        // for the new one, or a failed allocation); the error of the request stays
+        p->chunk = old;
+        (void)prep(p);
+    }
+    return rc;
 }
 
 size_t sht_plan_workspace_bytes(sht_plan p) { return p ? ws_need(p) : 0; }
@@ -1078,6 +1093,7 @@ long long sht_plan_ring_rows(sht_plan p)
 int sht_plan_set_workspace(sht_plan p, void* ptr, size_t bytes)
 {
     if (!p) return fail(SHT_ERR_ARG, "null plan");
+    if (ptr && ((uintptr_t)ptr & 255) != 0) return fail(SHT_ERR_ARG, "workspace must be 256-byte aligned");
     if (ptr && bytes < ws_need(p)) return fail(SHT_ERR_ARG, "workspace too small");
     if (p->ws && p->ws_owned) (void)hipFree(p->ws);
     p->ws = ptr;

@@ -135,6 +135,21 @@ class Plan:
     def workspace_bytes(self) -> int:
         return int(lib().sht_plan_workspace_bytes(self._h))
 
+    def set_workspace(self, buf=None, nbytes: int | None = None) -> None:
+        """Use caller device memory as workspace: a CUDA tensor (kept referenced
+        while the plan uses it) or a raw pointer with nbytes; None returns to a
+        plan-owned workspace."""
+        if buf is None:
+            _check(lib().sht_plan_set_workspace(self._h, None, 0))
+            self._ws_ref = None
+            return
+        if isinstance(buf, int):
+            ptr, n = buf, int(nbytes)
+        else:
+            ptr, n = buf.data_ptr(), int(nbytes if nbytes is not None else buf.numel() * buf.element_size())
+        _check(lib().sht_plan_set_workspace(self._h, ctypes.c_void_p(ptr), n))
+        self._ws_ref = buf
+
     def table_bytes(self) -> int:
         return int(lib().sht_plan_table_bytes(self._h))
 
