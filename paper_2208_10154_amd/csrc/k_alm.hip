@@ -78,11 +78,28 @@ __global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
     }
     __syncthreads();
     T* A = static_cast<T*>(a.A) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
-    for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
-        const int li = e / (2 * TK), c = e % (2 * TK);
-        if (l0 + li > L) continue;
-        if constexpr (__is_same(T, uint32_t)) A[(int64_t)li * a.ldx + c] = pack_bf16_pair((float)tile[li][c]);
-        else A[(int64_t)li * a.ldx + c] = (T)tile[li][c];
+    if constexpr (sizeof(T) == 4) {
+        // four columns per lane, one 16-byte store (4-byte stores left the kernel
+        // latency-bound); rows start on 64-column boundaries of a 256-byte aligned
+        // workspace, so every vector is aligned
+        struct alignas(16) V4 { T v[4]; };
+        for (int e = threadIdx.x; e < 2 * TK * TLB / 4; e += NT) {
+            const int li = e / (TK / 2), c = 4 * (e % (TK / 2));
+            if (l0 + li > L) continue;
+            V4 w;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if constexpr (__is_same(T, uint32_t)) w.v[q] = pack_bf16_pair((float)tile[li][c + q]);
+                else w.v[q] = (T)tile[li][c + q];
+            }
+            *reinterpret_cast<V4*>(A + (int64_t)li * a.ldx + c) = w;
+        }
+    } else {
+        for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+            const int li = e / (2 * TK), c = e % (2 * TK);
+            if (l0 + li > L) continue;
+            A[(int64_t)li * a.ldx + c] = (T)tile[li][c];
+        }
     }
 }
 
@@ -104,9 +121,22 @@ __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
     const int l0 = lb + lt * TLB;
     const int64_t csz = (int64_t)(L + 1) * (L + 1);
     const T* A = static_cast<const T*>(a.A) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
-    for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
-        const int li = e / (2 * TK), c = e % (2 * TK);
-        tile[li][c] = (l0 + li <= L) ? (double)A[(int64_t)li * a.ldx + c] : 0.0;
+    if constexpr (sizeof(T) == 4) {
+        // four columns per lane, one 16-byte load (aligned as in k_to_mmajor)
+        for (int e = threadIdx.x; e < 2 * TK * TLB / 4; e += NT) {
+            const int li = e / (TK / 2), c = 4 * (e % (TK / 2));
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (l0 + li <= L) v = *reinterpret_cast<const float4*>(A + (int64_t)li * a.ldx + c);
+            tile[li][c] = v.x;
+            tile[li][c + 1] = v.y;
+            tile[li][c + 2] = v.z;
+            tile[li][c + 3] = v.w;
+        }
+    } else {
+        for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+            const int li = e / (2 * TK), c = e % (2 * TK);
+            tile[li][c] = (l0 + li <= L) ? (double)A[(int64_t)li * a.ldx + c] : 0.0;
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
