@@ -206,39 +206,59 @@ def eb_leg(sht, args, precs, alm, maps, alm_out):
     return out
 
 
-LEG_SOURCES = ["paper_2208_10154_amd/csrc/k_leg.hip", "paper_2208_10154_amd/csrc/k_leg_bf16.hip",
-               "paper_2208_10154_amd/csrc/leg_rec.h", "paper_2208_10154_amd/csrc/leg_common.h",
-               "paper_2208_10154_amd/csrc/sht_internal.h"]
+# Sources each Legendre kernel family is built from: a committed counter record
+# applies only while the family's sources hash to the profiled version.
+LEG_COMMON = ["paper_2208_10154_amd/csrc/leg_rec.h", "paper_2208_10154_amd/csrc/leg_common.h",
+              "paper_2208_10154_amd/csrc/sht_internal.h"]
+LEG_SOURCES = {"fp": ["paper_2208_10154_amd/csrc/k_leg.hip"] + LEG_COMMON,
+               "bf": ["paper_2208_10154_amd/csrc/k_leg_bf16.hip"] + LEG_COMMON}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+MFMA_FILE = os.path.join(ROOT, "profiles", "mfma.json")
 
 
-def leg_source_hash() -> str:
+def leg_family(kernel: str) -> str:
+    return "bf" if "_bf" in kernel else "fp"
+
+
+def leg_source_hash(family: str = "fp") -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in LEG_SOURCES:
+    for f in LEG_SOURCES[family]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, nside: int, lmax: int, per_launch_maps: int):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if it
-    was taken on the current kernel sources at this workload (else None)."""
+def counter_record(path: str, kernel: str, nside: int, lmax: int, per_launch_maps: int):
+    """The committed counter record of `kernel`, if it was taken on the kernel's
+    current sources at this workload (else None)."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     e = rec.get(kernel)
-    if not e or e.get("source_hash") != leg_source_hash():
+    if not e or e.get("source_hash") != leg_source_hash(leg_family(kernel)):
         return None
     if (e.get("nside"), e.get("lmax"), e.get("maps_per_launch")) != (nside, lmax, per_launch_maps):
         return None
-    return e.get("bytes_per_launch")
+    return e
+
+
+def measured_traffic(kernel: str, nside: int, lmax: int, per_launch_maps: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary."""
+    e = counter_record(TRAFFIC_FILE, kernel, nside, lmax, per_launch_maps)
+    return e.get("bytes_per_launch") if e else None
 
 
 def roofline(args, prec, res):
-    """Dominant Legendre kernel's achieved FLOP rate from the live stage timings."""
+    """Dominant Legendre kernel's achieved FLOP rate from the live stage timings.
+
+    `achieved` counts the folded work (both hemispheres folded, every ring): an
+    effective rate, since the kernels skip the ring chunks where the Legendre
+    values are negligible.  `executed` divides the MFMA instructions the kernel
+    actually issues per launch (committed counter record, current sources only)
+    by the same live time, which is the occupancy of the matrix pipe."""
     st = res["stages"]
     cand = {k: v for k, v in st.items() if k.startswith(("m2a", "a2m")) and v[1] > 0}
     name = max(cand, key=lambda k: cand[k][0])
@@ -248,14 +268,43 @@ def roofline(args, prec, res):
     achieved = flops_per_step * args.steps / (ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
     kname = "k_" + name + {"fp64": "<double>", "fp32": "<float>", "bf16x3": "_bf"}[prec]
-    return {
+    out = {
         "kernel": kname,
         "bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
         "traffic": measured_traffic(kname, args.nside, args.lmax, args.chunk),
         "launches": launches, "avg_launch_ms": round(ms / launches, 3),
         "flops_per_launch": flops_per_step * args.steps / launches,
+        "achieved_counts": "folded flops (all rings of a hemisphere) per launch / live launch time",
     }
+    e = counter_record(MFMA_FILE, kname, args.nside, args.lmax, args.chunk)
+    if e and args.nmaps % args.chunk == 0:
+        ex = e["mfma_insts_per_launch"] * e["flops_per_inst"] / (ms / launches * 1e-3) / 1e12
+        out["executed"] = {"flops_per_launch": e["mfma_insts_per_launch"] * e["flops_per_inst"],
+                           "achieved": round(ex, 2), "frac": round(ex / peak, 4),
+                           "mfma_busy_profiled": e["mfma_busy"], "source": e["summary"]}
+    return out
+
+
+def layout_rate(args, prec, res):
+    """Coefficient layout stage (compact a_lm <-> m-major rows, both directions):
+    algorithmic HBM bytes (the compact FP64 side and the operand rows, each
+    moved once) over its measured time."""
+    es = 8 if prec == "fp64" else 4
+    L, n = args.lmax, args.nmaps
+    c = min(args.chunk, n)
+    ldx = 64 if c <= 32 else 2 * ((c + 63) // 64 * 64)
+    rows0 = (L + 1) * (L + 2) // 2
+    rows2 = sum(L + 1 - max(m, 2) for m in range(L + 1))
+    per_dir = 8 * (L + 1) ** 2 * 3 * n + (rows0 + 2 * rows2) * ldx * es * (n // c)
+    tot = 2 * per_dir * args.steps
+    ms, k = res["stages"]["alm_layout"]
+    if not k:
+        return None
+    gbs = tot / (ms * 1e-3) / 1e9
+    return {"GB/s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 3),
+            "bytes_per_step": per_dir * 2,
+            "counters": "profiles/k_layout_nside512_x125_hbm_counters.md"}
 
 
 def fft_rate(args, prec, res):
@@ -605,6 +654,7 @@ def main():
         "roofline": roofline(args, head, r),
         "paper_form_tflops_equiv": round(2 * paper_form_flops(args.nside, L) * n / (r["ms_per_step"] * 1e-3) / 1e12, 2),
         "fft_hbm": fft_rate(args, head, r),
+        "layout_hbm": layout_rate(args, head, r),
     }
     if "fp64" in results:
         line["mixed_over_fp64"] = {k: round(v["value"] / results["fp64"]["value"], 3) for k, v in results.items() if k != "fp64"}

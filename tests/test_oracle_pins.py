@@ -277,6 +277,26 @@ def test_immediate_iteration_beats_traditional_on_band_limited_maps():
         assert np.all(np.diff(rg) < 0)
 
 
+def test_iteration_modes_agree_below_two_nside():
+    """Below lmax = 2 nside the two iteration modes of Sec. 4 converge alike: after
+    three rounds the coefficient errors and residuals of the immediate sweep and of
+    the traditional iteration agree to within 3% (both fall by an order of
+    magnitude per round), unlike the band limit 3 nside - 1 of the test above,
+    where the immediate sweep wins clearly.  The paper reports the traditional
+    mode as slightly better in this regime on its own simulations; on these
+    band-limited Gaussian inputs the immediate sweep is not worse (its residual is
+    0-2% lower), so that observation itself is not reproduced here."""
+    for nside, L, pol in ((8, 15, True), (16, 23, False)):
+        at, maps = _band_limited(nside, L, 2, pol, 98)
+        aj, rj = oracle.map2alm_iter(nside, L, maps, 3, pol=pol)
+        ag, rg = oracle.map2alm_immediate(nside, L, maps, 3, pol=pol)
+        err = lambda a: np.sqrt(np.sum(np.abs(a - at) ** 2) / np.sum(np.abs(at) ** 2))
+        assert abs(err(ag) / err(aj) - 1) < 0.03, (err(ag), err(aj))
+        assert np.all(np.abs(rg / rj - 1) < 0.03), (rg, rj)
+        assert rg[-1] <= rj[-1] * (1 + 1e-9)
+        assert np.all(rj[1:] < 0.2 * rj[:-1]) and np.all(rg[1:] < 0.2 * rg[:-1])
+
+
 def test_immediate_iteration_brute_force():
     """The sweep written out literally for a tiny map: every (l, m) update as a
     pixel sum with scipy's Y_lm, the residual corrected pixel by pixel after each
