@@ -60,7 +60,10 @@ enum sht_status {
 enum sht_precision {
     SHT_FP64 = 0,   /* FP64 MFMA, FP64 ring Fourier coefficients */
     SHT_FP32 = 1,   /* FP32 MFMA, FP32 ring Fourier coefficients */
-    SHT_BF16X3 = 2  /* split-BF16 (hi*hi + hi*lo + lo*hi) MFMA accumulated in FP32 */
+    SHT_BF16X3 = 2  /* split BF16: each operand (rounded to FP32) as three bf16 numbers
+                     * hi + mid + lo, products from the six partial products of order
+                     * >= 2^-16 on the BF16 matrix cores, accumulated in FP32 (the
+                     * accuracy of an FP32 contraction) */
 };
 
 /* Create a plan for HEALPix resolution nside, band limit lmax and spin 0 (T maps)

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
         tile[li][2 * kk + part] = v;
     }
     __syncthreads();
-    T* A = static_cast<T*>(a.A) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
+    T* A = static_cast<T*>(a.Aop) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
     if constexpr (sizeof(T) == 4) {
         // four columns per lane, one 16-byte store (4-byte stores left the kernel
         // latency-bound); rows start on 64-column boundaries of a 256-byte aligned
@@ -88,11 +88,19 @@ __global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
             if (l0 + li > L) continue;
             V4 w;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if constexpr (__is_same(T, uint32_t)) w.v[q] = pack_bf16_pair((float)tile[li][c + q]);
-                else w.v[q] = (T)tile[li][c + q];
-            }
+            for (int q = 0; q < 4; ++q) w.v[q] = (T)tile[li][c + q];
             *reinterpret_cast<V4*>(A + (int64_t)li * a.ldx + c) = w;
+        }
+    } else if constexpr (__is_same(T, uint64_t)) {
+        // split-BF16 words: two columns per lane, one 16-byte store
+        struct alignas(16) W2 { uint64_t v[2]; };
+        for (int e = threadIdx.x; e < 2 * TK * TLB / 2; e += NT) {
+            const int li = e / TK, c = 2 * (e % TK);
+            if (l0 + li > L) continue;
+            W2 w;
+            w.v[0] = pack_bf16_triple((float)tile[li][c]);
+            w.v[1] = pack_bf16_triple((float)tile[li][c + 1]);
+            *reinterpret_cast<W2*>(A + (int64_t)li * a.ldx + c) = w;
         }
     } else {
         for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
@@ -106,8 +114,8 @@ __global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
 // m-major rows -> compact (FP64): alm = scale * A (or alm += scale * A).
 // kind 1 converts B' back: Re a_B = Im B', Im a_B = -Re B'.  Spin-2 components
 // have no l < 2 coefficients: the first tile of m < 2 clears them (store mode).
-// TO != void: also rewrite the rows in place as the alm2map operand of the same
-// update, in TO's format (see k_level_rows), from the tile already in LDS.
+// TO != void: also write scale * rows as the alm2map operand of the same update
+// (at Aop, in TO's format), from the tile already in LDS.
 template <typename T, typename TO = void>
 __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
 {
@@ -163,15 +171,16 @@ __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
         if (a.accumulate) base[o] += v; else base[o] = v;
     }
     if constexpr (!__is_same(TO, void)) {
-        // tile reads all happened before the barrier above
-        TO* out = static_cast<TO*>(a.A) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
+        // tile reads all happened before the barrier above (Aop is A itself
+        // unless the operand words have a region of their own)
+        TO* out = static_cast<TO*>(a.Aop) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
         const int drop = (m == 0) ? (kind == 0 ? 1 : 0) : -1;
         for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
             const int li = e / (2 * TK), c = e % (2 * TK);
             if (l0 + li > L) continue;
             const bool keep = (c & 1) != drop && kb * TK + (c >> 1) < a.nmaps;
             const double v = keep ? a.scale * tile[li][c] : 0.0;
-            if constexpr (__is_same(TO, uint32_t)) out[(int64_t)li * a.ldx + c] = pack_bf16_pair((float)v);
+            if constexpr (__is_same(TO, uint64_t)) out[(int64_t)li * a.ldx + c] = pack_bf16_triple((float)v);
             else out[(int64_t)li * a.ldx + c] = (TO)v;
         }
     }
@@ -186,14 +195,11 @@ __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
     }
 }
 
-// Immediate iteration: the map2alm rows of the listed m become the alm2map
-// operand of the update, scale * A, in place.  The parts the compact storage has
-// no slot for (Im of T and E at m = 0, Re of B' = i a_B at m = 0) and the padding
-// maps are zeroed, so the synthesis sees exactly the update the compact alm got.
-// TI: element type written by map2alm; TO: read by alm2map (split-BF16 words
-// for BF16x3, same size as the FP32 rows they replace).  scale = 0 clears the
-// rows without reading them (before a split map2alm adds into them).
-template <typename TI, typename TO>
+// Immediate iteration: the map2alm rows of the listed m become scale * A, in
+// place; the parts the compact storage has no slot for (Im of T and E at m = 0,
+// Re of B' = i a_B at m = 0) and the padding maps are zeroed.  scale = 0 clears
+// the rows without reading them (before a split map2alm adds into them).
+template <typename T>
 __global__ __launch_bounds__(NT) void k_level_rows(AlmArgs a)
 {
     const int comp = a.comp0 + blockIdx.y;
@@ -204,17 +210,14 @@ __global__ __launch_bounds__(NT) void k_level_rows(AlmArgs a)
     const int lb = lbase(a.spin, m);
     const int l0 = lb + lt * TLB;
     const int64_t o0 = comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
-    const TI* in = static_cast<const TI*>(a.A) + o0;
-    TO* out = static_cast<TO*>(a.A) + o0;
+    T* rows = static_cast<T*>(a.A) + o0;
     const int drop = (m == 0) ? (kind == 0 ? 1 : 0) : -1;  // part without a compact slot
     for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
         const int li = e / (2 * TK), c = e % (2 * TK);
         if (l0 + li > L) continue;
         const int64_t o = (int64_t)li * a.ldx + c;
         const bool keep = (c & 1) != drop && kb * TK + (c >> 1) < a.nmaps;
-        const double v = (keep && a.scale != 0.0) ? a.scale * (double)in[o] : 0.0;
-        if constexpr (__is_same(TO, uint32_t)) out[o] = pack_bf16_pair((float)v);
-        else out[o] = (TO)v;
+        rows[o] = (keep && a.scale != 0.0) ? (T)(a.scale * (double)rows[o]) : (T)0;
     }
 }
 
@@ -242,9 +245,8 @@ hipError_t launch_zero_strided(double* base, int rows, int64_t stride, int64_t l
 hipError_t launch_level_rows(const AlmArgs& a, int ncompl, int prec, hipStream_t st)
 {
     dim3 grid(a.ntiles * a.kblocks, ncompl);
-    if (prec == 0) hipLaunchKernelGGL((k_level_rows<double, double>), grid, dim3(NT), 0, st, a);
-    else if (prec == 2) hipLaunchKernelGGL((k_level_rows<float, uint32_t>), grid, dim3(NT), 0, st, a);
-    else hipLaunchKernelGGL((k_level_rows<float, float>), grid, dim3(NT), 0, st, a);
+    if (prec == 0) hipLaunchKernelGGL(k_level_rows<double>, grid, dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL(k_level_rows<float>, grid, dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
@@ -252,7 +254,7 @@ hipError_t launch_level_commit(const AlmArgs& a, int ncompl, int prec, hipStream
 {
     dim3 grid(a.ntiles * a.kblocks, ncompl);
     if (prec == 0) hipLaunchKernelGGL((k_from_mmajor<double, double>), grid, dim3(NT), 0, st, a);
-    else if (prec == 2) hipLaunchKernelGGL((k_from_mmajor<float, uint32_t>), grid, dim3(NT), 0, st, a);
+    else if (prec == 2) hipLaunchKernelGGL((k_from_mmajor<float, uint64_t>), grid, dim3(NT), 0, st, a);
     else hipLaunchKernelGGL((k_from_mmajor<float, float>), grid, dim3(NT), 0, st, a);
     return hipGetLastError();
 }
@@ -261,7 +263,7 @@ hipError_t launch_alm_to_mmajor(const AlmArgs& a, int ncompl, int prec, hipStrea
 {
     dim3 grid(a.ntiles * a.kblocks, ncompl);
     if (prec == 0) hipLaunchKernelGGL(k_to_mmajor<double>, grid, dim3(NT), 0, st, a);
-    else if (prec == 2) hipLaunchKernelGGL(k_to_mmajor<uint32_t>, grid, dim3(NT), 0, st, a);  // split-BF16 words
+    else if (prec == 2) hipLaunchKernelGGL(k_to_mmajor<uint64_t>, grid, dim3(NT), 0, st, a);  // split-BF16 words
     else hipLaunchKernelGGL(k_to_mmajor<float>, grid, dim3(NT), 0, st, a);
     return hipGetLastError();
 }

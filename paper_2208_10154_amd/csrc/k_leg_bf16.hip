@@ -1,16 +1,21 @@
 // Legendre contraction in split-BF16 precision (HIP, gfx950).
 //
 // The same products as k_leg.hip (the paper's per-m GEMMs, Sec. 2.2 and the 2x2
-// block of Sec. 2.3), with the operands held as pairs of bfloat16 numbers
-// x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) and every product formed as
-// hi*hi + hi*lo + lo*hi on the BF16 matrix cores with FP32 accumulation; the
-// dropped lo*lo term and the two roundings leave about 2^-17 relative error per
-// product.  The recursion, its exponent handling and the data in HBM are the
-// same as in the FP32 path (recursion FP64, workspace FP32), so only the MFMA
-// step changes precision.
+// block of Sec. 2.3), with every operand held as three bfloat16 numbers
+// x = hi + mid + lo (hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid)),
+// which carry the 24 significant bits of x rounded to FP32, and every product
+// formed on the BF16 matrix cores with FP32 accumulation from the six partial
+// products whose order is at most 2^-16 of the leading one:
+// hi*hi + hi*mid + mid*hi + hi*lo + mid*mid + lo*hi.  The three dropped terms are
+// below 2^-24 of the product, so the result has the accuracy of an FP32
+// contraction.  (Two pieces and three products leave about 4e-6 relative RMS
+// error per product, which the B mode, a tenth of the E power in typical skies,
+// amplifies past 1e-5.)  The recursion, its exponent handling and the data in
+// HBM are the same as in the FP32 path (recursion FP64, ring coefficients
+// FP32), so only the MFMA step changes precision.
 //
-// alm2map reads its coefficient rows already split, as 32-bit words holding hi
-// and lo (written so by the layout kernel), and only regroups them; map2alm
+// alm2map reads its coefficient rows already split, as 64-bit words holding hi,
+// mid and lo (written so by the layout kernel), and only regroups them; map2alm
 // splits the ring coefficients itself after folding the hemispheres (north +
 // south and north - south in FP32), since splitting north and south apart
 // would double its matrix products.
@@ -22,8 +27,8 @@
 // FP32 kernels.  Operand layouts (measured): A[i][k] from lane i + 16 (k / 8),
 // element k % 8 of the lane's 8-vector; B[k][j] likewise with j for i; result
 // row 4 (lane / 16) + v, column lane % 16.  The recursion tiles are stored
-// K-contiguous in LDS (rows of 32 values padded to 40), so each operand vector
-// is one 16-byte LDS read.
+// K-contiguous in LDS (rows of 32 values padded to 40), one plane per piece, so
+// each operand vector is one 16-byte LDS read.
 #include "leg_rec.h"
 
 namespace sht {
@@ -39,25 +44,44 @@ constexpr int RPP = SEG / NPH; // recursion rows per phase
 static_assert(RPP * NPH == SEG, "the fill of one segment is spread over the phases of a tile");
 constexpr int M_TR = 32;
 
-__device__ __forceinline__ v4f mfma3(v8bf ah, v8bf al, v8bf bh, v8bf bl, v4f c)
+// an operand split into three bf16 pieces
+struct S3 {
+    v8bf h, m, l;
+};
+
+// c + a*b over the six partial products of order >= 2^-16, small ones first
+__device__ __forceinline__ v4f mfma6(const S3& a, const S3& b, v4f c)
 {
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.m, b.m, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.m, b.h, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.m, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
 }
 
-// x = hi + lo for eight FP32 values
-__device__ __forceinline__ void split8(const float (&x)[8], v8bf& hi, v8bf& lo)
+// x = hi + mid + lo for eight FP32 values
+__device__ __forceinline__ void split8(const float (&x)[8], S3& s)
 {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const __bf16 h = (__bf16)x[e];
-        hi[e] = h;
-        lo[e] = (__bf16)(x[e] - (float)h);
+        const float r = x[e] - (float)h;
+        const __bf16 m = (__bf16)r;
+        s.h[e] = h;
+        s.m[e] = m;
+        s.l[e] = (__bf16)(r - (float)m);
     }
 }
 
 __device__ __forceinline__ v8bf lds8(const __bf16* p) { return *reinterpret_cast<const v8bf*>(p); }
+
+// the three planes of a split tile, PL elements apart
+template <int PL>
+__device__ __forceinline__ S3 lds3(const __bf16* p)
+{
+    return S3{lds8(p), lds8(p + PL), lds8(p + 2 * PL)};
+}
 
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
@@ -81,21 +105,26 @@ struct Rows {
     }
 };
 
-// hi and lo operand vectors of eight split-BF16 words (hi in the low half of
-// each word): two halves regrouped per output word
-__device__ __forceinline__ void unpack8(const uint32_t (&d)[8], v8bf& hi, v8bf& lo)
+// hi, mid and lo operand vectors of eight split-BF16 words (hi in bits 0-15,
+// mid in 16-31, lo in 32-47): halves regrouped per output word
+__device__ __forceinline__ void unpack8(const uint64_t (&d)[8], S3& s)
 {
-    v4u h, l;
+    v4u h, m, l;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        h[j] = __builtin_amdgcn_perm(d[2 * j + 1], d[2 * j], 0x05040100u);
-        l[j] = __builtin_amdgcn_perm(d[2 * j + 1], d[2 * j], 0x07060302u);
+        const uint32_t a0 = (uint32_t)d[2 * j], a1 = (uint32_t)d[2 * j + 1];
+        const uint32_t b0 = (uint32_t)(d[2 * j] >> 32), b1 = (uint32_t)(d[2 * j + 1] >> 32);
+        h[j] = __builtin_amdgcn_perm(a1, a0, 0x05040100u);
+        m[j] = __builtin_amdgcn_perm(a1, a0, 0x07060302u);
+        l[j] = __builtin_amdgcn_perm(b1, b0, 0x05040100u);
     }
-    hi = __builtin_bit_cast(v8bf, h);
-    lo = __builtin_bit_cast(v8bf, l);
+    s.h = __builtin_bit_cast(v8bf, h);
+    s.m = __builtin_bit_cast(v8bf, m);
+    s.l = __builtin_bit_cast(v8bf, l);
 }
 
-// Emitter for the split tiles: hi at d, lo LOFF further on, F- FOFF after F+.
+// Emitter for the split tiles: hi at d, mid and lo LOFF and 2 LOFF further on,
+// F- FOFF after F+.
 template <int STEP, int FOFF, int LOFF>
 struct EmitBF {
     __bf16* e0;
@@ -104,8 +133,11 @@ struct EmitBF {
     {
         const float f = (float)v;
         const __bf16 h = (__bf16)f;
+        const float r = f - (float)h;
+        const __bf16 m = (__bf16)r;
         d[0] = h;
-        d[LOFF] = (__bf16)(f - (float)h);
+        d[LOFF] = m;
+        d[2 * LOFF] = (__bf16)(r - (float)m);
     }
     template <int R>
     __device__ __forceinline__ void put(double v)
@@ -133,7 +165,7 @@ __device__ __forceinline__ const float* fptr(const void* base, int64_t comp, int
 template <int NU>
 __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
 {
-    constexpr int CLS = HALF * KP, HL = 2 * CLS, BUF = 2 * HL;
+    constexpr int CLS = HALF * KP, PL = 2 * CLS, BUF = 3 * PL;
     __shared__ __attribute__((aligned(16))) __bf16 lam[2 * BUF];
 
     int m, lt, ct;
@@ -184,7 +216,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
             seed_load(s, a, sbase + r, r);
         };
         auto emit_to = [&](int b) {
-            EmitBF<KP, 0, HL> e;
+            EmitBF<KP, 0, PL> e;
             e.e0 = lam + b * BUF + (SEG / 2) * fs * KP + frl;
             e.e1 = e.e0 + CLS;
             return e;
@@ -235,7 +267,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
             const int rcn = min(rc + 1, nchunk - 1);
             if (filler) f.start(sd, m2a_weight(a, (rsum - rcn) * M_TR + frl));
             // operands of this chunk: north + south and north - south, split
-            v8bf bh[2][NU], bl[2][NU];
+            S3 bs[2][NU];
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 float s8[8], d8[8];
@@ -244,8 +276,8 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
                     s8[e] = xr[0][u][e] + xr[1][u][e];
                     d8[e] = xr[0][u][e] - xr[1][u][e];
                 }
-                split8(s8, bh[0][u], bl[0][u]);
-                split8(d8, bh[1][u], bl[1][u]);
+                split8(s8, bs[0][u]);
+                split8(d8, bs[1][u]);
             }
             load_x(rcn);
             seed_of(sd, min(rc + 2, nchunk - 1));
@@ -257,9 +289,9 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
                 if constexpr ((P & 1) == 0) {
                     constexpr int cls = (P >> 2) & 1, t = (P >> 1) & 1;
                     const __bf16* q = lb_ + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
-                    const v8bf ah = lds8(q), al = lds8(q + HL);
+                    const S3 a3 = lds3<PL>(q);
 #pragma unroll
-                    for (int u = 0; u < NU; ++u) acc[cls][t][u] = mfma3(ah, al, bh[cls][u], bl[cls][u], acc[cls][t][u]);
+                    for (int u = 0; u < NU; ++u) acc[cls][t][u] = mfma6(a3, bs[cls][u], acc[cls][t][u]);
                 }
                 if (filler) rec_group<P, RPP>(f, cp, cnt, em);
             });
@@ -289,7 +321,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
 template <int NU, int EB>
 __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
 {
-    constexpr int CLS = HALF * KP, FOFF = 2 * CLS, HL = 2 * FOFF, BUF = 2 * HL;
+    constexpr int CLS = HALF * KP, FOFF = 2 * CLS, PL = 2 * FOFF, BUF = 3 * PL;
     __shared__ __attribute__((aligned(16))) __bf16 fpm[2 * BUF];
 
     int m, lt, ct;
@@ -345,7 +377,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
             seed_load(s, a, sbase + r, r);
         };
         auto emit_to = [&](int b) {
-            EmitBF<KP, FOFF, HL> e;
+            EmitBF<KP, FOFF, PL> e;
             e.e0 = fpm + b * BUF + po * CLS + (SEG / 2) * fs * KP + frl;
             e.e1 = fpm + b * BUF + (po ^ 1) * CLS + (SEG / 2) * fs * KP + frl;
             return e;
@@ -401,7 +433,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
             const int rcn = min(rc + 1, nchunk - 1);
             if (filler) f.start(sd, m2a_weight(a, (rsum - rcn) * M_TR + frl));
             // SX, DX, SY, DY split
-            v8bf bh[4][NU], bl[4][NU];
+            S3 bs[4][NU];
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 float o[4][8];
@@ -413,7 +445,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
                     o[3][e] = flip(xr[2][u][e] - xr[3][u][e], ysg);
                 }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) split8(o[i], bh[i][u], bl[i][u]);
+                for (int i = 0; i < 4; ++i) split8(o[i], bs[i][u]);
             }
             load_x(rcn);
             seed_of(sd, min(rc + 2, nchunk - 1));
@@ -425,19 +457,18 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
                 if constexpr ((P & 1) == 0) {
                     constexpr int cls = (P >> 2) & 1, t = (P >> 1) & 1;
                     const __bf16* q = fb + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
-                    const v8bf ph_ = lds8(q), pl = lds8(q + HL);               // F+
-                    const v8bf mh = lds8(q + FOFF), ml = lds8(q + FOFF + HL);  // F-
+                    const S3 fp = lds3<PL>(q), fm = lds3<PL>(q + FOFF);  // F+, F-
                     // even class: E = F+ SX + F- DY, B' = F+ SY + F- DX; odd: S <-> D
                     constexpr int X1 = cls ? 1 : 0, Y1 = cls ? 3 : 2, X2 = cls ? 0 : 1, Y2 = cls ? 2 : 3;
 #pragma unroll
                     for (int u = 0; u < NU; ++u) {
                         if constexpr (EB != 2) {
-                            accE[cls][t][u] = mfma3(ph_, pl, bh[X1][u], bl[X1][u], accE[cls][t][u]);
-                            accE[cls][t][u] = mfma3(mh, ml, bh[Y2][u], bl[Y2][u], accE[cls][t][u]);
+                            accE[cls][t][u] = mfma6(fp, bs[X1][u], accE[cls][t][u]);
+                            accE[cls][t][u] = mfma6(fm, bs[Y2][u], accE[cls][t][u]);
                         }
                         if constexpr (EB != 1) {
-                            accB[cls][t][u] = mfma3(ph_, pl, bh[Y1][u], bl[Y1][u], accB[cls][t][u]);
-                            accB[cls][t][u] = mfma3(mh, ml, bh[X2][u], bl[X2][u], accB[cls][t][u]);
+                            accB[cls][t][u] = mfma6(fp, bs[Y1][u], accB[cls][t][u]);
+                            accB[cls][t][u] = mfma6(fm, bs[X2][u], accB[cls][t][u]);
                         }
                     }
                 }
@@ -476,7 +507,7 @@ constexpr int A0_TR = 64;
 template <int NU>
 __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
 {
-    constexpr int CLS = A0_TR * KP, HL = 2 * CLS, BUF = 2 * HL;
+    constexpr int CLS = A0_TR * KP, PL = 2 * CLS, BUF = 3 * PL;
     __shared__ __attribute__((aligned(16))) __bf16 lam[2 * BUF];
     __shared__ double ctile[2][CoefTile<2>::N];
 
@@ -518,7 +549,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
 
     if (nch > 0) {
         const int64_t row0 = a.rowoff[m];
-        const uint32_t* Am = static_cast<const uint32_t*>(a.A) + row0 * a.ldx + col;
+        const uint64_t* Am = static_cast<const uint64_t*>(a.A) + row0 * a.ldx + col;
         const int64_t sb = a.seedoff[m] + frc;
         const int j0 = (lfirst - lb) / SEG + fs0;
         const int jmax = (L - lb) / SEG;
@@ -527,18 +558,18 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
         };
         auto ls_of = [&](int c, int i) { return lfirst + TL * c + SEG * (fs0 + 4 * i); };
         auto emit_to = [&](int b, int i) {
-            EmitBF<1, 0, HL> e;
+            EmitBF<1, 0, PL> e;
             e.e0 = lam + b * BUF + frl * KP + (SEG / 2) * (fs0 + 4 * i);
             e.e1 = e.e0 + CLS;
             return e;
         };
-        uint32_t ar[2][NU][8];  // [even, odd class][column tile][class row k0 + e] of the next chunk
+        uint64_t ar[2][NU][8];  // [even, odd class][column tile][class row k0 + e] of the next chunk
         auto load_a = [&](int c) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int le = lfirst + TL * c + 2 * (k0 + e);
-                const uint32_t* pe = Am + (int64_t)(min(le, L) - lb) * a.ldx;
-                const uint32_t* pq = Am + (int64_t)(min(le + 1, L) - lb) * a.ldx;
+                const uint64_t* pe = Am + (int64_t)(min(le, L) - lb) * a.ldx;
+                const uint64_t* pq = Am + (int64_t)(min(le + 1, L) - lb) * a.ldx;
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
                     ar[0][u][e] = pe[16 * u];
@@ -574,11 +605,11 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
             const int cnt0 = min(SEG, L - ls_of(cn, 0) + 1), cnt1 = min(SEG, L - ls_of(cn, 1) + 1);
 #pragma unroll
             for (int i = 0; i < 2; ++i) f[i].start(sd[i], w);
-            v8bf bh[2][NU], bl[2][NU];
+            S3 bs[2][NU];
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int u = 0; u < NU; ++u) unpack8(ar[p][u], bh[p][u], bl[p][u]);
+                for (int u = 0; u < NU; ++u) unpack8(ar[p][u], bs[p][u]);
             load_a(cn);
 #pragma unroll
             for (int i = 0; i < 2; ++i) seed_of(sd[i], min(c + 2, nch - 1), i);
@@ -590,11 +621,11 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
                 constexpr int P = decltype(ph)::v;
                 constexpr int cls = P >> 2, t = P & 3;
                 const __bf16* q = lb_ + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
-                const v8bf ah = lds8(q), al = lds8(q + HL);
+                const S3 a3 = lds3<PL>(q);
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
-                    if constexpr (cls == 0) accE[t][u] = mfma3(ah, al, bh[0][u], bl[0][u], accE[t][u]);
-                    else accO[t][u] = mfma3(ah, al, bh[1][u], bl[1][u], accO[t][u]);
+                    if constexpr (cls == 0) accE[t][u] = mfma6(a3, bs[0][u], accE[t][u]);
+                    else accO[t][u] = mfma6(a3, bs[1][u], accO[t][u]);
                 }
                 rec_group<P, RPP>(f[0], cp0, cnt0, em0);
                 rec_group<P, RPP>(f[1], cp1, cnt1, em1);
@@ -632,7 +663,7 @@ constexpr int A2_TR = 32;
 template <int NU, int EB>
 __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
 {
-    constexpr int CLS = A2_TR * KP, FOFF = 2 * CLS, HL = 2 * FOFF, BUF = 2 * HL;
+    constexpr int CLS = A2_TR * KP, FOFF = 2 * CLS, PL = 2 * FOFF, BUF = 3 * PL;
     __shared__ __attribute__((aligned(16))) __bf16 fpm[2 * BUF];
     __shared__ double ctile[2][CoefTile<4>::N];
 
@@ -675,20 +706,20 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
 
     if (nch > 0) {
         const int64_t row0 = a.rowoff[m];
-        const uint32_t* AE = static_cast<const uint32_t*>(a.A) + a.acomp + row0 * a.ldx + col;
-        const uint32_t* AB = static_cast<const uint32_t*>(a.A) + 2 * a.acomp + row0 * a.ldx + col;
+        const uint64_t* AE = static_cast<const uint64_t*>(a.A) + a.acomp + row0 * a.ldx + col;
+        const uint64_t* AB = static_cast<const uint64_t*>(a.A) + 2 * a.acomp + row0 * a.ldx + col;
         const int64_t sb = a.seedoff[m] + frc;
         const int j0 = (lfirst - lb) / SEG + fs;
         const int jmax = (L - lb) / SEG;
         auto seed_of = [&](Seed<2>& s, int c) { seed_load(s, a, sb + (int64_t)min(j0 + SPT * c, jmax) * a.rn, frc); };
         auto ls_of = [&](int c) { return lfirst + TL * c + SEG * fs; };
         auto emit_to = [&](int b) {
-            EmitBF<1, FOFF, HL> e;
+            EmitBF<1, FOFF, PL> e;
             e.e0 = fpm + b * BUF + po * CLS + frl * KP + (SEG / 2) * fs;
             e.e1 = fpm + b * BUF + (po ^ 1) * CLS + frl * KP + (SEG / 2) * fs;
             return e;
         };
-        uint32_t ar[4][NU][8];  // [E even, E odd, B' even, B' odd][column tile][class row k0 + e]
+        uint64_t ar[4][NU][8];  // [E even, E odd, B' even, B' odd][column tile][class row k0 + e]
         auto load_a_tile = [&](int c, int u) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -699,13 +730,13 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
                     ar[0][u][e] = AE[oe];
                     ar[1][u][e] = AE[oo];
                 } else {
-                    ar[0][u][e] = ar[1][u][e] = 0u;
+                    ar[0][u][e] = ar[1][u][e] = 0ull;
                 }
                 if constexpr (EB != 1) {
                     ar[2][u][e] = AB[oe];
                     ar[3][u][e] = AB[oo];
                 } else {
-                    ar[2][u][e] = ar[3][u][e] = 0u;
+                    ar[2][u][e] = ar[3][u][e] = 0ull;
                 }
             }
         };
@@ -740,7 +771,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
             // one tile's raw prefetch are live besides the accumulators.
             static_assert(NPH % NU == 0 && NPH / NU >= 4, "four MFMA phases per column tile");
             constexpr int PPU = NPH / NU;  // phases per column tile
-            v8bf bh[4], bl[4];
+            S3 bs[4];
             auto em = emit_to(b ^ 1);
             const __bf16* fb = fpm + b * BUF;
             static_for<0, NPH>([&](auto ph) {
@@ -748,7 +779,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
                 constexpr int u = P / PPU, pu = P % PPU;
                 if constexpr (pu == 0) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) unpack8(ar[i][u], bh[i], bl[i]);
+                    for (int i = 0; i < 4; ++i) unpack8(ar[i][u], bs[i]);
                     load_a_tile(cn, u);
                     if constexpr (u == 0) seed_of(sd, min(c + 2, nch - 1));
                     __builtin_amdgcn_sched_barrier(0);
@@ -758,27 +789,25 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
                     const __bf16* q = fb + (16 * t + (lane & 15)) * KP + k0;
                     if constexpr (!second) {
                         // F+ terms: U1 += F+e E_e, U2 += F+o E_o, V1 += F+e B'_e, V2 += F+o B'_o
-                        const v8bf eh = lds8(q), el = lds8(q + HL);
-                        const v8bf oh = lds8(q + CLS), ol = lds8(q + CLS + HL);
+                        const S3 fe = lds3<PL>(q), fo = lds3<PL>(q + CLS);
                         if constexpr (EB != 2) {
-                            u1[t][u] = mfma3(eh, el, bh[0], bl[0], u1[t][u]);
-                            u2[t][u] = mfma3(oh, ol, bh[1], bl[1], u2[t][u]);
+                            u1[t][u] = mfma6(fe, bs[0], u1[t][u]);
+                            u2[t][u] = mfma6(fo, bs[1], u2[t][u]);
                         }
                         if constexpr (EB != 1) {
-                            v1[t][u] = mfma3(eh, el, bh[2], bl[2], v1[t][u]);
-                            v2[t][u] = mfma3(oh, ol, bh[3], bl[3], v2[t][u]);
+                            v1[t][u] = mfma6(fe, bs[2], v1[t][u]);
+                            v2[t][u] = mfma6(fo, bs[3], v2[t][u]);
                         }
                     } else {
                         // F- terms: U1 += F-o B'_o, U2 += F-e B'_e, V1 += F-o E_o, V2 += F-e E_e
-                        const v8bf eh = lds8(q + FOFF), el = lds8(q + FOFF + HL);
-                        const v8bf oh = lds8(q + FOFF + CLS), ol = lds8(q + FOFF + CLS + HL);
+                        const S3 fe = lds3<PL>(q + FOFF), fo = lds3<PL>(q + FOFF + CLS);
                         if constexpr (EB != 1) {
-                            u1[t][u] = mfma3(oh, ol, bh[3], bl[3], u1[t][u]);
-                            u2[t][u] = mfma3(eh, el, bh[2], bl[2], u2[t][u]);
+                            u1[t][u] = mfma6(fo, bs[3], u1[t][u]);
+                            u2[t][u] = mfma6(fe, bs[2], u2[t][u]);
                         }
                         if constexpr (EB != 2) {
-                            v1[t][u] = mfma3(oh, ol, bh[1], bl[1], v1[t][u]);
-                            v2[t][u] = mfma3(eh, el, bh[0], bl[0], v2[t][u]);
+                            v1[t][u] = mfma6(fo, bs[1], v1[t][u]);
+                            v2[t][u] = mfma6(fe, bs[0], v2[t][u]);
                         }
                     }
                 }
@@ -830,16 +859,12 @@ hipError_t launch_leg_m2a_bf16(const LegArgs& a, hipStream_t st)
             hipLaunchKernelGGL((k_m2a_spin0_bf<1>), dim3(b.ntiles * b.ctiles * kparts(a)), blk, 0, st, b);
         }
     } else {
-        // two column tiles per workgroup halve the recursion per column (the
-        // kernel's VALU bound) and still fit 256 registers without spilling
-        const int nu = a.ldx % 128 == 0 ? 2 : 1;
-        b.ctiles = (int)(a.ldx / (64 * nu));
+        // one column tile per workgroup: with three pieces per operand, the
+        // split operands of two tiles need more than the 256 registers a wave
+        // may hold at two waves per SIMD
+        b.ctiles = (int)(a.ldx / 64);
         const dim3 grid(b.ntiles * b.ctiles * kparts(a));
-        if (nu == 2) {
-            if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2_bf<2, 1>), grid, blk, 0, st, b);
-            else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2_bf<2, 2>), grid, blk, 0, st, b);
-            else hipLaunchKernelGGL((k_m2a_spin2_bf<2, 0>), grid, blk, 0, st, b);
-        } else if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 1>), grid, blk, 0, st, b);
+        if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 1>), grid, blk, 0, st, b);
         else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 2>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_m2a_spin2_bf<1, 0>), grid, blk, 0, st, b);
     }

@@ -548,7 +548,11 @@ int build_mcut(sht_plan p)
 // --------------------------------------------------------------------------
 // workspace
 // --------------------------------------------------------------------------
+// element size of the ring coefficients X and of the rows map2alm writes
 size_t esize(int prec) { return prec == SHT_FP64 ? sizeof(double) : sizeof(float); }
+// bytes per element of a separate alm2map operand region: split-BF16 words (the
+// other precisions read the map2alm rows' own region)
+size_t opsize(int prec) { return prec == SHT_BF16X3 ? sizeof(uint64_t) : 0; }
 
 // columns of the m-major operand arrays: 2 * map sets, padded to 32 map sets for
 // batches of up to 32 (one 64-column tile) and to a multiple of 64 beyond
@@ -563,17 +567,29 @@ int64_t acomp_elems(sht_plan p)
     return (L + 1) * (L + 2) / 2 * ldx_for(p->chunk);
 }
 
-size_t ws_need(sht_plan p)
+// workspace bytes for chunks of `chunk` map sets in precision `prec`
+size_t ws_need_at(sht_plan p, int chunk, int prec)
 {
-    return (size_t)p->ncomp * (size_t)(xcomp_elems(p) + acomp_elems(p)) * esize(p->prec);
+    const int64_t L = p->lmax, ldx = ldx_for(chunk);
+    const size_t x = (size_t)(L + 1) * p->nring * ldx, a = (size_t)((L + 1) * (L + 2) / 2) * ldx;
+    return (size_t)p->ncomp * ((x + a) * esize(prec) + a * opsize(prec));
 }
 
+size_t ws_need(sht_plan p) { return ws_need_at(p, p->chunk, p->prec); }
+
 void* ws_A(sht_plan p) { return (char*)p->ws + (size_t)p->ncomp * xcomp_elems(p) * esize(p->prec); }
+// the alm2map operand rows: the map2alm rows' region, or the split-BF16 words after it
+void* ws_Aop(sht_plan p)
+{
+    if (!opsize(p->prec)) return ws_A(p);
+    return (char*)ws_A(p) + (size_t)p->ncomp * acomp_elems(p) * esize(p->prec);
+}
 
 int default_chunk(sht_plan p)
 {
     const double budget = 8.0e9;
-    double per = (double)p->ncomp * (p->lmax + 1) * (p->nring + (p->lmax + 2) / 2.0) * 2.0 * esize(p->prec);
+    double per = (double)p->ncomp * (p->lmax + 1) * 2.0 *
+                 ((p->nring + (p->lmax + 2) / 2.0) * esize(p->prec) + (p->lmax + 2) / 2.0 * opsize(p->prec));
     int c = (int)std::max(1.0, std::floor(budget / per));
     if (c >= 64) c = c / 64 * 64;
     return std::min(c, p->cap);
@@ -665,6 +681,7 @@ AlmArgs alm_args(sht_plan p, const SeedSet& S, int nmaps_chunk)
 {
     AlmArgs a{};
     a.A = ws_A(p);
+    a.Aop = ws_Aop(p);
     a.acomp = acomp_elems(p);
     a.rowoff = (const int64_t*)S.rowoff.p;
     a.tileoff = (const int*)S.tileoff.p;
@@ -739,11 +756,14 @@ int run_leg_a2m(sht_plan p, int sel)
 {
     if (sel_t(sel)) {
         StageTimer t(p, SHT_STAGE_A2M_SPIN0);
-        HIPCHK(launch_leg_a2m(leg_args(p, p->s0), p->prec, p->stream));
+        LegArgs a = leg_args(p, p->s0);
+        a.A = ws_Aop(p);
+        HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
     }
     if (sel_pol(p, sel)) {
         StageTimer t(p, SHT_STAGE_A2M_SPIN2);
         LegArgs a = leg_args(p, p->s2);
+        a.A = ws_Aop(p);
         a.eb = sel_eb(sel);
         HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
     }
@@ -933,6 +953,7 @@ int run_level(sht_plan p, double* alm, int nm, int d)
                 z.comp0 = spin == 0 ? 0 : 1;
                 HIPCHK(launch_level_zero(z, ml, nl, ncompl, p->stream));
             }
+            a.A = ws_Aop(p);  // the rows the commit wrote as the synthesis operand
             HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
         }
     }

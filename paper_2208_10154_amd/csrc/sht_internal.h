@@ -25,17 +25,21 @@ constexpr int SPT = TL / SEG;  // segments per tile
 constexpr int RCHUNK = 32;   // ring granularity of the skip table
 
 // ----------------------------------------------------------------------------
-// Split-BF16 operands: x (rounded to FP32) = hi + lo with hi = bf16(x) and
-// lo = bf16(x - hi), stored as one 32-bit word, hi in the low half.  The layout
-// kernel writes the coefficient rows of the BF16x3 alm2map contraction in this
-// form, so that kernel only regroups halves instead of splitting every operand
-// in every tile.
+// Split-BF16 operands: x (rounded to FP32) = hi + mid + lo with hi = bf16(x),
+// mid = bf16(x - hi), lo = bf16(x - hi - mid): three bfloat16 numbers carry the
+// 24 significant bits of the FP32 value.  Stored as one 64-bit word, hi in bits
+// 0-15, mid in 16-31, lo in 32-47.  The layout kernel writes the coefficient rows
+// of the split-BF16 alm2map contraction in this form, so that kernel only
+// regroups halves instead of splitting every operand in every tile.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t pack_bf16_pair(float x)
+__device__ __forceinline__ uint64_t pack_bf16_triple(float x)
 {
     const __bf16 h = (__bf16)x;
-    const __bf16 l = (__bf16)(x - (float)h);
-    return (uint32_t)__builtin_bit_cast(unsigned short, h) | ((uint32_t)__builtin_bit_cast(unsigned short, l) << 16);
+    const float r = x - (float)h;
+    const __bf16 m = (__bf16)r;
+    const __bf16 l = (__bf16)(r - (float)m);
+    const uint32_t w0 = (uint32_t)__builtin_bit_cast(unsigned short, h) | ((uint32_t)__builtin_bit_cast(unsigned short, m) << 16);
+    return (uint64_t)w0 | ((uint64_t)__builtin_bit_cast(unsigned short, l) << 32);
 }
 
 // ----------------------------------------------------------------------------
@@ -149,7 +153,9 @@ struct LegArgs {
 struct AlmArgs {
     const double* alm_in;   // compact alm of the chunk (to m-major)
     double* alm_out;        // compact alm of the chunk (from m-major)
-    void* A;
+    void* A;                // rows the map2alm contraction writes (double or float)
+    void* Aop;              // rows the alm2map contraction reads: A itself, except for
+                            // split BF16, whose 64-bit words sit in a region of their own
     int64_t acomp;
     const int64_t* rowoff;
     const int* tileoff;     // l tiles of 64 per m for this spin
@@ -168,11 +174,13 @@ hipError_t launch_alm_to_mmajor(const AlmArgs& a, int ncompl, int prec, hipStrea
 hipError_t launch_alm_from_mmajor(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
 // base[i*stride + j] = 0 for i < rows, j < len
 hipError_t launch_zero_strided(double* base, int rows, int64_t stride, int64_t len, hipStream_t st);
-// immediate iteration: A rows of the listed m (m2a output) -> scale * rows in the
-// alm2map operand format, with the parts the compact storage lacks (m = 0) zeroed
+// immediate iteration: A rows of the listed m (m2a output) -> scale * rows, in
+// place, with the parts the compact storage lacks (m = 0) zeroed; scale = 0
+// clears them (before a split map2alm adds into them)
 hipError_t launch_level_rows(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
 // immediate iteration: alm += scale * rows (as launch_alm_from_mmajor with
-// accumulate) and the rows rewritten as launch_level_rows does, in one pass
+// accumulate) and scale * rows written as the alm2map operand (Aop, m = 0 parts
+// without a compact slot zeroed), in one pass
 hipError_t launch_level_commit(const AlmArgs& a, int ncompl, int prec, hipStream_t st);
 
 // immediate iteration, Fourier side (k_iter.hip), on the residual spectra
@@ -238,7 +246,8 @@ hipError_t launch_seeds(const SeedArgs& a, hipStream_t st);
 // recursion coefficient table (layout of LegArgs::coef); rows must be zeroed first
 hipError_t launch_coefs(double* coef, const int64_t* rowoff, int lmax, int spin, hipStream_t st);
 
-// prec: 0 FP64, 1 FP32, 2 BF16x3 (operands in the FP32 workspace)
+// prec: 0 FP64, 1 FP32, 2 split BF16 (FP32 ring coefficients and map2alm rows,
+// 64-bit split words as the alm2map operand rows)
 hipError_t launch_leg_m2a(const LegArgs& a, int prec, hipStream_t st);
 hipError_t launch_leg_a2m(const LegArgs& a, int prec, hipStream_t st);
 hipError_t launch_leg_m2a_bf16(const LegArgs& a, hipStream_t st);

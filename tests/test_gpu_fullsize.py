@@ -42,7 +42,7 @@ def batch():
     return alm_c, alm, maps_np, maps
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_alm2map_sampled_pixels(batch, prec):
     import torch
     from paper_2208_10154_amd import sht
@@ -64,7 +64,7 @@ def test_alm2map_sampled_pixels(batch, prec):
     p.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_map2alm_sampled_coefficients(batch, prec):
     import torch
     from paper_2208_10154_amd import sht

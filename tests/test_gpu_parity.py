@@ -96,6 +96,7 @@ POL_CASES = [
     (16, 47, 2, None),
     (4, 15, 1, None),
     (24, 71, 2, None),  # aliased rows in the power-of-two and Bluestein ring kernels
+    (64, 191, 4, None), # a larger sky: B (a tenth of E's power) held to the bar on its own norm
 ]
 
 
