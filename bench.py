@@ -500,17 +500,64 @@ def immediate_leg(args):
     return {"workload": f"healpix_iqu_nside{nside}_lmax{L}_x{n}_bandlimited_iter{niter}", "by_precision": res}
 
 
+def small_batch_leg(args):
+    """Small batches (the BLAS2 regime): latency of alm2map + map2alm of 1, 8 and
+    9 IQU triples at nside 512 / lmax 1535 and nside 1024 / lmax 2047, FP64 and
+    split BF16, inputs resident in HBM, median over repetitions.  Up to 8 map sets
+    run the narrow Legendre tiles; 9 run the 64-column tile (32 map sets wide)."""
+    import torch
+    from paper_2208_10154_amd import sht
+    out = {}
+    stream = torch.cuda.current_stream()
+    for nside, L in ((512, 1535), (1024, 2047)):
+        p = sht.Plan(nside, L, 2, 9)
+        alm = torch.empty((9, 3, (L + 1) ** 2), dtype=torch.float64, device="cuda")
+        fill_alm(alm, L, seed=220810154 + 8, block=9)
+        maps = torch.empty((9, 3, 12 * nside * nside), dtype=torch.float64, device="cuda")
+        back = torch.empty_like(alm)
+        res = {}
+        for prec in ("fp64", "bf16x3"):
+            p.set_precision(prec)
+            for n in (1, 8, 9):
+                p.set_nmaps(n)
+                p.alm2map(alm[:n], maps[:n], stream)
+                p.map2alm(maps[:n], back[:n], stream)
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(max(3, args.steps)):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    p.alm2map(alm[:n], maps[:n], stream)
+                    p.map2alm(maps[:n], back[:n], stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ts.append(e0.elapsed_time(e1))
+                ms = sorted(ts)[len(ts) // 2]
+                res[f"{prec}_x{n}"] = {"ms": round(ms, 3), "triples_per_s": round(n * 1000.0 / ms, 1)}
+        p.close()
+        del alm, maps, back
+        torch.cuda.empty_cache()
+        out[f"nside{nside}_lmax{L}"] = res
+        log(f"small batches nside {nside}: {res}")
+    return out
+
+
 def serving(args):
     """Config 5: a seeded mix of requests (nside 64..1024, lmax = 3 nside - 1, T or
-    IQU, both directions, FP64 or BF16x3, log-normal map counts) through the
-    batching server: a saturated pass (all requests at once) gives the capacity,
-    a Poisson pass at 80% of it gives p50/p99 latency, and a serial FP64 pass (one
-    request at a time through the same library) is the baseline.  Plan creation
-    (and graph capture) happen in a warm-up pass, timed separately."""
+    IQU, both directions, FP64 or the mixed precision, log-normal map counts with
+    median 16 capped at 512 map sets, no other cap) through the batching server:
+    a saturated pass (all requests at once) gives the capacity, a Poisson pass at
+    80% of it gives p50/p99 latency, and the baseline serves the same Poisson
+    arrivals in FP64 one request at a time, first come first served, on one
+    stream.  The callers hold at most --serve-live-gb of request inputs and outputs
+    in HBM at a time (a request that would exceed it is created once earlier ones
+    finish; its latency still counts from its arrival).  Plan creation happens in
+    a warm-up pass, timed separately."""
     import torch
     from paper_2208_10154_amd import serve
     N = args.serve_requests
     base = serve.request_mix(N, rate_hz=1.0, seed=7, mixed=args.serve_mixed)
+    live = args.serve_live_gb * 1e9
 
     def make_io(d):
         nside, spin, n = d["nside"], d["spin"], d["nmaps"]
@@ -523,48 +570,58 @@ def serving(args):
         ev.record()
         return inp, out, ev
 
-    def server(depth=2, nstreams=4):
-        return serve.Server(args.serve_budget_gb * 1e9, max_slots=512, depth=depth,
-                            executor=serve.Executor(nstreams=nstreams, graphs=args.serve_graphs))
+    def warm_up(srv, precisions):
+        t0 = time.perf_counter()
+        warm = [dict(arrival=0.0, nside=k[0], spin=k[1], direction=k[2], precision=k[3], nmaps=1)
+                for k in sorted({(d["nside"], d["spin"], d["direction"], p) for d in base for p in precisions})]
+        serve.replay(srv, warm, make_io)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
-    srv = server()
-    t0 = time.perf_counter()
-    warm = []
-    for key in sorted({(d["nside"], d["spin"], d["direction"], d["precision"]) for d in base}):
-        warm.append(dict(arrival=0.0, nside=key[0], spin=key[1], direction=key[2], precision=key[3], nmaps=1))
-    serve.replay(srv, warm, make_io)
-    torch.cuda.synchronize()
-    init_s = time.perf_counter() - t0
-    log(f"serve: warm-up (plans for {len(srv.plans)} keys) {init_s:.1f}s, {srv.used / 1e9:.1f} GB held")
-
-    def rebased(mix, scale):
+    def rebased(srv, mix, scale):
         now = srv.now()
         return [dict(d, arrival=now + 0.05 + d["arrival"] * scale) for d in mix]
 
-    sat = serve.replay(srv, rebased([dict(d, arrival=0.0) for d in base], 0.0), make_io)
+    srv = serve.Server(args.serve_budget_gb * 1e9, max_slots=512, depth=2,
+                       executor=serve.Executor(nstreams=4, graphs=args.serve_graphs))
+    init_s = warm_up(srv, sorted({d["precision"] for d in base}))
+    log(f"serve: warm-up (plans for {len(srv.plans)} keys) {init_s:.1f}s, {srv.used / 1e9:.1f} GB held")
+    sat = serve.replay(srv, rebased(srv, [dict(d, arrival=0.0) for d in base], 0.0), make_io, max_live_bytes=live)
     st_sat = serve.latency_stats(sat)
     cap_req = N / st_sat["makespan_s"]
     rate = 0.8 * cap_req
     log(f"serve: saturated {st_sat}")
-    poisson = serve.replay(srv, rebased(base, 1.0 / rate), make_io)
+    poisson = serve.replay(srv, rebased(srv, base, 1.0 / rate), make_io, max_live_bytes=live)
     st_p = serve.latency_stats(poisson)
     log(f"serve: poisson at {rate:.2f} req/s {st_p}")
-    # serial FP64 baseline: one request at a time, each waited for
-    serial = []
-    for d in base:
-        r = serve.replay(srv, [dict(d, precision="fp64", arrival=srv.now())], make_io)[0]
-        serial.append(r)
+    peak = srv.peak
+    srv.close()
+    del srv
+    torch.cuda.empty_cache()
+    # baseline: the same arrivals, FP64, one request per launch, in arrival order on one stream
+    ser = serve.Server(args.serve_budget_gb * 1e9, max_slots=512, depth=1 << 20, batching=False,
+                       executor=serve.Executor(nstreams=1))
+    warm_up(ser, ["fp64"])
+    serial = serve.replay(ser, rebased(ser, [dict(d, precision="fp64") for d in base], 1.0 / rate), make_io,
+                          max_live_bytes=live)
     st_s = serve.latency_stats(serial)
-    log(f"serve: serial fp64 {st_s}")
-    out = {"requests": N, "mix": f"nside 64-1024 (lmax 3 nside - 1), T/IQU, alm2map/map2alm, fp64/{args.serve_mixed}, "
-                                 "log-normal maps (median 16)",
+    log(f"serve: serial fp64 fifo {st_s}")
+    ser.close()
+    del ser
+    torch.cuda.empty_cache()
+    sizes = sorted(d["nmaps"] for d in base)
+    out = {"requests": N,
+           "mix": f"nside 64-1024 (lmax 3 nside - 1), T/IQU, alm2map/map2alm, fp64/{args.serve_mixed}, "
+                  "log-normal map sets (median 16, sigma_ln 1, cap 512), no byte cap",
+           "map_sets_median_max": [sizes[len(sizes) // 2], sizes[-1]],
+           "largest_request_gb": round(max(serve.request_bytes(d) for d in base) / 1e9, 1),
            "rate_req_per_s": round(rate, 3), "capacity_req_per_s": round(cap_req, 3),
            "p50_ms": st_p["p50_ms"], "p99_ms": st_p["p99_ms"], "maps_per_s": st_p["maps_per_s"],
            "saturated_maps_per_s": st_sat["maps_per_s"],
-           "serial_fp64": {"maps_per_s": st_s["maps_per_s"], "p50_ms": st_s["p50_ms"], "p99_ms": st_s["p99_ms"]},
-           "graphs": bool(args.serve_graphs), "budget_gb": args.serve_budget_gb,
-           "peak_server_gb": round(srv.peak / 1e9, 1), "init_s": round(init_s, 1)}
-    srv.close()
+           "serial_fp64_fifo": {"maps_per_s": st_s["maps_per_s"], "p50_ms": st_s["p50_ms"], "p99_ms": st_s["p99_ms"],
+                                "arrivals": "the same Poisson arrivals, one request per launch, first come first served"},
+           "graphs": bool(args.serve_graphs), "budget_gb": args.serve_budget_gb, "live_request_gb": args.serve_live_gb,
+           "peak_server_gb": round(peak / 1e9, 1), "init_s": round(init_s, 1)}
     return out
 
 
@@ -585,6 +642,7 @@ def main():
     ap.add_argument("--no-eb", action="store_true", help="skip the E/B leg")
     ap.add_argument("--no-imm", action="store_true", help="skip the immediate-iteration leg")
     ap.add_argument("--no-spin0", action="store_true", help="skip the spin-0 nside 128 leg")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-batch latency leg")
     ap.add_argument("--imm-nmaps", type=int, default=64, help="IQU triples of the immediate-iteration leg")
     ap.add_argument("--imm-precisions", default="fp64,bf16x3")
     ap.add_argument("--eb-nmaps", type=int, default=250, help="IQU triples of the E/B leg")
@@ -592,8 +650,10 @@ def main():
     ap.add_argument("--iter-nmaps", type=int, default=200)
     ap.add_argument("--iter-chunk", type=int, default=64)
     ap.add_argument("--iter-precisions", default="bf16x3,fp32,fp64")
-    ap.add_argument("--serve-requests", type=int, default=48)
-    ap.add_argument("--serve-budget-gb", type=float, default=240.0)
+    ap.add_argument("--serve-requests", type=int, default=500)
+    ap.add_argument("--serve-budget-gb", type=float, default=185.0, help="HBM the server may hold (plans, slots)")
+    ap.add_argument("--serve-live-gb", type=float, default=65.0,
+                    help="HBM the emulated callers hold for request inputs and outputs at a time")
     ap.add_argument("--serve-mixed", default="bf16x3")
     ap.add_argument("--serve-graphs", action="store_true")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -671,6 +731,8 @@ def main():
         line["spin0"] = spin0_leg(args)
     if not args.no_imm:
         line["immediate"] = immediate_leg(args)
+    if not args.no_small:
+        line["small_batch"] = small_batch_leg(args)
     if not args.no_serve:
         line["serve"] = serving(args)
     if not args.no_cpu_baseline:

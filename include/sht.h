@@ -69,11 +69,32 @@ enum sht_precision {
 /* Create a plan for HEALPix resolution nside, band limit lmax and spin 0 (T maps)
  * or 2 (IQU map triples), for batches of up to nmaps map sets per call.
  * Requires 1 <= nside <= 8192, 0 <= lmax <= 4*nside-1 (spin 2: lmax >= 2),
- * nmaps >= 1 (SHT_ERR_ARG otherwise); this library supports nside <= 1024 and
- * lmax <= 4094 (SHT_ERR_UNSUPPORTED beyond).  Builds the ring tables, FFT plans and Legendre seed tables on the
- * current HIP device (the paper's once-only initialisation, Sec. 3.3) and
- * allocates the workspace for one chunk of map sets (see sht_plan_set_chunk). */
+ * nmaps >= 1 (SHT_ERR_ARG otherwise); this library supports nside <= 2048
+ * (SHT_ERR_UNSUPPORTED beyond).  Builds the ring tables, FFT plans and Legendre
+ * seed tables on the current HIP device (the paper's once-only initialisation,
+ * Sec. 3.3) and allocates the workspace for one chunk of map sets (see
+ * sht_plan_set_chunk).  The seed tables hold about 80 nside lmax^2 / 8 bytes
+ * (spin 2: three times that), 8.6 GB at nside 512 / lmax 1535; a plan whose
+ * tables do not fit the device gives SHT_ERR_NOMEM (sht_plan_create_part splits
+ * them). */
 int sht_plan_create(sht_plan* out, int nside, int lmax, int spin, int nmaps);
+
+/* Create a plan that owns part `part` (0 <= part < nparts) of the orders m: the
+ * pairs (q, lmax - q) of m are dealt to the parts in turn (q mod nparts == part),
+ * which balances the triangle of (l, m) work between parts.  This is one GPU's
+ * share of the split by m that resolutions beyond one GPU's memory need (Sec. 5:
+ * nside >= 2048; the Legendre step of each part needs nothing from the others).
+ * The plan's seed and coefficient tables cover its own m only.  Its transforms:
+ *   sht_map2alm  writes the a_lm of its own m and leaves every other a_lm entry
+ *                of the output unchanged (so the parts can fill one array);
+ *   sht_alm2map  writes the maps synthesised from the a_lm of its own m only
+ *                (the sum over the parts' maps is the full synthesis).
+ * The ring FFTs are computed for all rings on the plan's GPU (the exchange
+ * between ring and m layouts that splits them across GPUs is not part of this
+ * library).  Iterations, E/B separation and component selections need a plan
+ * of all m (SHT_ERR_UNSUPPORTED).  Arguments as
+ * for sht_plan_create; SHT_ERR_ARG if part is out of range or owns no m. */
+int sht_plan_create_part(sht_plan* out, int nside, int lmax, int spin, int nmaps, int part, int nparts);
 
 /* Release every device and host resource of the plan (NULL is accepted). */
 int sht_plan_destroy(sht_plan plan);

@@ -179,6 +179,11 @@ __device__ __forceinline__ void run_passes(double2 (&v)[8], double2 (&w)[8], dou
 // item); workgroups are dealt to the 8 XCDs round-robin, so the block index is
 // remapped to give each XCD one contiguous range (neighbouring pair groups of a
 // ring, which write adjacent columns of the same m-major rows, then share an L2).
+// A workgroup whose map pairs all lie past the chunk's map sets returns at once:
+// their ring coefficient columns are never read into a result (every later step
+// treats the columns of a map set on their own, and pairs the two map sets of one
+// FFT sequence only with each other), so a small batch does not pay for the
+// padding of its column tile.
 struct Item {
     int ring, pair0, comp;
 };
@@ -305,7 +310,9 @@ template <int LOGN, typename XT>
 __global__ __launch_bounds__(P2<LOGN>::NTH, 4) void k_fft_fwd_p2(FftArgs a, const FftItem* items, int nitems)
 {
     extern __shared__ double2 lds[];
-    fwd_item<LOGN, XT>(a, work_item(items, nitems, a.comp0), lds);
+    const Item it = work_item(items, nitems, a.comp0);
+    if (2 * it.pair0 >= a.nmaps) return;  // only padding map sets: nothing reads them
+    fwd_item<LOGN, XT>(a, it, lds);
 }
 
 template <int LOGN, typename XT>
@@ -341,7 +348,7 @@ __device__ __forceinline__ void inv_item(const FftArgs& a, const Item it, double
                 const double2 p = tw[(m * s) & (2 * N - 1)];
                 const double2 ph = make_double2(p.x, -p.y);  // e^{+i m phi0}
                 const double2 ca = cmul(ph, ta), cb = cmul(ph, tb);
-                const bool live = m <= lmax;
+                const bool live = m <= lmax && (!a.mown || a.mown[min(m, lmax)]);
                 zs[m] = live ? make_double2(ca.x - cb.y, ca.y + cb.x) : make_double2(0.0, 0.0);
                 e[u] = (live && m >= 1) ? make_double2(ca.x + cb.y, cb.x - ca.y) : make_double2(0.0, 0.0);
             }
@@ -349,7 +356,7 @@ __device__ __forceinline__ void inv_item(const FftArgs& a, const Item it, double
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int m = mi + u * MSTEP;
-                if (m >= 1 && m <= lmax) {
+                if (m >= 1 && m <= lmax && (!a.mown || a.mown[m])) {
                     double2& z = zs[N - m];
                     z = make_double2(z.x + e[u].x, z.y + e[u].y);
                 }
@@ -369,7 +376,7 @@ __device__ __forceinline__ void inv_item(const FftArgs& a, const Item it, double
 #pragma unroll
                 for (int u = 0; u < MB; ++u) {
                     const int m = m0 + u * MSTEP;
-                    if (m <= lmax) {
+                    if (m <= lmax && (!a.mown || a.mown[m])) {
                         const double2 ph = make_double2(p[u].x, -p[u].y);
                         const double2 ca = cmul(ph, ta[u]), cb = cmul(ph, tb[u]);
                         double* z1 = reinterpret_cast<double*>(zs + (m & (N - 1)));
@@ -424,7 +431,9 @@ template <int LOGN, typename XT>
 __global__ __launch_bounds__(P2<LOGN>::NTH, 4) void k_fft_inv_p2(FftArgs a, const FftItem* items, int nitems)
 {
     extern __shared__ double2 lds[];
-    inv_item<LOGN, XT>(a, work_item(items, nitems, a.comp0), lds);
+    const Item it = work_item(items, nitems, a.comp0);
+    if (2 * it.pair0 >= a.nmaps) return;  // only padding map sets: nothing reads them
+    inv_item<LOGN, XT>(a, it, lds);
 }
 
 // ----------------------------------------------------------------------------
@@ -641,7 +650,7 @@ __device__ __forceinline__ void inv_item_blue(const FftArgs& a, const Item it, d
                 const int m = m0 + q * MSTEP;
                 const double2 c = cmul(make_double2(p[q].x, -p[q].y), tv[q]);  // c_m of this lane's map
                 const double cbx = __shfl_xor(c.x, 1), cby = __shfl_xor(c.y, 1);
-                if (part == 0 && m <= lmax) {
+                if (part == 0 && m <= lmax && (!a.mown || a.mown[m])) {
                     const double2 ca = c, cb = make_double2(cbx, cby);
                     double* z1 = reinterpret_cast<double*>(zs + jj[q]);
                     atomicAdd(z1, ca.x - cb.y);
@@ -696,14 +705,18 @@ template <int LOGM, typename XT>
 __global__ __launch_bounds__(P2<LOGM>::NTH, 4) void k_fft_fwd_blue(FftArgs a, const FftItem* items, int nitems)
 {
     extern __shared__ double2 lds[];
-    fwd_item_blue<LOGM, XT>(a, work_item(items, nitems, a.comp0), lds);
+    const Item it = work_item(items, nitems, a.comp0);
+    if (2 * it.pair0 >= a.nmaps) return;  // only padding map sets: nothing reads them
+    fwd_item_blue<LOGM, XT>(a, it, lds);
 }
 
 template <int LOGM, typename XT>
 __global__ __launch_bounds__(P2<LOGM>::NTH, 4) void k_fft_inv_blue(FftArgs a, const FftItem* items, int nitems)
 {
     extern __shared__ double2 lds[];
-    inv_item_blue<LOGM, XT>(a, work_item(items, nitems, a.comp0), lds);
+    const Item it = work_item(items, nitems, a.comp0);
+    if (2 * it.pair0 >= a.nmaps) return;  // only padding map sets: nothing reads them
+    inv_item_blue<LOGM, XT>(a, it, lds);
 }
 
 template <int LOGN, typename XT>

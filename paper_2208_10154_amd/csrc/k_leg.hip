@@ -53,7 +53,7 @@ static_assert(M_TR == RCHUNK, "ring chunks and skip-table entries coincide");
 // the m-major coefficient workspace.  Tile: 64 l x 64*NU columns; rings in
 // chunks of 32; wave w owns NU column tiles of 16 and all 64 rows.
 // ============================================================================
-template <typename T, int NU>
+template <typename T, int NU, bool NW = false>
 __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
 {
     constexpr int RS = HALF + 1;        // [ring][row/2]
@@ -67,8 +67,10 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
     const int L = a.lmax, lb = m;
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int lane = threadIdx.x & 63, wave = wave_index();
-    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
-    // fill items: 32 rings x 2 segments; lanes 0..15 compute, every lane loads
+    const int col = NW ? (lane & 15) : ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    // narrow tile (NW: at most 8 map sets, the first 16 columns): the four waves
+    // split the tile's output blocks instead of its columns
+    auto mine = [&](int p, int t) { return !NW || (p == (wave >> 1) && t == (wave & 1)); };
     // fill items: 32 rings x SPT segments, one per lane (segment uniform per half-wave)
     static_assert(M_TR * SPT == NT, "one fill item per thread");
     constexpr bool filler = true;
@@ -157,15 +159,16 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) av[p][t] = lb_[p * CLS + kr * RS + 16 * t + (lane & 15)];
+                    for (int t = 0; t < 2; ++t)
+                        if (mine(p, t)) av[p][t] = lb_[p * CLS + kr * RS + 16 * t + (lane & 15)];
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
                     const T bs = xb[ks & 1][0][u] + xb[ks & 1][1][u];
                     const T bd = xb[ks & 1][0][u] - xb[ks & 1][1][u];
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
-                        acc[0][t][u] = MF::run(av[0][t], bs, acc[0][t][u]);
-                        acc[1][t][u] = MF::run(av[1][t], bd, acc[1][t][u]);
+                        if (mine(0, t)) acc[0][t][u] = MF::run(av[0][t], bs, acc[0][t][u]);
+                        if (mine(1, t)) acc[1][t][u] = MF::run(av[1][t], bd, acc[1][t][u]);
                     }
                 }
                 if (filler) rec_group<ks, RPK>(f, cp, cnt, em);
@@ -182,6 +185,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
+                if (!mine(p, t)) continue;
                 const int ci = 16 * t + MF::row(lane, v);
                 const int l = l0 + 2 * ci + p;
                 if (l > L) continue;
@@ -198,7 +202,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
 // rings in chunks of 32; wave w owns NU column tiles of 16.  EB = 1 (E only) or
 // 2 (B only) computes one block row of the transform; the other stays zero.
 // ============================================================================
-template <typename T, int NU, int EB>
+template <typename T, int NU, int EB, bool NW = false>
 __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
 {
     constexpr int RS = HALF + 1;
@@ -213,7 +217,10 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int po = (lb - m) & 1;
     const int lane = threadIdx.x & 63, wave = wave_index();
-    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    const int col = NW ? (lane & 15) : ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    // narrow tile (NW: at most 8 map sets, the first 16 columns): the four waves
+    // split the tile's output blocks instead of its columns
+    auto mine = [&](int p, int t) { return !NW || (p == (wave >> 1) && t == (wave & 1)); };
     const int pcol = col ^ 1;                           // Y = iU swaps re/im: partner column
     const unsigned ysg = (col & 1) ? 0u : 0x80000000u;  // Y_re = -U_im, Y_im = U_re
     // fill items: 32 rings x SPT segments, one per lane (segment uniform per half-wave)
@@ -307,6 +314,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
                 for (int p = 0; p < 2; ++p)
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
+                        if (!mine(p, t)) continue;
                         fp[p][t] = fb[p * CLS + kr * RS + 16 * t + (lane & 15)];
                         fm[p][t] = fb[FOFF + p * CLS + kr * RS + 16 * t + (lane & 15)];
                     }
@@ -318,23 +326,23 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
                         if constexpr (EB != 2) {
-                            accE[0][t][u] = MF::run(fp[0][t], sx, accE[0][t][u]);
-                            accE[1][t][u] = MF::run(fp[1][t], dx, accE[1][t][u]);
+                            if (mine(0, t)) accE[0][t][u] = MF::run(fp[0][t], sx, accE[0][t][u]);
+                            if (mine(1, t)) accE[1][t][u] = MF::run(fp[1][t], dx, accE[1][t][u]);
                         }
                         if constexpr (EB != 1) {
-                            accB[0][t][u] = MF::run(fp[0][t], sy, accB[0][t][u]);
-                            accB[1][t][u] = MF::run(fp[1][t], dy, accB[1][t][u]);
+                            if (mine(0, t)) accB[0][t][u] = MF::run(fp[0][t], sy, accB[0][t][u]);
+                            if (mine(1, t)) accB[1][t][u] = MF::run(fp[1][t], dy, accB[1][t][u]);
                         }
                     }
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
                         if constexpr (EB != 2) {
-                            accE[0][t][u] = MF::run(fm[0][t], dy, accE[0][t][u]);
-                            accE[1][t][u] = MF::run(fm[1][t], sy, accE[1][t][u]);
+                            if (mine(0, t)) accE[0][t][u] = MF::run(fm[0][t], dy, accE[0][t][u]);
+                            if (mine(1, t)) accE[1][t][u] = MF::run(fm[1][t], sy, accE[1][t][u]);
                         }
                         if constexpr (EB != 1) {
-                            accB[0][t][u] = MF::run(fm[0][t], dx, accB[0][t][u]);
-                            accB[1][t][u] = MF::run(fm[1][t], sx, accB[1][t][u]);
+                            if (mine(0, t)) accB[0][t][u] = MF::run(fm[0][t], dx, accB[0][t][u]);
+                            if (mine(1, t)) accB[1][t][u] = MF::run(fm[1][t], sx, accB[1][t][u]);
                         }
                     }
                 }
@@ -352,6 +360,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
+                if (!mine(p, t)) continue;
                 const int ci = 16 * t + MF::row(lane, v);
                 const int l = l0 + 2 * ci + (p ^ po);
                 if (l > L) continue;
@@ -371,7 +380,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2(LegArgs a)
 // ============================================================================
 constexpr int A0_TR = 64;
 
-template <typename T, int NU>
+template <typename T, int NU, bool NW = false>
 __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
 {
     constexpr int RS = A0_TR + 1;       // [row/2][ring]
@@ -389,7 +398,10 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
     const int L = a.lmax, lb = m;
     const int r0 = rt * A0_TR;
     const int lane = threadIdx.x & 63, wave = wave_index();
-    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    const int col = NW ? (lane & 15) : ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    // narrow tile (NW: at most 8 map sets, the first 16 columns): the four waves
+    // split the tile's output blocks instead of its columns
+    auto mine = [&](int t) { return !NW || t == wave; };
     // fill items: 64 rings x SPT segments, two per lane: ring = lane, segments
     // wave and wave + 4 (wave-uniform)
     static_assert(A0_TR * SPT == 2 * NT && SPT == 8, "two fill items per thread");
@@ -487,6 +499,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
                 const int kl = 4 * ks + (lane >> 4);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
+                    if (!mine(t)) continue;
                     const T aE = lb_[kl * RS + 16 * t + (lane & 15)];
                     const T aO = lb_[CLS + kl * RS + 16 * t + (lane & 15)];
 #pragma unroll
@@ -509,6 +522,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+            if (!mine(t)) continue;
             const int r = r0 + 16 * t + MF::row(lane, v);
             if (r >= a.rn) continue;
             const int rs = a.nring - 1 - r;
@@ -532,7 +546,7 @@ constexpr int A2_TR = 32;
 
 // EB = 1 (E only) or 2 (B only) drops the other block's loads and products:
 // the half-block transforms of pixel-domain E/B separation (Sec. 2.3).
-template <typename T, int NU, int EB>
+template <typename T, int NU, int EB, bool NW = false>
 __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
 {
     constexpr int RS = A2_TR + 1;
@@ -551,7 +565,12 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
     const int po = (lb - m) & 1;
     const int r0 = rt * A2_TR;
     const int lane = threadIdx.x & 63, wave = wave_index();
-    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    const int col = NW ? (lane & 15) : ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    // narrow tile (NW: at most 8 map sets, the first 16 columns): the four waves
+    // split the tile's output blocks instead of its columns
+    // (waves 0 and 1: the Q sums of ring tiles 0 and 1; waves 2 and 3: the iU sums)
+    auto mineq = [&](int t) { return !NW || (t == (wave & 1) && wave < 2); };
+    auto mineu = [&](int t) { return !NW || (t == (wave & 1) && wave >= 2); };
     static_assert(A2_TR * SPT == NT, "one fill item per thread");
     constexpr bool filler = true;
     const int frl = lane & 31;
@@ -649,29 +668,30 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
                 const T(&d)[4][NU] = bb[ks & 1];
 #pragma unroll
                 for (int t = 0; t < 2; ++t) {
+                    if (!mineq(t) && !mineu(t)) continue;
                     const int o = kl * RS + 16 * t + (lane & 15);
                     const T pe = fb[o], pd = fb[CLS + o];
                     const T me = fb[FOFF + o], mo = fb[FOFF + CLS + o];
 #pragma unroll
                     for (int u = 0; u < NU; ++u) {
                         if constexpr (EB != 2) {
-                            u1[t][u] = MF::run(pe, d[0][u], u1[t][u]);
-                            u2[t][u] = MF::run(pd, d[1][u], u2[t][u]);
+                            if (mineq(t)) u1[t][u] = MF::run(pe, d[0][u], u1[t][u]);
+                            if (mineq(t)) u2[t][u] = MF::run(pd, d[1][u], u2[t][u]);
                         }
                         if constexpr (EB != 1) {
-                            v1[t][u] = MF::run(pe, d[2][u], v1[t][u]);
-                            v2[t][u] = MF::run(pd, d[3][u], v2[t][u]);
+                            if (mineu(t)) v1[t][u] = MF::run(pe, d[2][u], v1[t][u]);
+                            if (mineu(t)) v2[t][u] = MF::run(pd, d[3][u], v2[t][u]);
                         }
                     }
 #pragma unroll
                     for (int u = 0; u < NU; ++u) {
                         if constexpr (EB != 2) {
-                            v1[t][u] = MF::run(mo, d[1][u], v1[t][u]);
-                            v2[t][u] = MF::run(me, d[0][u], v2[t][u]);
+                            if (mineu(t)) v1[t][u] = MF::run(mo, d[1][u], v1[t][u]);
+                            if (mineu(t)) v2[t][u] = MF::run(me, d[0][u], v2[t][u]);
                         }
                         if constexpr (EB != 1) {
-                            u1[t][u] = MF::run(mo, d[3][u], u1[t][u]);
-                            u2[t][u] = MF::run(me, d[2][u], u2[t][u]);
+                            if (mineq(t)) u1[t][u] = MF::run(mo, d[3][u], u1[t][u]);
+                            if (mineq(t)) u2[t][u] = MF::run(me, d[2][u], u2[t][u]);
                         }
                     }
                 }
@@ -699,11 +719,13 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2(LegArgs a)
             for (int u = 0; u < NU; ++u) {
                 const T U1 = u1[t][u][v], U2 = u2[t][u][v];
                 const T V1 = v1[t][u][v], V2 = v2[t][u][v];
-                put_out(&XQ[(int64_t)r * a.ldx + 16 * u], (T)(U1 + U2), a.ksplit > 1);
-                put_out(&XU[(int64_t)r * a.ldx + 16 * u], flip((T)(V1 + V2), usg), a.ksplit > 1);
-                if (rs != r) {
-                    put_out(&XQ[(int64_t)rs * a.ldx + 16 * u], (T)(U1 - U2), a.ksplit > 1);
-                    put_out(&XU[(int64_t)rs * a.ldx + 16 * u], flip((T)(V1 - V2), usg), a.ksplit > 1);
+                if (mineq(t)) {
+                    put_out(&XQ[(int64_t)r * a.ldx + 16 * u], (T)(U1 + U2), a.ksplit > 1);
+                    if (rs != r) put_out(&XQ[(int64_t)rs * a.ldx + 16 * u], (T)(U1 - U2), a.ksplit > 1);
+                }
+                if (mineu(t)) {
+                    put_out(&XU[(int64_t)r * a.ldx + 16 * u], flip((T)(V1 + V2), usg), a.ksplit > 1);
+                    if (rs != r) put_out(&XU[(int64_t)rs * a.ldx + 16 * u], flip((T)(V1 - V2), usg), a.ksplit > 1);
                 }
             }
         }
@@ -729,7 +751,8 @@ hipError_t launch_m2a_t(const LegArgs& a, hipStream_t st)
         const int nu = pick_nu(4, a.ldx);
         b.ctiles = (int)(a.ldx / (64 * nu));
         const dim3 grid(b.ntiles * b.ctiles * kparts(a));
-        if (nu == 4) hipLaunchKernelGGL((k_m2a_spin0<T, 4>), grid, blk, 0, st, b);
+        if (narrow(a)) hipLaunchKernelGGL((k_m2a_spin0<T, 1, true>), grid, blk, 0, st, b);
+        else if (nu == 4) hipLaunchKernelGGL((k_m2a_spin0<T, 4>), grid, blk, 0, st, b);
         else if (nu == 2) hipLaunchKernelGGL((k_m2a_spin0<T, 2>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_m2a_spin0<T, 1>), grid, blk, 0, st, b);
     } else {
@@ -740,6 +763,10 @@ hipError_t launch_m2a_t(const LegArgs& a, hipStream_t st)
             if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2<T, 2, 1>), grid, blk, 0, st, b);
             else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2<T, 2, 2>), grid, blk, 0, st, b);
             else hipLaunchKernelGGL((k_m2a_spin2<T, 2, 0>), grid, blk, 0, st, b);
+        } else if (narrow(a)) {
+            if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2<T, 1, 1, true>), grid, blk, 0, st, b);
+            else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2<T, 1, 2, true>), grid, blk, 0, st, b);
+            else hipLaunchKernelGGL((k_m2a_spin2<T, 1, 0, true>), grid, blk, 0, st, b);
         } else {
             if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2<T, 1, 1>), grid, blk, 0, st, b);
             else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2<T, 1, 2>), grid, blk, 0, st, b);
@@ -765,7 +792,8 @@ hipError_t launch_a2m_t(const LegArgs& a, hipStream_t st)
                 return hipGetLastError();
             }
         }
-        if (nu == 1) hipLaunchKernelGGL((k_a2m_spin0<T, 1>), grid, blk, 0, st, b);
+        if (narrow(a)) hipLaunchKernelGGL((k_a2m_spin0<T, 1, true>), grid, blk, 0, st, b);
+        else if (nu == 1) hipLaunchKernelGGL((k_a2m_spin0<T, 1>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_a2m_spin0<T, 2>), grid, blk, 0, st, b);
     } else {
         const int nu = pick_nu(2, a.ldx);
@@ -775,6 +803,10 @@ hipError_t launch_a2m_t(const LegArgs& a, hipStream_t st)
             if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2<T, 2, 1>), grid, blk, 0, st, b);
             else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2<T, 2, 2>), grid, blk, 0, st, b);
             else hipLaunchKernelGGL((k_a2m_spin2<T, 2, 0>), grid, blk, 0, st, b);
+        } else if (narrow(a)) {
+            if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2<T, 1, 1, true>), grid, blk, 0, st, b);
+            else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2<T, 1, 2, true>), grid, blk, 0, st, b);
+            else hipLaunchKernelGGL((k_a2m_spin2<T, 1, 0, true>), grid, blk, 0, st, b);
         } else {
             if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2<T, 1, 1>), grid, blk, 0, st, b);
             else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2<T, 1, 2>), grid, blk, 0, st, b);

@@ -162,7 +162,7 @@ __device__ __forceinline__ const float* fptr(const void* base, int64_t comp, int
 // map2alm, spin 0.  Tile 64 l x 64*NU columns, rings in chunks of 32.
 // LDS: [buffer][hi, lo][parity class][class row][ring (K)].
 // ============================================================================
-template <int NU>
+template <int NU, bool NW = false>
 __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
 {
     constexpr int CLS = HALF * KP, PL = 2 * CLS, BUF = 3 * PL;
@@ -175,7 +175,10 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
     const int L = a.lmax, lb = m;
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int lane = threadIdx.x & 63, wave = wave_index();
-    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    const int col = NW ? (lane & 15) : ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    // narrow tile (NW: at most 8 map sets, the first 16 columns): the four waves
+    // split the tile's output blocks instead of its columns
+    auto mine = [&](int p, int t) { return !NW || (p == (wave >> 1) && t == (wave & 1)); };
     const int k0 = 8 * (lane >> 4);
     // fill items: 32 rings x SPT segments, one per lane (segment uniform per half-wave)
     static_assert(32 * SPT == NT, "one fill item per thread");
@@ -276,8 +279,8 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
                     s8[e] = xr[0][u][e] + xr[1][u][e];
                     d8[e] = xr[0][u][e] - xr[1][u][e];
                 }
-                split8(s8, bs[0][u]);
-                split8(d8, bs[1][u]);
+                if (!NW || wave < 2) split8(s8, bs[0][u]);   // narrow: only the waves of the class
+                if (!NW || wave >= 2) split8(d8, bs[1][u]);
             }
             load_x(rcn);
             seed_of(sd, min(rc + 2, nchunk - 1));
@@ -288,10 +291,12 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
                 constexpr int P = decltype(ph)::v;
                 if constexpr ((P & 1) == 0) {
                     constexpr int cls = (P >> 2) & 1, t = (P >> 1) & 1;
-                    const __bf16* q = lb_ + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
-                    const S3 a3 = lds3<PL>(q);
+                    if (mine(cls, t)) {
+                        const __bf16* q = lb_ + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
+                        const S3 a3 = lds3<PL>(q);
 #pragma unroll
-                    for (int u = 0; u < NU; ++u) acc[cls][t][u] = mfma6(a3, bs[cls][u], acc[cls][t][u]);
+                        for (int u = 0; u < NU; ++u) acc[cls][t][u] = mfma6(a3, bs[cls][u], acc[cls][t][u]);
+                    }
                 }
                 if (filler) rec_group<P, RPP>(f, cp, cnt, em);
             });
@@ -306,6 +311,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
+                if (!mine(p, t)) continue;
                 const int ci = 16 * t + 4 * (lane >> 4) + v;
                 const int l = l0 + 2 * ci + p;
                 if (l > L) continue;
@@ -318,7 +324,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0_bf(LegArgs a)
 // map2alm, spin 2 (see k_m2a_spin2 in k_leg.hip for the block form and EB).
 // LDS: [buffer][hi, lo][F+, F-][parity class][class row][ring (K)].
 // ============================================================================
-template <int NU, int EB>
+template <int NU, int EB, bool NW = false>
 __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
 {
     constexpr int CLS = HALF * KP, FOFF = 2 * CLS, PL = 2 * FOFF, BUF = 3 * PL;
@@ -332,7 +338,10 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
     const int l0 = lb + lt * TL, lend = min(L, l0 + TL - 1);
     const int po = (lb - m) & 1;
     const int lane = threadIdx.x & 63, wave = wave_index();
-    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    const int col = NW ? (lane & 15) : ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    // narrow tile (NW: at most 8 map sets, the first 16 columns): the four waves
+    // split the tile's output blocks instead of its columns
+    auto mine = [&](int p, int t) { return !NW || (p == (wave >> 1) && t == (wave & 1)); };
     const int pcol = col ^ 1;
     const unsigned ysg = (col & 1) ? 0u : 0x80000000u;
     const int k0 = 8 * (lane >> 4);
@@ -456,19 +465,21 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
                 constexpr int P = decltype(ph)::v;
                 if constexpr ((P & 1) == 0) {
                     constexpr int cls = (P >> 2) & 1, t = (P >> 1) & 1;
-                    const __bf16* q = fb + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
-                    const S3 fp = lds3<PL>(q), fm = lds3<PL>(q + FOFF);  // F+, F-
-                    // even class: E = F+ SX + F- DY, B' = F+ SY + F- DX; odd: S <-> D
-                    constexpr int X1 = cls ? 1 : 0, Y1 = cls ? 3 : 2, X2 = cls ? 0 : 1, Y2 = cls ? 2 : 3;
+                    if (mine(cls, t)) {
+                        const __bf16* q = fb + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
+                        const S3 fp = lds3<PL>(q), fm = lds3<PL>(q + FOFF);  // F+, F-
+                        // even class: E = F+ SX + F- DY, B' = F+ SY + F- DX; odd: S <-> D
+                        constexpr int X1 = cls ? 1 : 0, Y1 = cls ? 3 : 2, X2 = cls ? 0 : 1, Y2 = cls ? 2 : 3;
 #pragma unroll
-                    for (int u = 0; u < NU; ++u) {
-                        if constexpr (EB != 2) {
-                            accE[cls][t][u] = mfma6(fp, bs[X1][u], accE[cls][t][u]);
-                            accE[cls][t][u] = mfma6(fm, bs[Y2][u], accE[cls][t][u]);
-                        }
-                        if constexpr (EB != 1) {
-                            accB[cls][t][u] = mfma6(fp, bs[Y1][u], accB[cls][t][u]);
-                            accB[cls][t][u] = mfma6(fm, bs[X2][u], accB[cls][t][u]);
+                        for (int u = 0; u < NU; ++u) {
+                            if constexpr (EB != 2) {
+                                accE[cls][t][u] = mfma6(fp, bs[X1][u], accE[cls][t][u]);
+                                accE[cls][t][u] = mfma6(fm, bs[Y2][u], accE[cls][t][u]);
+                            }
+                            if constexpr (EB != 1) {
+                                accB[cls][t][u] = mfma6(fp, bs[Y1][u], accB[cls][t][u]);
+                                accB[cls][t][u] = mfma6(fm, bs[X2][u], accB[cls][t][u]);
+                            }
                         }
                     }
                 }
@@ -486,6 +497,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
+                if (!mine(p, t)) continue;
                 const int ci = 16 * t + 4 * (lane >> 4) + v;
                 const int l = l0 + 2 * ci + (p ^ po);
                 if (l > L) continue;
@@ -504,7 +516,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin2_bf(LegArgs a)
 // ============================================================================
 constexpr int A0_TR = 64;
 
-template <int NU>
+template <int NU, bool NW = false>
 __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
 {
     constexpr int CLS = A0_TR * KP, PL = 2 * CLS, BUF = 3 * PL;
@@ -521,7 +533,10 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
     const int L = a.lmax, lb = m;
     const int r0 = rt * A0_TR;
     const int lane = threadIdx.x & 63, wave = wave_index();
-    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    const int col = NW ? (lane & 15) : ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    // narrow tile (NW: at most 8 map sets, the first 16 columns): the four waves
+    // split the tile's output blocks instead of its columns
+    auto mine = [&](int t) { return !NW || t == wave; };
     const int k0 = 8 * (lane >> 4);
     // fill items: 64 rings x SPT segments, two per lane: ring = lane, segments
     // wave and wave + 4 (wave-uniform)
@@ -620,12 +635,14 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
             static_for<0, NPH>([&](auto ph) {
                 constexpr int P = decltype(ph)::v;
                 constexpr int cls = P >> 2, t = P & 3;
-                const __bf16* q = lb_ + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
-                const S3 a3 = lds3<PL>(q);
+                if (mine(t)) {
+                    const __bf16* q = lb_ + cls * CLS + (16 * t + (lane & 15)) * KP + k0;
+                    const S3 a3 = lds3<PL>(q);
 #pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    if constexpr (cls == 0) accE[t][u] = mfma6(a3, bs[0][u], accE[t][u]);
-                    else accO[t][u] = mfma6(a3, bs[1][u], accO[t][u]);
+                    for (int u = 0; u < NU; ++u) {
+                        if constexpr (cls == 0) accE[t][u] = mfma6(a3, bs[0][u], accE[t][u]);
+                        else accO[t][u] = mfma6(a3, bs[1][u], accO[t][u]);
+                    }
                 }
                 rec_group<P, RPP>(f[0], cp0, cnt0, em0);
                 rec_group<P, RPP>(f[1], cp1, cnt1, em1);
@@ -641,6 +658,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+            if (!mine(t)) continue;
             const int r = r0 + 16 * t + 4 * (lane >> 4) + v;
             if (r >= a.rn) continue;
             const int rs = a.nring - 1 - r;
@@ -660,7 +678,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
 constexpr int A2_TR = 32;
 
 // EB = 1 (E only) or 2 (B only): the half-block transforms, as in k_leg.hip
-template <int NU, int EB>
+template <int NU, int EB, bool NW = false>
 __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
 {
     constexpr int CLS = A2_TR * KP, FOFF = 2 * CLS, PL = 2 * FOFF, BUF = 3 * PL;
@@ -678,7 +696,12 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
     const int po = (lb - m) & 1;
     const int r0 = rt * A2_TR;
     const int lane = threadIdx.x & 63, wave = wave_index();
-    const int col = ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    const int col = NW ? (lane & 15) : ct * (64 * NU) + 16 * NU * wave + (lane & 15);
+    // narrow tile (NW: at most 8 map sets, the first 16 columns): the four waves
+    // split the tile's output blocks instead of its columns
+    // (waves 0 and 1: the Q sums of ring tiles 0 and 1; waves 2 and 3: the iU sums)
+    auto mineq = [&](int t) { return !NW || (t == (wave & 1) && wave < 2); };
+    auto mineu = [&](int t) { return !NW || (t == (wave & 1) && wave >= 2); };
     const int k0 = 8 * (lane >> 4);
     // fill items: 32 rings x SPT segments, one per lane (segment uniform per half-wave)
     static_assert(32 * SPT == NT, "one fill item per thread");
@@ -787,28 +810,30 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
                 if constexpr (pu < 4) {
                     constexpr int t = pu & 1, second = pu >> 1;
                     const __bf16* q = fb + (16 * t + (lane & 15)) * KP + k0;
+                    if (mineq(t) || mineu(t)) {
                     if constexpr (!second) {
                         // F+ terms: U1 += F+e E_e, U2 += F+o E_o, V1 += F+e B'_e, V2 += F+o B'_o
                         const S3 fe = lds3<PL>(q), fo = lds3<PL>(q + CLS);
                         if constexpr (EB != 2) {
-                            u1[t][u] = mfma6(fe, bs[0], u1[t][u]);
-                            u2[t][u] = mfma6(fo, bs[1], u2[t][u]);
+                            if (mineq(t)) u1[t][u] = mfma6(fe, bs[0], u1[t][u]);
+                            if (mineq(t)) u2[t][u] = mfma6(fo, bs[1], u2[t][u]);
                         }
                         if constexpr (EB != 1) {
-                            v1[t][u] = mfma6(fe, bs[2], v1[t][u]);
-                            v2[t][u] = mfma6(fo, bs[3], v2[t][u]);
+                            if (mineu(t)) v1[t][u] = mfma6(fe, bs[2], v1[t][u]);
+                            if (mineu(t)) v2[t][u] = mfma6(fo, bs[3], v2[t][u]);
                         }
                     } else {
                         // F- terms: U1 += F-o B'_o, U2 += F-e B'_e, V1 += F-o E_o, V2 += F-e E_e
                         const S3 fe = lds3<PL>(q + FOFF), fo = lds3<PL>(q + FOFF + CLS);
                         if constexpr (EB != 1) {
-                            u1[t][u] = mfma6(fo, bs[3], u1[t][u]);
-                            u2[t][u] = mfma6(fe, bs[2], u2[t][u]);
+                            if (mineq(t)) u1[t][u] = mfma6(fo, bs[3], u1[t][u]);
+                            if (mineq(t)) u2[t][u] = mfma6(fe, bs[2], u2[t][u]);
                         }
                         if constexpr (EB != 2) {
-                            v1[t][u] = mfma6(fo, bs[1], v1[t][u]);
-                            v2[t][u] = mfma6(fe, bs[0], v2[t][u]);
+                            if (mineu(t)) v1[t][u] = mfma6(fo, bs[1], v1[t][u]);
+                            if (mineu(t)) v2[t][u] = mfma6(fe, bs[0], v2[t][u]);
                         }
+                    }
                     }
                 }
                 if (filler) rec_group<P, RPP>(f, cp, cnt, em);
@@ -834,11 +859,13 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
             for (int u = 0; u < NU; ++u) {
                 const float U1 = u1[t][u][v], U2 = u2[t][u][v];
                 const float V1 = v1[t][u][v], V2 = v2[t][u][v];
-                put_out(&XQ[(int64_t)r * a.ldx + 16 * u], (float)(U1 + U2), a.ksplit > 1);
-                put_out(&XU[(int64_t)r * a.ldx + 16 * u], (float)flip(V1 + V2, usg), a.ksplit > 1);
-                if (rs != r) {
-                    put_out(&XQ[(int64_t)rs * a.ldx + 16 * u], (float)(U1 - U2), a.ksplit > 1);
-                    put_out(&XU[(int64_t)rs * a.ldx + 16 * u], (float)flip(V1 - V2, usg), a.ksplit > 1);
+                if (mineq(t)) {
+                    put_out(&XQ[(int64_t)r * a.ldx + 16 * u], (float)(U1 + U2), a.ksplit > 1);
+                    if (rs != r) put_out(&XQ[(int64_t)rs * a.ldx + 16 * u], (float)(U1 - U2), a.ksplit > 1);
+                }
+                if (mineu(t)) {
+                    put_out(&XU[(int64_t)r * a.ldx + 16 * u], (float)flip(V1 + V2, usg), a.ksplit > 1);
+                    if (rs != r) put_out(&XU[(int64_t)rs * a.ldx + 16 * u], (float)flip(V1 - V2, usg), a.ksplit > 1);
                 }
             }
         }
@@ -851,7 +878,10 @@ hipError_t launch_leg_m2a_bf16(const LegArgs& a, hipStream_t st)
     LegArgs b = a;
     const dim3 blk(NT);
     if (a.spin == 0) {
-        if (a.ldx % 128 == 0) {
+        if (narrow(a)) {
+            b.ctiles = 1;
+            hipLaunchKernelGGL((k_m2a_spin0_bf<1, true>), dim3(b.ntiles * kparts(a)), blk, 0, st, b);
+        } else if (a.ldx % 128 == 0) {
             b.ctiles = (int)(a.ldx / 128);
             hipLaunchKernelGGL((k_m2a_spin0_bf<2>), dim3(b.ntiles * b.ctiles * kparts(a)), blk, 0, st, b);
         } else {
@@ -864,7 +894,11 @@ hipError_t launch_leg_m2a_bf16(const LegArgs& a, hipStream_t st)
         // may hold at two waves per SIMD
         b.ctiles = (int)(a.ldx / 64);
         const dim3 grid(b.ntiles * b.ctiles * kparts(a));
-        if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 1>), grid, blk, 0, st, b);
+        if (narrow(a)) {
+            if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 1, true>), grid, blk, 0, st, b);
+            else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 2, true>), grid, blk, 0, st, b);
+            else hipLaunchKernelGGL((k_m2a_spin2_bf<1, 0, true>), grid, blk, 0, st, b);
+        } else if (a.eb == 1) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 1>), grid, blk, 0, st, b);
         else if (a.eb == 2) hipLaunchKernelGGL((k_m2a_spin2_bf<1, 2>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_m2a_spin2_bf<1, 0>), grid, blk, 0, st, b);
     }
@@ -879,12 +913,17 @@ hipError_t launch_leg_a2m_bf16(const LegArgs& a, hipStream_t st)
         const int nu = a.ldx % 128 == 0 ? 2 : 1;
         b.ctiles = (int)(a.ldx / (64 * nu));
         const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A0_TR - 1) / A0_TR) * kparts(a));
-        if (nu == 2) hipLaunchKernelGGL((k_a2m_spin0_bf<2>), grid, blk, 0, st, b);
+        if (narrow(a)) hipLaunchKernelGGL((k_a2m_spin0_bf<1, true>), grid, blk, 0, st, b);
+        else if (nu == 2) hipLaunchKernelGGL((k_a2m_spin0_bf<2>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_a2m_spin0_bf<1>), grid, blk, 0, st, b);
     } else {
         b.ctiles = (int)(a.ldx / 64);
         const dim3 grid(nm_rows(a) * b.ctiles * ((a.rn + A2_TR - 1) / A2_TR) * kparts(a));
-        if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2_bf<1, 1>), grid, blk, 0, st, b);
+        if (narrow(a)) {
+            if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2_bf<1, 1, true>), grid, blk, 0, st, b);
+            else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2_bf<1, 2, true>), grid, blk, 0, st, b);
+            else hipLaunchKernelGGL((k_a2m_spin2_bf<1, 0, true>), grid, blk, 0, st, b);
+        } else if (a.eb == 1) hipLaunchKernelGGL((k_a2m_spin2_bf<1, 1>), grid, blk, 0, st, b);
         else if (a.eb == 2) hipLaunchKernelGGL((k_a2m_spin2_bf<1, 2>), grid, blk, 0, st, b);
         else hipLaunchKernelGGL((k_a2m_spin2_bf<1, 0>), grid, blk, 0, st, b);
     }

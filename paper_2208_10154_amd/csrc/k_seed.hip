@@ -22,6 +22,7 @@ __global__ __launch_bounds__(128) void k_seeds(SeedArgs a)
     const int L = a.lmax;
     const int lb = lbase(a.spin, m);
     if (lb > L) return;
+    if (a.seedoff[m + 1] == a.seedoff[m]) return;  // an m the plan does not own: no seeds
     const double x = a.rings[r].z;
     const int64_t base = a.seedoff[m] + r;
     const int64_t st = a.seedstride;
@@ -106,6 +107,7 @@ __global__ __launch_bounds__(256) void k_coefs(double* coef, const int64_t* rowo
     const int lb = lbase(spin, m);
     const int l = lb + blockIdx.x * blockDim.x + threadIdx.x;
     if (l > lmax) return;
+    if (rowoff[m + 1] == rowoff[m]) return;  // an m the plan does not own: no rows
     if (spin == 0) {
         double* c = coef + (rowoff[m] + (l - lb)) * 2;
         coef_spin0(l, m, c[0], c[1]);

@@ -79,6 +79,7 @@ struct sht_plan_s {
     std::vector<FftClass> classes;  // the current width's classes
     int items_npairs = -1;
     int64_t ldx_cur = 0;            // row pitch of the m-major arrays for the chunk being run
+    int nm_cur = 0;                 // map sets of the chunk being run
 
     // workspace
     void* ws = nullptr;
@@ -101,6 +102,12 @@ struct sht_plan_s {
         std::vector<int> ntiles0, ntiles2;     // per level: l tiles of the listed m per spin
         Dev mlist, pref0, pref2, cmin;         // device: m per entry; per-level tile prefix sums
     } lev;
+
+    // part `part` of `nparts` of the orders m (sht_plan_create_part): own[m] = 1 for
+    // the m this plan transforms; d_own its device copy, d_mlist the owned m
+    int part = 0, nparts = 1, nown = 0;
+    std::vector<unsigned char> own;
+    Dev d_own, d_mlist;
 
     // optional per-stage profiling
     bool profiling = false;
@@ -128,6 +135,10 @@ struct StageTimer {
         p->recs.push_back(sht_plan_s::Rec{stage, a, b});
     }
 };
+
+// whether the plan transforms order m: pairs (q, lmax - q) of the folded order
+// 0, lmax, 1, lmax - 1, ... are dealt to the parts in turn, q mod nparts
+bool owns(sht_plan p, int m) { return p->nparts <= 1 || p->own[m]; }
 
 int dev_alloc(sht_plan p, Dev& d, size_t bytes)
 {
@@ -258,6 +269,24 @@ int build_fft(sht_plan p)
             } else {
                 L.m = smooth_at_least(2 * r.n - 1);
             }
+            if (L.m > 16 * FFT_THREADS && r.n <= 16 * FFT_THREADS) {
+                // the convolution would not fit the LDS: direct DFT of the ring
+                // (its n values fit), one map pair per workgroup
+                L.blue = 0;
+                L.direct = 1;
+                L.m = 0;
+                L.bp2 = 0;
+                L.nstage = 0;
+                L.nseq = 1;
+                L.lgseq = 0;
+                L.ldsc = r.n;
+                L.lstride = r.n + r.n / 16 + 16;
+                L.lds = L.lstride;
+                r.len = (int)p->lens.size();
+                len_index[r.n] = r.len;
+                p->lens.push_back(L);
+                continue;
+            }
             factor_radices(L.m, rad);
             if (!tw_of.count(L.m)) { tw_of[L.m] = (int64_t)pool.size(); push_twiddles(pool, L.m); }
             L.twm = tw_of[L.m];
@@ -347,8 +376,8 @@ int build_items(sht_plan p, int npairs)
         return SHT_OK;
     }
     // classes 0..2: runtime-length kernels by LDS size; 3 + (k - 6): length 2^k;
-    // 10 + (k - 6): Bluestein through length 2^k
-    constexpr int NCLS = 3 + 7 + 7;
+    // 10 + (k - 6): Bluestein through length 2^k; 17: direct DFT
+    constexpr int NCLS = 3 + 7 + 7 + 1;
     std::vector<FftItem> cls_items[NCLS];
     int lds[NCLS] = {};
     for (int r = 0; r < p->nring; ++r) {
@@ -356,6 +385,7 @@ int build_items(sht_plan p, int npairs)
         int c = (L.ldsc <= 2 * FFT_THREADS) ? 0 : (L.ldsc <= 8 * FFT_THREADS ? 1 : 2);
         if (L.p2) c = 3 + (L.p2 - 6);
         if (L.bp2) c = 10 + (L.bp2 - 6);
+        if (L.direct) c = NCLS - 1;
         lds[c] = std::max(lds[c], L.lds);
         if (npairs % L.nseq) return fail(SHT_ERR_UNSUPPORTED, "map pairs per chunk not a multiple of the ring batch");
         for (int q = 0; q < npairs; q += L.nseq) cls_items[c].push_back(FftItem{r, q});
@@ -374,8 +404,9 @@ int build_items(sht_plan p, int npairs)
     for (int c = 0; c < NCLS; ++c) {
         const int elems = c == 0 ? 2 : (c == 2 ? 16 : 8);
         const int lg = c >= 10 ? c - 10 + 6 : (c >= 3 ? c - 3 + 6 : 0);
+        const bool dir = (c == NCLS - 1);
         set.classes.push_back(FftClass{(const FftItem*)set.dev.p + off[c], (int)cls_items[c].size(), lds[c], elems,
-                                       lg, c >= 10 ? 1 : 0});
+                                       dir ? 0 : lg, (c >= 10 && !dir) ? 1 : 0, dir ? 1 : 0});
     }
     p->classes = set.classes;
     p->item_sets.emplace(npairs, std::move(set));
@@ -406,6 +437,7 @@ int build_seeds(sht_plan p, SeedSet& S, int spin)
         ld lognorm = -0.5L * log2l(4.0L * PI_L);
         for (int m = 0; m <= L; ++m) {
             if (m > 0) lognorm += 0.5L * log2l((ld)(2 * m + 1) / (ld)(2 * m));
+            if (!owns(p, m)) continue;
             double sign = (m & 1) ? -1.0 : 1.0;
             for (int r = 0; r < rn; ++r) {
                 ld t = lognorm + (ld)m * log2l((ld)p->rings[r].sth);
@@ -415,6 +447,7 @@ int build_seeds(sht_plan p, SeedSet& S, int spin)
     } else {
         // {}_{+-2}lambda_{lb} = sqrt((2lb+1)/4pi) d^{lb}_{m,-+2}(theta), lb = max(m, 2)
         for (int m = 0; m <= L; ++m) {
+            if (!owns(p, m)) continue;
             int lb = std::max(m, 2);
             ld lnorm = 0.5L * logl((ld)(2 * lb + 1) / (4.0L * PI_L));
             for (int r = 0; r < rn; ++r) {
@@ -454,10 +487,11 @@ int build_seeds(sht_plan p, SeedSet& S, int spin)
         seedoff[m] = tot;
         tileoff[m] = tt;
         rowoff[m] = rows;
-        int ns = nsegs(spin, L, m);
+        // an m the plan does not own has no seeds, l tiles or coefficient rows
+        const int ns = owns(p, m) ? nsegs(spin, L, m) : 0;
         tot += (int64_t)ns * rn;
         tt += (ns + SPT - 1) / SPT;  // l tiles of TL = SPT segments
-        rows += std::max(0, L + 1 - lbase(spin, m));
+        rows += owns(p, m) ? std::max(0, L + 1 - lbase(spin, m)) : 0;
     }
     seedoff[L + 1] = tot;
     tileoff[L + 1] = tt;
@@ -648,12 +682,14 @@ FftArgs fft_args(sht_plan p, int nmaps_chunk)
     a.nring = p->nring;
     a.xcomp = xcomp_elems(p);
     a.x32 = (p->prec != SHT_FP64);
+    a.mown = p->nparts > 1 ? (const unsigned char*)p->d_own.p : nullptr;
     return a;
 }
 
 LegArgs leg_args(sht_plan p, const SeedSet& S)
 {
     LegArgs a{};
+    a.ncols = 2 * p->nm_cur;
     a.rings = p->d_rings;
     a.mu = (const double*)S.mu.p;
     a.kk = (const int*)S.kk.p;
@@ -702,6 +738,7 @@ int prep(sht_plan p)
     int rc = ensure_workspace(p);
     if (rc) return rc;
     p->ldx_cur = ldx_for(p->chunk);
+    p->nm_cur = p->chunk;
     return build_items(p, (int)(p->ldx_cur / 4));
 }
 
@@ -711,6 +748,7 @@ int prep(sht_plan p)
 int use_width(sht_plan p, int nm)
 {
     p->ldx_cur = ldx_for(nm);
+    p->nm_cur = nm;
     return build_items(p, (int)(p->ldx_cur / 4));
 }
 
@@ -751,6 +789,15 @@ int run_to_mmajor(sht_plan p, const double* alm, int nm, int sel)
     return SHT_OK;
 }
 
+// a plan owning part of the m runs the alm2map kernels on its m list (the
+// map2alm kernels and the layout kernels find no tiles for the other m)
+void own_list(sht_plan p, LegArgs& a)
+{
+    if (p->nparts <= 1) return;
+    a.mlist = (const int*)p->d_mlist.p;
+    a.nlist = p->nown;
+}
+
 // m-major rows -> ring Fourier coefficients of the selected components
 int run_leg_a2m(sht_plan p, int sel)
 {
@@ -758,12 +805,14 @@ int run_leg_a2m(sht_plan p, int sel)
         StageTimer t(p, SHT_STAGE_A2M_SPIN0);
         LegArgs a = leg_args(p, p->s0);
         a.A = ws_Aop(p);
+        own_list(p, a);
         HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
     }
     if (sel_pol(p, sel)) {
         StageTimer t(p, SHT_STAGE_A2M_SPIN2);
         LegArgs a = leg_args(p, p->s2);
         a.A = ws_Aop(p);
+        own_list(p, a);
         a.eb = sel_eb(sel);
         HIPCHK(launch_leg_a2m(a, p->prec, p->stream));
     }
@@ -962,6 +1011,14 @@ int run_level(sht_plan p, double* alm, int nm, int d)
     return SHT_OK;
 }
 
+// the calls a plan owning part of the m does not offer
+int whole_only(sht_plan p, const char* what)
+{
+    if (p && p->nparts > 1)
+        return fail(SHT_ERR_UNSUPPORTED, std::string(what) + " needs a plan of all orders m (sht_plan_create)");
+    return SHT_OK;
+}
+
 int check_ready(sht_plan p)
 {
     if (!p) return fail(SHT_ERR_ARG, "null plan");
@@ -1004,7 +1061,11 @@ extern "C" {
 
 const char* sht_last_error(void) { return g_err.c_str(); }
 
-int sht_plan_create(sht_plan* out, int nside, int lmax, int spin, int nmaps)
+}  // extern "C"
+
+namespace {
+
+int create_plan(sht_plan* out, int nside, int lmax, int spin, int nmaps, int part, int nparts)
 {
     g_err.clear();
     if (!out) return fail(SHT_ERR_ARG, "out is NULL");
@@ -1014,8 +1075,8 @@ int sht_plan_create(sht_plan* out, int nside, int lmax, int spin, int nmaps)
     if (spin != 0 && spin != 2) return fail(SHT_ERR_ARG, "spin must be 0 or 2");
     if (spin == 2 && lmax < 2) return fail(SHT_ERR_ARG, "spin 2 needs lmax >= 2");
     if (nmaps < 1) return fail(SHT_ERR_ARG, "nmaps must be >= 1");
-    if (lmax > 4094) return fail(SHT_ERR_UNSUPPORTED, "lmax above 4094 is not supported");
-    if (nside > 1024) return fail(SHT_ERR_UNSUPPORTED, "nside above 1024 is not supported (ring FFT LDS plan)");
+    if (nparts < 1 || part < 0 || part >= nparts) return fail(SHT_ERR_ARG, "part must be in [0, nparts)");
+    if (nside > 2048) return fail(SHT_ERR_UNSUPPORTED, "nside above 2048 is not supported (ring FFT LDS plan)");
     sht_plan p = new sht_plan_s();
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) { delete p; return fail(SHT_ERR_DEVICE, "no HIP device"); }
@@ -1027,9 +1088,25 @@ int sht_plan_create(sht_plan* out, int nside, int lmax, int spin, int nmaps)
     p->cap = nmaps;
     p->nmaps = nmaps;
     p->stream = nullptr;
+    p->part = part;
+    p->nparts = nparts;
+    std::vector<int> mlist;
+    if (nparts > 1) {
+        p->own.assign(lmax + 1, 0);
+        for (int i = 0; i <= lmax; ++i)
+            if ((i >> 1) % nparts == part) p->own[mfold(i, lmax)] = 1;
+        for (int m = 0; m <= lmax; ++m)
+            if (p->own[m]) mlist.push_back(m);
+        p->nown = (int)mlist.size();
+    } else {
+        p->nown = lmax + 1;
+    }
     build_rings(p);
     p->nrc = (p->rn + RCHUNK - 1) / RCHUNK;
     int rc = build_fft(p);
+    if (!rc && nparts > 1) rc = upload(p, p->d_own, p->own);
+    if (!rc && nparts > 1) rc = upload(p, p->d_mlist, mlist);
+    if (!rc && p->nown == 0) rc = fail(SHT_ERR_ARG, "this part owns no order m (more parts than m pairs)");
     if (!rc) rc = build_seeds(p, p->s0, 0);
     if (!rc && spin == 2) rc = build_seeds(p, p->s2, 2);
     if (!rc) rc = build_mcut(p);
@@ -1044,6 +1121,20 @@ int sht_plan_create(sht_plan* out, int nside, int lmax, int spin, int nmaps)
     if (rc) { destroy_all(p); return rc; }
     *out = p;
     return SHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sht_plan_create(sht_plan* out, int nside, int lmax, int spin, int nmaps)
+{
+    return create_plan(out, nside, lmax, spin, nmaps, 0, 1);
+}
+
+int sht_plan_create_part(sht_plan* out, int nside, int lmax, int spin, int nmaps, int part, int nparts)
+{
+    return create_plan(out, nside, lmax, spin, nmaps, part, nparts);
 }
 
 int sht_plan_destroy(sht_plan p)
@@ -1130,6 +1221,8 @@ int sht_alm2map_sel(sht_plan p, int comps, const double* alm, double* map)
     if (rc) return rc;
     if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
     if ((rc = valid_sel(p, comps))) return rc;
+    if (comps != (p->spin == 0 ? SHT_COMP_T : SHT_COMP_ALL) && (rc = whole_only(p, "a component selection")))
+        return rc;
     if ((rc = prep(p))) return rc;
     const int64_t astride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
     const int64_t mstride = (int64_t)p->ncomp * p->npix;
@@ -1153,6 +1246,8 @@ int sht_map2alm_sel(sht_plan p, int comps, const double* map, double* alm)
     if (rc) return rc;
     if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
     if ((rc = valid_sel(p, comps))) return rc;
+    if (comps != (p->spin == 0 ? SHT_COMP_T : SHT_COMP_ALL) && (rc = whole_only(p, "a component selection")))
+        return rc;
     if ((rc = prep(p))) return rc;
     const int64_t astride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
     const int64_t mstride = (int64_t)p->ncomp * p->npix;
@@ -1184,6 +1279,7 @@ int sht_eb_split(sht_plan p, const double* map, double* alm, double* map_e, doub
 {
     int rc = check_ready(p);
     if (rc) return rc;
+    if ((rc = whole_only(p, "E/B separation"))) return rc;
     if (!map || !alm || !map_e || !map_b) return fail(SHT_ERR_ARG, "null data pointer");
     if (p->spin != 2) return fail(SHT_ERR_ARG, "E/B separation needs a spin-2 plan");
     if (map_e == map_b) return fail(SHT_ERR_ARG, "map_e and map_b must be distinct arrays");
@@ -1215,6 +1311,7 @@ int sht_map2alm_iter(sht_plan p, const double* map, double* alm, int niter, doub
 {
     int rc = check_ready(p);
     if (rc) return rc;
+    if ((rc = whole_only(p, "the iteration"))) return rc;
     if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
     if (niter < 0) return fail(SHT_ERR_ARG, "niter must be >= 0");
     if ((rc = prep(p))) return rc;
@@ -1267,6 +1364,7 @@ int sht_map2alm_immediate(sht_plan p, const double* map, double* alm, int niter,
 {
     int rc = check_ready(p);
     if (rc) return rc;
+    if ((rc = whole_only(p, "the immediate iteration"))) return rc;
     if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
     if (niter < 0) return fail(SHT_ERR_ARG, "niter must be >= 0");
     if ((rc = prep(p))) return rc;

@@ -63,6 +63,7 @@ struct FftLen {
     int lds;                // complex LDS slots per workgroup = nseq * lstride
     int p2;                 // log2(n) when n is a power of two handled by k_fft_p2.hip, else 0
     int bp2;                // log2(m) when a Bluestein length m = 2^bp2 is handled by k_fft_p2.hip, else 0
+    int direct;             // 1: direct DFT in LDS (Bluestein would need a convolution beyond the LDS)
 };
 
 struct RingDev {
@@ -110,6 +111,9 @@ struct FftArgs {
     // immediate iteration: residual spectra, halfcomplex per ring, bin-major with the
     // maps of the chunk contiguous: R[(comp * npix + pixel slot) * nmaps + map]
     double* R;
+    // optional 0/1 per m (lmax + 1 entries): the inverse transforms fold only the
+    // rows of m marked 1 (a plan that owns a subset of the m)
+    const unsigned char* mown;
 };
 
 struct LegArgs {
@@ -147,7 +151,14 @@ struct LegArgs {
     // tiles) is split over ksplit workgroups that add into pre-zeroed outputs
     // (list mode, where one level's grid is too small to fill the chip)
     int ksplit;
+    int ncols;              // columns holding map sets in this chunk (2 per map set); the rest pad
 };
+
+// Narrow tiles: a chunk of at most 8 map sets (16 columns, inside one 64-column
+// tile) runs Legendre kernels whose four waves split the tile's output blocks
+// instead of its columns, so a small batch is not charged for the 24 padding map
+// sets of the tile.
+__host__ __device__ inline bool narrow(const LegArgs& a) { return a.ldx == 64 && a.ncols > 0 && a.ncols <= 16; }
 
 // Layout change compact alm <-> m-major rows (one spin's components per launch).
 struct AlmArgs {
@@ -220,6 +231,7 @@ struct FftClass {
     int elems;   // 2, 8 or 16
     int p2;      // 0: runtime-length kernels; else log2 of the (convolution) length (k_fft_p2.hip)
     int blue;    // with p2: Bluestein rings through a power-of-two convolution
+    int direct;  // direct-DFT rings (FftLen::direct), one map pair per workgroup
 };
 // power-of-two ring lengths 2^6 .. 2^12: map pairs per workgroup (0: not handled)
 int p2_seqs_per_group(int logn);

@@ -151,6 +151,7 @@ class Executor:
         import torch
         self.torch = torch
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self._idle = torch.cuda.Stream()  # plans are destroyed on it (it never carries work)
         self.graphs_enabled = graphs
         self._graphs = {}
         self._ref = torch.cuda.Event(enable_timing=True)
@@ -183,17 +184,25 @@ class Executor:
         return self.torch.empty(shape, dtype=self.torch.float64, device="cuda")
 
     def free_plan(self, plan) -> None:
-        self.torch.cuda.synchronize()
+        """Release an idle plan.  The server evicts only plans whose batches have all
+        retired (their completion events were seen), so none of its work is in
+        flight; its stream is pointed at a stream of its own that never carries
+        work, so destroying the plan waits for no other plan's batches."""
+        plan.set_stream(self._idle)
         plan.close()
+
+    def reclaim(self) -> None:
+        """Return device memory cached by torch but unused (freed request and slot
+        tensors) before the library allocates a plan."""
+        self.torch.cuda.empty_cache()
 
     # --- one batch
     def run(self, plan, stream_id, direction, precision, reqs, n, slot_in, slot_out):
         torch = self.torch
         s = self.streams[stream_id]
         plan.set_stream(s)
-        plan.set_precision(precision)
         width = bucket(n)
-        plan.set_chunk(width)
+        self._sized(plan, precision, width)
         with torch.cuda.stream(s):
             for r in reqs:
                 if r.ready is not None:
@@ -223,6 +232,19 @@ class Executor:
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(s)
         return ev
+
+    def _sized(self, plan, precision, width) -> None:
+        """Set the batch's precision and chunk; a workspace that grows may meet
+        device memory cached by torch, which is then given back once."""
+        for attempt in (0, 1):
+            try:
+                plan.set_precision(precision)
+                plan.set_chunk(width)
+                return
+            except sht.ShtError as e:
+                if e.code != SHT_ERR_NOMEM or attempt:
+                    raise
+                self.reclaim()
 
     def _transform(self, plan, s, direction, precision, width, n, slot_in, slot_out):
         torch = self.torch
@@ -274,8 +296,9 @@ class Server:
     finished batches, launches new ones), wait()/drain() block."""
 
     def __init__(self, hbm_budget_bytes: float, max_slots: int = 512, executor=None,
-                 slot_bytes_per_plan: float = 2e9, depth: int = 2):
+                 slot_bytes_per_plan: float = 8e9, depth: int = 2, batching: bool = True):
         self.budget = float(hbm_budget_bytes)
+        self.batching = bool(batching)  # False: one request per launch (the serial baseline)
         self.max_slots = int(max_slots)
         self.slot_bytes_per_plan = float(slot_bytes_per_plan)
         self.depth = depth
@@ -382,13 +405,38 @@ class Server:
             if not idle:
                 return None
             self._evict(min(idle)[1])
-        plan = self.ex.new_plan(req.nside, req.lmax, req.spin, slots)
+        plan = self._new_plan(req, slots)
+        if plan is None:
+            return None
         nbytes = max(est, self.ex.plan_bytes(plan, slots, "fp64"))
         p = _Plan(plan, 0, slots, nbytes)
         self.plans[pk] = p
         self.used += nbytes
         self.peak = max(self.peak, self.used)
         return p
+
+    def _new_plan(self, req: Request, slots: int):
+        """Create req's plan; when the device is out of memory (memory held outside
+        the server's account, such as cached request tensors), give cached memory
+        back and evict idle plans, then try again; None if nothing is left to free."""
+        while True:
+            try:
+                return self.ex.new_plan(req.nside, req.lmax, req.spin, slots)
+            except sht.ShtError as e:
+                if e.code != SHT_ERR_NOMEM:
+                    raise
+            reclaim = getattr(self.ex, "reclaim", None)
+            if reclaim is not None:
+                reclaim()
+                try:
+                    return self.ex.new_plan(req.nside, req.lmax, req.spin, slots)
+                except sht.ShtError as e:
+                    if e.code != SHT_ERR_NOMEM:
+                        raise
+            idle = [(q.last_use, k) for k, q in self.plans.items() if q.inflight == 0]
+            if not idle:
+                return None
+            self._evict(min(idle)[1])
 
     def _evict(self, pk) -> None:
         p = self.plans.pop(pk)
@@ -439,7 +487,7 @@ class Server:
     def _launch(self, key, q, p) -> bool:
         head = q[0]
         reqs, n = [], 0
-        while q and n + q[0].nmaps <= p.slots:
+        while q and n + q[0].nmaps <= p.slots and (self.batching or not reqs):
             r = q.popleft()
             reqs.append(r)
             n += r.nmaps
@@ -485,12 +533,12 @@ class Server:
 # ---------------------------------------------------------------------------
 def request_mix(n: int, rate_hz: float, seed: int = 5, nsides=(64, 128, 256, 512, 1024),
                 mixed: str = "bf16x3", median_maps: int = 16, sigma_ln: float = 1.0, max_maps: int = 512,
-                mapset_cap_bytes: float = 2e9):
+                mapset_cap_bytes: float | None = None):
     """n request descriptors (no data): Poisson arrivals at rate_hz, nside uniform
     over nsides (lmax = 3 nside - 1), T or IQU, alm2map or map2alm and FP64 or the
     mixed precision with probability 1/2 each, map count log-normal (median
-    median_maps, log-sd sigma_ln) capped at max_maps and at mapset_cap_bytes of
-    maps + alm per request."""
+    median_maps, log-sd sigma_ln) capped at max_maps (and, if given, at
+    mapset_cap_bytes of maps + alm per request)."""
     import numpy as np
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([220810154, 5, seed])))
     t = 0.0
@@ -502,31 +550,52 @@ def request_mix(n: int, rate_hz: float, seed: int = 5, nsides=(64, 128, 256, 512
         direction = "alm2map" if rng.random() < 0.5 else "map2alm"
         prec = "fp64" if rng.random() < 0.5 else mixed
         k = int(round(median_maps * np.exp(sigma_ln * rng.standard_normal())))
-        cap = max(1, int(mapset_cap_bytes // mapset_bytes(nside, lmax_of(nside), spin)))
-        k = max(1, min(k, max_maps, cap))
+        k = max(1, min(k, max_maps))
+        if mapset_cap_bytes is not None:
+            k = max(1, min(k, int(mapset_cap_bytes // mapset_bytes(nside, lmax_of(nside), spin))))
         out.append(dict(arrival=t, nside=nside, spin=spin, direction=direction, precision=prec, nmaps=k))
     return out
 
 
-def replay(server: Server, mix, make_io, release: bool = True, poll_sleep: float = 5e-5, stall_s: float = 60.0):
+def request_bytes(d) -> int:
+    """Device bytes of a request descriptor's input and output (maps + alm, FP64)."""
+    return d["nmaps"] * mapset_bytes(d["nside"], d.get("lmax", lmax_of(d["nside"])), d["spin"])
+
+
+def replay(server: Server, mix, make_io, release: bool = True, poll_sleep: float = 5e-5, stall_s: float = 60.0,
+           max_live_bytes: float | None = None):
     """Drive `server` with the request descriptors of `mix` (request_mix()
     dictionaries): each request is created with make_io(desc) -> (inp, out, ready)
     when the server clock reaches its arrival time, then submitted; finished
-    requests drop their tensors when `release` is set.  Returns the requests.
-    Raises RuntimeError if work is waiting but nothing completes for stall_s."""
+    requests drop their tensors when `release` is set.  With max_live_bytes the
+    callers hold at most that many bytes of request inputs and outputs at a time:
+    a request that would exceed it is created, in arrival order, once earlier
+    requests have finished; its latency still counts from its arrival time.
+    Returns the requests.  Raises RuntimeError if work is waiting but nothing
+    completes for stall_s."""
     order = sorted(range(len(mix)), key=lambda k: mix[k]["arrival"])
-    reqs, live, i = [], [], 0
+    if max_live_bytes is not None:
+        if not release:
+            raise ValueError("a bound on live request bytes needs release=True")
+        big = max(request_bytes(d) for d in mix)
+        if big > max_live_bytes:
+            raise ValueError(f"a request of {big / 1e9:.1f} GB exceeds the {max_live_bytes / 1e9:.1f} GB of live requests")
+    reqs, live, i, live_bytes = [], [], 0, 0
     last_progress = time.perf_counter()
     while i < len(order) or server.busy():
         now = server.now()
         while i < len(order) and mix[order[i]]["arrival"] <= now:
             d = mix[order[i]]
+            nb = request_bytes(d)
+            if max_live_bytes is not None and live_bytes + nb > max_live_bytes:
+                break  # the callers' memory is full: create it once earlier requests finish
             inp, out, ready = make_io(d)
             r = Request(nside=d["nside"], spin=d["spin"], direction=d["direction"], precision=d["precision"],
                         nmaps=d["nmaps"], inp=inp, out=out, arrival=d["arrival"], ready=ready)
             server.submit(r)
             reqs.append(r)
-            live.append(r)
+            live.append((r, nb))
+            live_bytes += nb
             i += 1
             last_progress = time.perf_counter()
         if server.poll():
@@ -539,11 +608,12 @@ def replay(server: Server, mix, make_io, release: bool = True, poll_sleep: float
                                f"plans {list(server.plans)}, {server.used / 1e9:.1f} of {server.budget / 1e9:.1f} GB")
         if release and live:
             keep = []
-            for r in live:
+            for r, nb in live:
                 if r.done is not None or r.status != 0:
                     r.inp = r.out = r.ready = None
+                    live_bytes -= nb
                 else:
-                    keep.append(r)
+                    keep.append((r, nb))
             live = keep
     return reqs
 

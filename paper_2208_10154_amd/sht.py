@@ -24,7 +24,8 @@ EXPORTS = ["sht_plan_create", "sht_plan_destroy", "sht_plan_set_precision", "sht
            "sht_plan_set_nmaps", "sht_plan_set_chunk", "sht_plan_workspace_bytes", "sht_plan_table_bytes",
            "sht_plan_set_workspace", "sht_alm2map", "sht_map2alm", "sht_map2alm_iter", "sht_plan_sync",
            "sht_last_error", "sht_plan_set_profiling", "sht_plan_get_profile", "sht_alm2map_sel",
-           "sht_map2alm_sel", "sht_eb_split", "sht_map2alm_immediate", "sht_plan_ring_rows"]
+           "sht_map2alm_sel", "sht_eb_split", "sht_map2alm_immediate", "sht_plan_ring_rows",
+           "sht_plan_create_part"]
 
 STAGES = ["fft_fwd", "fft_inv", "residual", "m2a_spin0", "m2a_spin2", "a2m_spin0", "a2m_spin2", "alm_layout"]
 
@@ -46,6 +47,7 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         P, I, D, V, S = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_size_t
         L.sht_plan_create.argtypes = [ctypes.POINTER(P), I, I, I, I]
+        L.sht_plan_create_part.argtypes = [ctypes.POINTER(P), I, I, I, I, I, I]
         L.sht_plan_destroy.argtypes = [P]
         L.sht_plan_set_precision.argtypes = [P, I]
         L.sht_plan_set_stream.argtypes = [P, V]
@@ -99,16 +101,34 @@ def npix(nside: int) -> int:
     return 12 * nside * nside
 
 
+def part_orders(lmax: int, part: int, nparts: int) -> list:
+    """The orders m a plan of part `part` of `nparts` owns (sht_plan_create_part):
+    pairs (q, lmax - q) of the folded order 0, lmax, 1, lmax - 1, ... dealt to the
+    parts in turn."""
+    ms = set()
+    for i in range(lmax + 1):
+        if (i >> 1) % nparts == part:
+            ms.add(i >> 1 if i % 2 == 0 else lmax - (i >> 1))
+    return sorted(ms)
+
+
 class Plan:
     """One transform plan: nside, lmax, spin (0: T maps, 2: IQU triples) and the
     largest batch of map sets per call."""
 
-    def __init__(self, nside: int, lmax: int, spin: int, nmaps: int, precision: str = "fp64", chunk: int | None = None):
+    def __init__(self, nside: int, lmax: int, spin: int, nmaps: int, precision: str = "fp64", chunk: int | None = None,
+                 part: int | None = None, nparts: int = 1):
+        """part/nparts: a plan that owns part `part` of `nparts` of the orders m
+        (sht_plan_create_part); by default all of them (sht_plan_create)."""
         self.nside, self.lmax, self.spin, self.capacity = nside, lmax, spin, nmaps
         self.ncomp = 1 if spin == 0 else 3
         self.nmaps = nmaps
+        self.part, self.nparts = (0 if part is None else part), nparts
         h = ctypes.c_void_p()
-        _check(lib().sht_plan_create(ctypes.byref(h), nside, lmax, spin, nmaps))
+        if part is None and nparts == 1:
+            _check(lib().sht_plan_create(ctypes.byref(h), nside, lmax, spin, nmaps))
+        else:
+            _check(lib().sht_plan_create_part(ctypes.byref(h), nside, lmax, spin, nmaps, self.part, nparts))
         self._h = h
         self.precision = "fp64"
         if precision != "fp64":

@@ -61,3 +61,26 @@ def test_component_masks():
     for bad in ("", "X", "TQ"):
         with pytest.raises(ValueError):
             sht.comp_mask(bad)
+
+
+@pytest.mark.parametrize("lmax,nparts", [(47, 4), (6143, 8), (10, 3), (5, 6)])
+def test_part_orders_partition_the_orders_and_balance_the_work(lmax, nparts):
+    """The m of the parts of sht_plan_create_part: disjoint, together every m, and
+    the (l, m) work of a part, sum over its m of lmax + 1 - m, within one pair's
+    work (lmax + 2) of every other part's."""
+    parts = [sht.part_orders(lmax, k, nparts) for k in range(nparts)]
+    allm = sorted(m for p in parts for m in p)
+    assert allm == list(range(lmax + 1))
+    work = [sum(lmax + 1 - m for m in p) for p in parts if p]
+    assert max(work) - min(work) <= lmax + 2
+    for p in parts:  # pairs (q, lmax - q) stay together
+        for m in p:
+            assert (lmax - m) in p
+
+
+def test_part_plan_arguments_rejected_before_device_use():
+    L = sht.lib()
+    h = ctypes.c_void_p()
+    for part, nparts in ((-1, 4), (4, 4), (0, 0)):
+        assert L.sht_plan_create_part(ctypes.byref(h), 16, 47, 2, 1, part, nparts) == sht.SHT_ERR_ARG
+        assert not h.value

@@ -199,3 +199,36 @@ def test_batch_position_invariance(sht):
     full = run_a2m(sht, nside, lmax, 2, c)
     alone = run_a2m(sht, nside, lmax, 2, c[5:6])
     assert np.all(rel_rms(full[5], alone[0]) < 1e-13)
+
+
+# Small batches: up to 8 map sets run the narrow Legendre tiles (the waves of a
+# workgroup split the output blocks of 16 columns) and the ring FFTs skip the
+# workgroups that hold only padding map sets; 9 map sets run the 64-column tile.
+SMALL = [(48, 143, 1), (48, 143, 8), (33, 98, 9), (16, 63, 3)]
+_small_refs = {}
+
+
+def _small_case(nside, lmax, nmaps, pol):
+    """Seeded inputs and the oracle's results for them (shared by the precisions)."""
+    key = (nside, lmax, nmaps, pol)
+    if key not in _small_refs:
+        a, c = alm_inputs(lmax, nmaps, pol, workload=51)
+        ref_m = oracle.alm2map_iqu(nside, lmax, a) if pol else oracle.alm2map(nside, lmax, a[:, 0])[:, None]
+        maps = synth.white_maps(12 * nside * nside, nmaps, 3 if pol else 1, workload=51)
+        ref_a = oracle.to_compact(oracle.map2alm_iqu(nside, lmax, maps) if pol
+                                  else oracle.map2alm(nside, lmax, maps[:, 0])[:, None])
+        _small_refs[key] = (c, ref_m, maps, ref_a)
+    return _small_refs[key]
+
+
+@pytest.mark.parametrize("nside,lmax,nmaps", SMALL)
+@pytest.mark.parametrize("pol", [False, True])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_small_batches_both_directions(sht, nside, lmax, nmaps, prec, pol):
+    note(f"small batch pol={pol} nside={nside} lmax={lmax} nmaps={nmaps} {prec}")
+    c, ref_m, maps, ref_a = _small_case(nside, lmax, nmaps, pol)
+    got_m = run_a2m(sht, nside, lmax, 2 if pol else 0, c, prec)
+    assert np.all(rel_rms(got_m, ref_m) <= TOL[prec]), rel_rms(got_m, ref_m)
+    got_a = run_m2a(sht, nside, lmax, 2 if pol else 0, maps, prec)
+    assert np.all(np.isfinite(got_a))
+    assert np.all(rel_rms(got_a, ref_a) <= TOL[prec]), rel_rms(got_a, ref_a)

@@ -158,3 +158,61 @@ def test_footprint_estimate_bounds_the_library(mods, nside, spin, slots):
     p.close()
     est = serve.plan_bytes_estimate(nside, 3 * nside - 1, spin, slots)
     assert actual <= est <= 1.5 * actual + (64 << 20), (actual, est)
+
+
+def _oracle_request(serve, torch, spin, direction, precision, nmaps, workload):
+    """A served request at nside 64 (lmax 191) on seeded inputs, with the oracle's
+    result for them: alm2map of Gaussian a_lm, map2alm of white maps."""
+    import oracle
+    from paper_2208_10154_amd import synth
+    nside, lmax, nc = 64, 191, (1 if spin == 0 else 3)
+    if direction == "alm2map":
+        a, c = alm_inputs(lmax, nmaps, spin == 2, workload=workload)
+        ref = oracle.alm2map_iqu(nside, lmax, a) if spin == 2 else oracle.alm2map(nside, lmax, a[:, 0])[:, None]
+        inp = to_dev(c)
+        out = torch.full((nmaps, nc, 12 * nside * nside), np.nan, dtype=torch.float64, device="cuda")
+    else:
+        m = synth.white_maps(12 * nside * nside, nmaps, nc, workload=workload)
+        ref = oracle.to_compact(oracle.map2alm_iqu(nside, lmax, m) if spin == 2
+                                else oracle.map2alm(nside, lmax, m[:, 0])[:, None])
+        inp = to_dev(m)
+        out = torch.full((nmaps, nc, (lmax + 1) ** 2), np.nan, dtype=torch.float64, device="cuda")
+    r = serve.Request(nside=nside, spin=spin, direction=direction, precision=precision, nmaps=nmaps,
+                      inp=inp, out=out, arrival=0.0)
+    return r, ref
+
+
+@pytest.mark.parametrize("batching", [True, False])
+def test_served_requests_match_the_oracle(mods, batching):
+    """One request per key (spin 0 / 2, both directions, FP64 / split BF16) at
+    nside 64, served together through the batching server (and through the
+    one-request-per-launch baseline), each checked against the oracle: 1e-10
+    relative RMS per map and component in FP64, 1e-5 in split BF16."""
+    serve, sht, torch = mods
+    note(f"serve: served requests against the oracle, batching={batching}")
+    kw = dict(executor=serve.Executor(nstreams=2)) if batching else \
+        dict(executor=serve.Executor(nstreams=1), batching=False, depth=64)
+    s = serve.Server(40e9, max_slots=64, **kw)
+    cases, k = [], 0
+    for spin in (0, 2):
+        for direction in ("alm2map", "map2alm"):
+            for prec in ("fp64", "bf16x3"):
+                for n in (2, 3):  # two requests per key: batched together when batching
+                    cases.append(_oracle_request(serve, torch, spin, direction, prec, n, 810 + k))
+                    k += 1
+    for r, _ in cases:
+        s.submit(r)
+    s.drain()
+    torch.cuda.synchronize()
+    if batching:
+        assert any(nr > 1 for _, _, _, nr in s.batches)
+    else:
+        assert all(nr == 1 for _, _, _, nr in s.batches)
+    tol = {"fp64": 1e-10, "bf16x3": 1e-5}
+    for r, ref in cases:
+        assert r.status == 0
+        got = from_dev(r.out)
+        assert np.all(np.isfinite(got))
+        err = rel_rms(got, ref)
+        assert np.all(err <= tol[r.precision]), (r.key, err)
+    s.close()

@@ -4,6 +4,7 @@ than the budget, latency accounting and the synthetic request mix.  A recording
 executor stands in for the GPU; it runs nothing."""
 import time
 
+import numpy as np
 import pytest
 
 from paper_2208_10154_amd import serve
@@ -213,7 +214,36 @@ def test_request_mix_is_seeded_and_bounded():
     assert {r["spin"] for r in a} == {0, 2} and {r["precision"] for r in a} == {"fp64", "bf16x3"}
     for r in a:
         assert 1 <= r["nmaps"] <= 512
-        assert r["nmaps"] * serve.mapset_bytes(r["nside"], 3 * r["nside"] - 1, r["spin"]) <= 2e9 or r["nmaps"] == 1
+    # log-normal with median 16: some requests are far larger than the median
+    assert max(r["nmaps"] for r in a) > 64
+    assert abs(np.median([r["nmaps"] for r in a]) - 16) <= 4
+    c = serve.request_mix(200, rate_hz=50.0, seed=3, mapset_cap_bytes=2e9)
+    for r in c:
+        assert serve.request_bytes(r) <= 2e9 or r["nmaps"] == 1
+
+
+def test_replay_bounds_live_request_bytes():
+    """Callers that hold at most max_live_bytes of request data: a request that
+    would exceed it is created once earlier ones have finished, in arrival order,
+    and its latency counts from its arrival."""
+    ex = RecordingExecutor()
+    ex.duration = 0.02
+    s = serve.Server(1e12, max_slots=64, executor=ex)
+    per = serve.mapset_bytes(16, 47, 0)
+    mix = [dict(arrival=0.0 + 0.001 * k, nside=16, spin=0, direction="alm2map", precision="fp64", nmaps=4)
+           for k in range(6)]
+    made = []
+
+    def make_io(d):
+        made.append((s.now(), d["arrival"]))
+        return None, None, None
+    reqs = serve.replay(s, mix, make_io, max_live_bytes=8.5 * per, stall_s=5.0)
+    assert len(reqs) == 6 and all(r.done is not None for r in reqs)
+    # two requests of 4 map sets fit at a time: the later ones waited for memory
+    assert sum(1 for t, a in made if t > a + 0.015) >= 3
+    assert all(r.latency >= r.done - r.arrival - 1e-9 for r in reqs)
+    with pytest.raises(ValueError):
+        serve.replay(s, mix, make_io, max_live_bytes=2 * per)
 
 
 def test_request_validation():
@@ -267,3 +297,43 @@ def test_idle_plan_takes_the_least_loaded_stream():
     assert st[64] != st[32] and st[16] == st[32]
     assert all(v == 0.0 for v in s.stream_load)
 
+
+
+def test_serial_mode_runs_one_request_per_launch_in_arrival_order():
+    ex = RecordingExecutor()
+    s = serve.Server(1e12, max_slots=64, executor=ex, batching=False, depth=1)
+    ts = [s.submit(req(nside=16 if k % 2 else 32, nmaps=2, arrival=0.0001 * k)) for k in range(6)]
+    s.drain()
+    assert [r["rids"] for r in ex.runs] == [[t] for t in ts]
+
+
+def test_plan_creation_reclaims_then_evicts_on_device_out_of_memory():
+    """A plan that meets a full device (memory held outside the server's account)
+    first gets cached memory back, then idle plans are evicted, then it is
+    created; with nothing left to free it waits instead of failing."""
+    from paper_2208_10154_amd import sht
+
+    class Tight(RecordingExecutor):
+        def __init__(self):
+            super().__init__()
+            self.free_calls, self.fail_next = 0, 0
+
+        def new_plan(self, nside, lmax, spin, slots):
+            if self.fail_next:
+                self.fail_next -= 1
+                raise sht.ShtError(serve.SHT_ERR_NOMEM, "hipMalloc failed")
+            return super().new_plan(nside, lmax, spin, slots)
+
+        def reclaim(self):
+            self.free_calls += 1
+
+    ex = Tight()
+    s = serve.Server(1e12, max_slots=64, executor=ex)
+    s.submit(req(nside=16, arrival=0.0))
+    s.drain()
+    ex.fail_next = 2  # the first try and the try after reclaiming fail
+    t = s.submit(req(nside=32, arrival=0.0))
+    s.drain()
+    assert ex.free_calls == 1
+    assert (16, 47, 0) not in s.plans and (32, 95, 0) in s.plans  # the idle plan was evicted
+    assert s.tickets[t].status == 0
