@@ -22,7 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "IQU maps/s (alm2map+map2alm) nside 512, FP64 vs mixed; serve p50/p99 ms"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
+# split BF16 forms each product from six bf16 MFMA products, so its peak in
+# products is a sixth of the BF16 matrix peak
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 6.0}
 PEAK_HBM_GBS = 8000.0
 
 
@@ -542,6 +544,47 @@ def small_batch_leg(args):
     return out
 
 
+def part_leg(args):
+    """One GPU's share of the split by m at the resolution beyond one GPU's memory
+    (Sec. 5): a plan owning part 0 of 8 of the orders m at nside 2048 / lmax 6143,
+    IQU, FP64, `--part-nmaps` map sets: Legendre (K_LEG) and ring-FFT time per
+    call, from the library's stage timers.  The exchange between the ring and m
+    layouts that would join the parts across GPUs is not part of this build."""
+    import torch
+    from paper_2208_10154_amd import sht
+    nside, L, nparts, n = 2048, 6143, 8, args.part_nmaps
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    p = sht.Plan(nside, L, 2, n, part=0, nparts=nparts)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    alm = torch.empty((n, 3, (L + 1) ** 2), dtype=torch.float64, device="cuda")
+    fill_alm(alm, L, seed=220810154 + 9, block=max(1, n))
+    maps = torch.empty((n, 3, 12 * nside * nside), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    p.alm2map(alm, maps, stream)
+    p.map2alm(maps, alm, stream)
+    torch.cuda.synchronize()
+    p.set_profiling(True)
+    p.profile(reset=True)
+    reps = max(1, min(3, args.steps))
+    for _ in range(reps):
+        p.alm2map(alm, maps, stream)
+        p.map2alm(maps, alm, stream)
+    prof = p.profile(reset=True)
+    out = {"workload": f"healpix_iqu_nside{nside}_lmax{L}_x{n}_mpart0of{nparts}", "dtype": "f64",
+           "owned_m": len(sht.part_orders(L, 0, nparts)), "plan_init_s": round(init_s, 2),
+           "table_gb": round(p.table_bytes() / 1e9, 2), "workspace_gb": round(p.workspace_bytes() / 1e9, 2),
+           "ms_per_call": {k: round(v[0] / reps, 3) for k, v in prof.items() if v[1]}}
+    leg = sum(v for k, v in out["ms_per_call"].items() if k.startswith(("m2a", "a2m")))
+    out["k_leg_ms_per_call_pair"] = round(leg, 3)
+    p.close()
+    del alm, maps
+    torch.cuda.empty_cache()
+    log(f"m part: {out}")
+    return out
+
+
 def serving(args):
     """Config 5: a seeded mix of requests (nside 64..1024, lmax = 3 nside - 1, T or
     IQU, both directions, FP64 or the mixed precision, log-normal map counts with
@@ -643,6 +686,8 @@ def main():
     ap.add_argument("--no-imm", action="store_true", help="skip the immediate-iteration leg")
     ap.add_argument("--no-spin0", action="store_true", help="skip the spin-0 nside 128 leg")
     ap.add_argument("--no-small", action="store_true", help="skip the small-batch latency leg")
+    ap.add_argument("--no-part", action="store_true", help="skip the nside 2048 m-part leg")
+    ap.add_argument("--part-nmaps", type=int, default=2, help="IQU map sets of the m-part leg")
     ap.add_argument("--imm-nmaps", type=int, default=64, help="IQU triples of the immediate-iteration leg")
     ap.add_argument("--imm-precisions", default="fp64,bf16x3")
     ap.add_argument("--eb-nmaps", type=int, default=250, help="IQU triples of the E/B leg")
@@ -733,6 +778,8 @@ def main():
         line["immediate"] = immediate_leg(args)
     if not args.no_small:
         line["small_batch"] = small_batch_leg(args)
+    if not args.no_part:
+        line["m_part"] = part_leg(args)
     if not args.no_serve:
         line["serve"] = serving(args)
     if not args.no_cpu_baseline:

@@ -84,6 +84,7 @@ __device__ __forceinline__ S3 lds3(const __bf16* p)
 }
 
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
 
 // Row loads through a buffer descriptor: one per-lane offset for the first row
 // and a wave-uniform scalar offset per further row, so a chunk's eight rows cost
@@ -102,6 +103,11 @@ struct Rows {
     __device__ __forceinline__ uint32_t ld(int voff, int soff) const
     {
         return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    }
+    __device__ __forceinline__ uint64_t ld64(int voff, int soff) const
+    {
+        const v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        return ((uint64_t)v.y << 32) | v.x;
     }
 };
 
@@ -579,7 +585,24 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
             return e;
         };
         uint64_t ar[2][NU][8];  // [even, odd class][column tile][class row k0 + e] of the next chunk
+        // rows of this m through a buffer descriptor: one lane offset for the
+        // chunk and a wave-uniform scalar offset per row pair, so the eight rows
+        // cost no vector address arithmetic; the last chunk of an m, whose rows
+        // may pass lmax, takes the clamped per-row addresses
+        const Rows ab(static_cast<const uint64_t*>(a.A) + row0 * a.ldx, (int64_t)(L + 1 - lb) * a.ldx * 8);
+        const int rstep = 2 * (int)a.ldx * 8;
         auto load_a = [&](int c) {
+            if (ab.ok && lfirst + TL * c + TL - 1 <= L) {
+                const int v0 = ((lfirst + TL * c + 2 * k0 - lb) * (int)a.ldx + col) * 8;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int u = 0; u < NU; ++u) {
+                        ar[0][u][e] = ab.ld64(v0 + 128 * u, e * rstep);
+                        ar[1][u][e] = ab.ld64(v0 + (int)a.ldx * 8 + 128 * u, e * rstep);
+                    }
+                return;
+            }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int le = lfirst + TL * c + 2 * (k0 + e);
@@ -743,7 +766,33 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
             return e;
         };
         uint64_t ar[4][NU][8];  // [E even, E odd, B' even, B' odd][column tile][class row k0 + e]
+        // rows through buffer descriptors as in the spin-0 kernel (the last chunk
+        // of an m takes the clamped per-row addresses)
+        const int64_t mbytes = (int64_t)(L + 1 - lb) * a.ldx * 8;
+        const Rows eb(static_cast<const uint64_t*>(a.A) + a.acomp + row0 * a.ldx, mbytes);
+        const Rows bb(static_cast<const uint64_t*>(a.A) + 2 * a.acomp + row0 * a.ldx, mbytes);
+        const int rstep = 2 * (int)a.ldx * 8;
         auto load_a_tile = [&](int c, int u) {
+            if (eb.ok && lfirst + TL * c + TL - 1 <= L) {
+                const int ve = ((lfirst + TL * c + 2 * k0 + po - lb) * (int)a.ldx + col + 16 * u) * 8;
+                const int vo = ve + (po ? -8 : 8) * (int)a.ldx;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if constexpr (EB != 2) {
+                        ar[0][u][e] = eb.ld64(ve, e * rstep);
+                        ar[1][u][e] = eb.ld64(vo, e * rstep);
+                    } else {
+                        ar[0][u][e] = ar[1][u][e] = 0ull;
+                    }
+                    if constexpr (EB != 1) {
+                        ar[2][u][e] = bb.ld64(ve, e * rstep);
+                        ar[3][u][e] = bb.ld64(vo, e * rstep);
+                    } else {
+                        ar[2][u][e] = ar[3][u][e] = 0ull;
+                    }
+                }
+                return;
+            }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int lc = lfirst + TL * c + 2 * (k0 + e);

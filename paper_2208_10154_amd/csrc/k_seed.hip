@@ -23,7 +23,9 @@ __global__ __launch_bounds__(128) void k_seeds(SeedArgs a)
     const int lb = lbase(a.spin, m);
     if (lb > L) return;
     if (a.seedoff[m + 1] == a.seedoff[m]) return;  // an m the plan does not own: no seeds
-    const double x = a.rings[r].z;
+    // x = cos(theta) enters as 1 - t with t = 1 - x exact to rounding: products
+    // a x are formed as a - a t, so a pole ring's rounded z biases no row
+    const double t = a.rings[r].omz;
     const int64_t base = a.seedoff[m] + r;
     const int64_t st = a.seedstride;
     int lsig = L + 1;
@@ -31,7 +33,8 @@ __global__ __launch_bounds__(128) void k_seeds(SeedArgs a)
     if (a.spin == 0) {
         double v0 = a.start[(int64_t)m * a.rn + r];
         int k = a.startk[(int64_t)m * a.rn + r];
-        double v1 = sqrt(2.0 * m + 3.0) * x * v0;  // lambda_{m+1,m}
+        const double s3 = sqrt(2.0 * m + 3.0);
+        double v1 = fma(-s3, t, s3) * v0;  // lambda_{m+1,m} = sqrt(2m+3) x lambda_mm
         if (k == 0) lsig = lb;
         int j = 0;
         for (int l = lb; l <= L; ++l) {
@@ -49,7 +52,7 @@ __global__ __launch_bounds__(128) void k_seeds(SeedArgs a)
             }
             double ca, cab;
             coef_spin0(l + 2, m, ca, cab);
-            double v2 = (ca * x) * v1 - cab * v0;
+            double v2 = fma(-ca, t, ca) * v1 - cab * v0;
             if (k > 0 && fabs(v2) > RESCALE_AT) {
                 v2 *= SCALE_DOWN;
                 v1 *= SCALE_DOWN;
@@ -64,8 +67,9 @@ __global__ __launch_bounds__(128) void k_seeds(SeedArgs a)
         int k = a.startk[(int64_t)m * a.rn + r];
         double al, be, ga;
         coef_spin2(lb + 1, m, al, be, ga);
-        double p1 = (al * x + be) * p0;  // gamma(lb) = 0
-        double q1 = (al * x - be) * q0;
+        const double ax1 = fma(-al, t, al);
+        double p1 = (ax1 + be) * p0;  // gamma(lb) = 0
+        double q1 = (ax1 - be) * q0;
         if (k == 0) lsig = lb;
         int j = 0;
         for (int l = lb; l <= L; ++l) {
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(128) void k_seeds(SeedArgs a)
                 continue;
             }
             coef_spin2(l + 2, m, al, be, ga);
-            double ax = al * x;
+            double ax = fma(-al, t, al);
             double p2 = (ax + be) * p1 - ga * p0;
             double q2 = (ax - be) * q1 - ga * q0;
             if (k > 0 && fmax(fabs(p2), fabs(q2)) > RESCALE_AT) {

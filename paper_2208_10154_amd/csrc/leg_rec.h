@@ -41,12 +41,12 @@ template <int SPIN>
 struct Seed;
 template <>
 struct Seed<0> {
-    double v0, v1, x;
+    double v0, v1, t;  // t = 1 - x, x = cos(theta) of the ring
     int k;
 };
 template <>
 struct Seed<2> {
-    double p0, p1, q0, q1, x;
+    double p0, p1, q0, q1, t;
     int k;
 };
 
@@ -55,7 +55,7 @@ __device__ __forceinline__ void seed_load(Seed<0>& s, const LegArgs& a, int64_t 
     s.v0 = a.mu[idx];
     s.v1 = a.mu[a.seedstride + idx];
     s.k = a.kk[idx];
-    s.x = a.rings[r].z;
+    s.t = a.rings[r].omz;
 }
 __device__ __forceinline__ void seed_load(Seed<2>& s, const LegArgs& a, int64_t idx, int r)
 {
@@ -64,27 +64,27 @@ __device__ __forceinline__ void seed_load(Seed<2>& s, const LegArgs& a, int64_t 
     s.q0 = a.mu[2 * a.seedstride + idx];
     s.q1 = a.mu[3 * a.seedstride + idx];
     s.k = a.kk[idx];
-    s.x = a.rings[r].z;
+    s.t = a.rings[r].omz;
 }
 
 template <int SPIN>
 struct Rec;
 template <>
 struct Rec<0> {
-    double v0, v1, x;  // lambda at rows t-2, t-1 (scaled by 2^(600k))
+    double v0, v1, t;  // lambda at rows t-2, t-1 (scaled by 2^(600k)); t = 1 - x
     int k;
     // w: 1, 0.5 (equator ring in the map2alm fold) or 0 (no ring)
     __device__ __forceinline__ void start(const Seed<0>& s, double w)
     {
         v0 = w * s.v0;
         v1 = w * s.v1;
-        x = s.x;
+        t = s.t;
         k = s.k;
     }
 };
 template <>
 struct Rec<2> {
-    double a0, a1, b0, b1, x;  // F+ and F- at rows t-2, t-1
+    double a0, a1, b0, b1, t;  // F+ and F- at rows t-2, t-1; t = 1 - x
     int k;
     // F+- = -(P +- M)/2 from the seed pair (P = lambda_{+2}, M = lambda_{-2})
     __device__ __forceinline__ void start(const Seed<2>& s, double w)
@@ -94,7 +94,7 @@ struct Rec<2> {
         a1 = h * (s.p1 + s.q1);
         b0 = h * (s.p0 - s.q0);
         b1 = h * (s.p1 - s.q1);
-        x = s.x;
+        t = s.t;
         k = s.k;
     }
 };
@@ -133,8 +133,9 @@ __device__ __forceinline__ void rec_row(Rec<0>& f, const double (&c)[3], int cnt
     } else if constexpr (R == 1) {
         v = f.v1;
     } else {
-        // lambda_l = (a_l x) lambda_{l-1} - (a_l b_l) lambda_{l-2}
-        v = (c[0] * f.x) * f.v1 - c[1] * f.v0;
+        // lambda_l = (a_l x) lambda_{l-1} - (a_l b_l) lambda_{l-2}, with a_l x formed
+        // as a_l - a_l (1 - x): a rounded x near a pole would bias every row alike
+        v = fma(-c[0], f.t, c[0]) * f.v1 - c[1] * f.v0;
         if (__any(f.k > 0)) {
             if (f.k > 0 && fabs(v) > RESCALE_AT) {
                 v *= SCALE_DOWN;
@@ -161,7 +162,7 @@ __device__ __forceinline__ void rec_row(Rec<2>& f, const double (&c)[3], int cnt
     } else {
         // P_l = (al x + be) P_{l-1} - ga P_{l-2}, M_l = (al x - be) M_{l-1} - ga M_{l-2}
         // in the F+- basis: F+_l = al x F+_{l-1} + be F-_{l-1} - ga F+_{l-2} (and + <-> -)
-        const double ax = c[0] * f.x, be = c[1], ga = c[2];
+        const double ax = fma(-c[0], f.t, c[0]), be = c[1], ga = c[2];  // al x as al - al (1 - x)
         fp = fma(ax, f.a1, fma(be, f.b1, -ga * f.a0));
         fm = fma(ax, f.b1, fma(be, f.a1, -ga * f.b0));
         if (__any(f.k > 0)) {

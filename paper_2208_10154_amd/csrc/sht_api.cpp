@@ -180,6 +180,7 @@ void build_rings(sht_plan p)
             int64_t j = (i < ns) ? i : 4 * ns - i;
             ld onemz = (ld)(j * j) / (3.0L * (ld)ns * (ld)ns);
             z = 1.0L - onemz;
+            r.omz = (double)onemz;
             sth = sqrtl(onemz * (2.0L - onemz));
             r.n = (int)(4 * j);
             r.s = 1;
@@ -188,6 +189,8 @@ void build_rings(sht_plan p)
         } else {
             z = (ld)(4 * ns - 2 * i) / (3.0L * (ld)ns);
             sth = sqrtl((1.0L - z) * (1.0L + z));
+            const int64_t az = (4 * ns - 2 * i) < 0 ? -(4 * ns - 2 * i) : (4 * ns - 2 * i);
+            r.omz = (double)((ld)(3 * ns - az) / (3.0L * (ld)ns));
             r.n = (int)(4 * ns);
             r.s = ((i - ns) % 2 == 0) ? 1 : 0;
             r.first = 2 * ns * (ns - 1) + (i - ns) * 4 * ns;
@@ -451,8 +454,9 @@ int build_seeds(sht_plan p, SeedSet& S, int spin)
             int lb = std::max(m, 2);
             ld lnorm = 0.5L * logl((ld)(2 * lb + 1) / (4.0L * PI_L));
             for (int r = 0; r < rn; ++r) {
-                ld z = (ld)p->rings[r].z;
-                ld lc = 0.5L * logl((1.0L + z) / 2.0L), ls = 0.5L * logl((1.0L - z) / 2.0L);
+                // cos^2(theta/2) = (1 + z)/2, sin^2(theta/2) = (1 - z)/2 from the exact 1 - z
+                const ld omz = (ld)p->rings[r].omz;
+                ld lc = 0.5L * log1pl(-omz / 2.0L), ls = 0.5L * logl(omz / 2.0L);
                 ld lP, lM;
                 double sP, sM;
                 if (m >= 2) {

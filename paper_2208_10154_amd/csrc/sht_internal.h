@@ -68,6 +68,8 @@ struct FftLen {
 
 struct RingDev {
     double z;               // cos(theta)
+    double omz;             // 1 - |z| from the exact rational: near the poles z rounded to FP64
+                            // loses the relative precision of 1 - z that the recursion needs
     double sth;             // sin(theta)
     int64_t first;          // first pixel
     int n;                  // pixels
