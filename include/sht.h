@@ -91,8 +91,8 @@ int sht_plan_create(sht_plan* out, int nside, int lmax, int spin, int nmaps);
  *                (the sum over the parts' maps is the full synthesis).
  * The ring FFTs are computed for all rings on the plan's GPU (the exchange
  * between ring and m layouts that splits them across GPUs is not part of this
- * library).  Iterations, E/B separation and component selections need a plan
- * of all m (SHT_ERR_UNSUPPORTED).  Arguments as
+ * library).  Iterations, E/B separation, component selections and
+ * sht_alm2map_noalloc need a plan of all m (SHT_ERR_UNSUPPORTED).  Arguments as
  * for sht_plan_create; SHT_ERR_ARG if part is out of range or owns no m. */
 int sht_plan_create_part(sht_plan* out, int nside, int lmax, int spin, int nmaps, int part, int nparts);
 
@@ -141,6 +141,22 @@ int sht_plan_set_workspace(sht_plan plan, void* dev_ptr, size_t bytes);
 
 /* Backward transform (alm -> maps) of the current batch.  Device pointers. */
 int sht_alm2map(sht_plan plan, const double* alm, double* map);
+
+/* Backward transform (alm -> maps) of the current batch, as sht_alm2map, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): this call allocates nothing.
+ * Its workspace is a static device array of SHT_NOALLOC_WORKSPACE_BYTES bytes
+ * that each GPU the library runs on holds until the process ends (the plan's own
+ * workspace is not used).  The batch runs in chunks of as many map sets as fit
+ * that array at the plan's precision; if one map set does not fit (for example
+ * nside 256, lmax 767, spin 0 in FP64) the call returns SHT_ERR_ARG and does
+ * nothing.  All calls on one GPU share the array: calls that overlap in time on
+ * one GPU (two streams, two host threads) race and give undefined results;
+ * calls ordered on one stream are safe.  Every workspace element a chunk reads
+ * is written earlier in the same chunk, so nothing is cleared between calls.
+ * Same layouts and results as sht_alm2map (the same kernels). */
+#define SHT_NOALLOC_WORKSPACE_BYTES (256u << 20)
+int sht_alm2map_noalloc(sht_plan plan, const double* alm, double* map);
 
 /* Forward transform (maps -> alm) of the current batch.  Device pointers. */
 int sht_map2alm(sht_plan plan, const double* map, double* alm);

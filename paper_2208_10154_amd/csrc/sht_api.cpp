@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,33 @@ int fail(int code, const std::string& msg)
 
 typedef long double ld;
 const ld PI_L = 3.141592653589793238462643383279502884197L;
+
+// Static workspace of sht_alm2map_noalloc: a device array each GPU holds from
+// the first use of the library on it until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it only names the symbol):
+// plan creation resolves its device address once per device with
+// hipGetSymbolAddress, and that address is what the kernels receive.
+constexpr size_t SCRATCH_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device (resolved once per device).
+int resolve_scratch(int dev, void** out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(SHT_ERR_UNSUPPORTED, "device index beyond the static workspace table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SHT_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SHT_OK;
+}
 
 // Device allocation that records its size (for the table accounting).
 struct Dev {
@@ -102,6 +130,9 @@ struct sht_plan_s {
         std::vector<int> ntiles0, ntiles2;     // per level: l tiles of the listed m per spin
         Dev mlist, pref0, pref2, cmin;         // device: m per entry; per-level tile prefix sums
     } lev;
+
+    // device address of the static workspace on the plan's device
+    void* scratch = nullptr;
 
     // part `part` of `nparts` of the orders m (sht_plan_create_part): own[m] = 1 for
     // the m this plan transforms; d_own its device copy, d_mlist the owned m
@@ -615,6 +646,18 @@ size_t ws_need_at(sht_plan p, int chunk, int prec)
 
 size_t ws_need(sht_plan p) { return ws_need_at(p, p->chunk, p->prec); }
 
+// largest chunk (at most the plan's capacity) whose workspace fits the static
+// workspace in precision `prec`; 0 if one map set does not fit
+int noalloc_chunk(sht_plan p, int prec)
+{
+    int lo = 0, hi = p->cap;
+    while (lo < hi) {  // ws_need_at grows with the chunk
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (ws_need_at(p, mid, prec) <= SCRATCH_BYTES) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 void* ws_A(sht_plan p) { return (char*)p->ws + (size_t)p->ncomp * xcomp_elems(p) * esize(p->prec); }
 // the alm2map operand rows: the map2alm rows' region, or the split-BF16 words after it
 void* ws_Aop(sht_plan p)
@@ -1118,6 +1161,16 @@ int create_plan(sht_plan* out, int nside, int lmax, int spin, int nmaps, int par
         p->chunk = default_chunk(p);
         rc = prep(p);
     }
+    // the static workspace of sht_alm2map_noalloc and the FFT work lists of every
+    // chunk width it may use, so that call allocates nothing
+    if (!rc) rc = resolve_scratch(dev, &p->scratch);
+    if (!rc) {
+        std::vector<int64_t> widths;
+        for (int k = 1; k <= noalloc_chunk(p, SHT_FP32); ++k)
+            if (widths.empty() || widths.back() != ldx_for(k)) widths.push_back(ldx_for(k));
+        for (size_t i = 0; i < widths.size() && !rc; ++i) rc = build_items(p, (int)(widths[i] / 4));
+        if (!rc) rc = build_items(p, (int)(p->ldx_cur / 4));
+    }
     if (!rc) {
         hipError_t e = hipStreamSynchronize(p->stream);
         if (e != hipSuccess) rc = fail(SHT_ERR_DEVICE, std::string("plan set-up: ") + hipGetErrorString(e));
@@ -1237,6 +1290,53 @@ int sht_alm2map_sel(sht_plan p, int comps, const double* alm, double* map)
         if ((rc = run_fft_inv(p, map + k0 * mstride, nm, comps))) return rc;
     }
     return SHT_OK;
+}
+
+int sht_alm2map_noalloc(sht_plan p, const double* alm, double* map)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if ((rc = whole_only(p, "the allocation-free synthesis"))) return rc;
+    if (!alm || !map) return fail(SHT_ERR_ARG, "null data pointer");
+    if (!p->scratch) return fail(SHT_ERR_DEVICE, "static workspace not resolved on this device");
+    const int c = noalloc_chunk(p, p->prec);
+    if (c < 1)
+        return fail(SHT_ERR_ARG, "the workspace of one map set (" + std::to_string(ws_need_at(p, 1, p->prec)) +
+                                     " bytes) exceeds the static workspace of " + std::to_string(SCRATCH_BYTES) +
+                                     " bytes");
+    for (int k0 = 0; k0 < p->nmaps; k0 += c) {  // every width's work list exists (plan creation)
+        const int npairs = (int)(ldx_for(std::min(c, p->nmaps - k0)) / 4);
+        if (!p->item_sets.count(npairs)) return fail(SHT_ERR_UNSUPPORTED, "no FFT work list for this chunk width");
+    }
+    // run the plan's own stages on the static workspace, with chunks of c map sets,
+    // no stage timing (events), then give the plan back its own workspace
+    void* const ws = p->ws;
+    const size_t ws_bytes = p->ws_bytes;
+    const bool ws_owned = p->ws_owned, profiling = p->profiling;
+    const int chunk = p->chunk, nm_cur = p->nm_cur;
+    const int64_t ldx = p->ldx_cur;
+    p->ws = p->scratch;
+    p->ws_bytes = SCRATCH_BYTES;
+    p->ws_owned = false;
+    p->profiling = false;
+    p->chunk = c;
+    const int64_t astride = (int64_t)p->ncomp * (p->lmax + 1) * (p->lmax + 1);
+    const int64_t mstride = (int64_t)p->ncomp * p->npix;
+    for (int k0 = 0; k0 < p->nmaps && !rc; k0 += c) {
+        const int nm = std::min(c, p->nmaps - k0);
+        rc = use_width(p, nm);
+        if (!rc) rc = run_a2m(p, alm + k0 * astride, nm, SHT_COMP_ALL);
+        if (!rc) rc = run_fft_inv(p, map + k0 * mstride, nm, SHT_COMP_ALL);
+    }
+    p->ws = ws;
+    p->ws_bytes = ws_bytes;
+    p->ws_owned = ws_owned;
+    p->profiling = profiling;
+    p->chunk = chunk;
+    p->ldx_cur = ldx;
+    p->nm_cur = nm_cur;
+    const int rc2 = build_items(p, (int)(ldx / 4));  // cached: selects the plan's list again
+    return rc ? rc : rc2;
 }
 
 int sht_alm2map(sht_plan p, const double* alm, double* map)

@@ -25,7 +25,7 @@ EXPORTS = ["sht_plan_create", "sht_plan_destroy", "sht_plan_set_precision", "sht
            "sht_plan_set_workspace", "sht_alm2map", "sht_map2alm", "sht_map2alm_iter", "sht_plan_sync",
            "sht_last_error", "sht_plan_set_profiling", "sht_plan_get_profile", "sht_alm2map_sel",
            "sht_map2alm_sel", "sht_eb_split", "sht_map2alm_immediate", "sht_plan_ring_rows",
-           "sht_plan_create_part"]
+           "sht_alm2map_noalloc", "sht_plan_create_part"]
 
 STAGES = ["fft_fwd", "fft_inv", "residual", "m2a_spin0", "m2a_spin2", "a2m_spin0", "a2m_spin2", "alm_layout"]
 
@@ -61,6 +61,7 @@ def lib() -> ctypes.CDLL:
         L.sht_plan_ring_rows.restype = ctypes.c_longlong
         L.sht_plan_set_workspace.argtypes = [P, V, S]
         L.sht_alm2map.argtypes = [P, V, V]
+        L.sht_alm2map_noalloc.argtypes = [P, V, V]
         L.sht_map2alm.argtypes = [P, V, V]
         L.sht_map2alm_iter.argtypes = [P, V, V, I, D]
         L.sht_alm2map_sel.argtypes = [P, I, V, V]
@@ -205,6 +206,14 @@ class Plan:
     def alm2map(self, alm, maps, stream=None):
         self._stream(stream)
         _check(lib().sht_alm2map(self._h, self._ptr(alm, self.alm_shape(), "alm"), self._ptr(maps, self.map_shape(), "maps")))
+        return maps
+
+    def alm2map_noalloc(self, alm, maps, stream=None):
+        """sht_alm2map_noalloc: alm2map on the library's static workspace (the call
+        allocates no device memory)."""
+        self._stream(stream)
+        _check(lib().sht_alm2map_noalloc(self._h, self._ptr(alm, self.alm_shape(), "alm"),
+                                         self._ptr(maps, self.map_shape(), "maps")))
         return maps
 
     def map2alm(self, maps, alm, stream=None):

@@ -84,7 +84,7 @@ def test_part_plans_refuse_the_whole_plan_calls(sht):
     a = torch.zeros(p.alm_shape(), dtype=torch.float64, device="cuda")
     for call in (lambda: p.map2alm_iter(m, a, 1), lambda: p.map2alm_immediate(m, a, 1),
                  lambda: p.eb_split(m, a, torch.zeros_like(m), torch.zeros_like(m)),
-                 lambda: p.alm2map_sel("E", a, m)):
+                 lambda: p.alm2map_sel("E", a, m), lambda: p.alm2map_noalloc(a, m)):
         with pytest.raises(sht.ShtError) as e:
             call()
         assert e.value.code == sht.SHT_ERR_UNSUPPORTED
