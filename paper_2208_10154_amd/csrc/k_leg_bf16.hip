@@ -1,18 +1,21 @@
 // Legendre contraction in split-BF16 precision (HIP, gfx950).
 //
 // The same products as k_leg.hip (the paper's per-m GEMMs, Sec. 2.2 and the 2x2
-// block of Sec. 2.3), with every operand held as three bfloat16 numbers
-// x = hi + mid + lo (hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid)),
-// which carry the 24 significant bits of x rounded to FP32, and every product
-// formed on the BF16 matrix cores with FP32 accumulation from the six partial
-// products whose order is at most 2^-16 of the leading one:
-// hi*hi + hi*mid + mid*hi + hi*lo + mid*mid + lo*hi.  The three dropped terms are
-// below 2^-24 of the product, so the result has the accuracy of an FP32
-// contraction.  (Two pieces and three products leave about 4e-6 relative RMS
-// error per product, which the B mode, a tenth of the E power in typical skies,
-// amplifies past 1e-5.)  The recursion, its exponent handling and the data in
-// HBM are the same as in the FP32 path (recursion FP64, ring coefficients
-// FP32), so only the MFMA step changes precision.
+// block of Sec. 2.3), with every operand x (rounded to FP32) held exactly as
+// three bfloat16 numbers x = hi + mid + lo: hi is x with its significand cut to
+// 8 bits, mid the rest rounded to bf16, lo what then remains, which has at most
+// 8 significant bits and so is a bf16 itself (|mid| < 2^-7 |x|, |lo| <= 2^-16 |x|).
+// Cutting hi costs one AND where rounding costs a conversion and a shift, and
+// the rounded mid keeps the dropped terms below free of sign bias.  Every
+// product is formed on the BF16 matrix cores with FP32 accumulation from six
+// partial products: hi*hi + hi*mid + mid*hi + hi*lo + mid*mid + lo*hi.  The three
+// dropped terms (mid*lo, lo*mid, lo*lo) are below 2^-22 of the product, so the
+// result has the accuracy of an FP32 contraction.  (Two pieces and three
+// products leave about 4e-6 relative RMS error per product, which the B mode, a
+// tenth of the E power in typical skies, amplifies past 1e-5.)  The recursion,
+// its exponent handling and the data in HBM are the same as in the FP32 path
+// (recursion FP64, ring coefficients FP32), so only the MFMA step changes
+// precision.
 //
 // alm2map reads its coefficient rows already split, as 64-bit words holding hi,
 // mid and lo (written so by the layout kernel), and only regroups them; map2alm
@@ -35,6 +38,8 @@ namespace sht {
 namespace {
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
 
 constexpr int NT = 256;
 constexpr int HALF = TL / 2;
@@ -60,18 +65,33 @@ __device__ __forceinline__ v4f mfma6(const S3& a, const S3& b, v4f c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
 }
 
-// x = hi + mid + lo for eight FP32 values
+// x = hi + mid + lo (see above) as FP32 bit patterns whose upper halves are the
+// three bf16 numbers (the lower halves are zero)
+struct P3 {
+    uint32_t h, m, l;
+};
+__device__ __forceinline__ P3 split3(float x)
+{
+    const uint32_t h = __float_as_uint(x) & 0xFFFF0000u;
+    const float r = x - __uint_as_float(h);
+    const float m = (float)(__bf16)r;
+    return P3{h, __float_as_uint(m), __float_as_uint(r - m)};
+}
+
+// the three operand vectors of eight FP32 values: upper halves paired per word
 __device__ __forceinline__ void split8(const float (&x)[8], S3& s)
 {
+    v4u h, m, l;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const __bf16 h = (__bf16)x[e];
-        const float r = x[e] - (float)h;
-        const __bf16 m = (__bf16)r;
-        s.h[e] = h;
-        s.m[e] = m;
-        s.l[e] = (__bf16)(r - (float)m);
+    for (int j = 0; j < 4; ++j) {
+        const P3 a = split3(x[2 * j]), b = split3(x[2 * j + 1]);
+        h[j] = __builtin_amdgcn_perm(b.h, a.h, 0x07060302u);
+        m[j] = __builtin_amdgcn_perm(b.m, a.m, 0x07060302u);
+        l[j] = __builtin_amdgcn_perm(b.l, a.l, 0x07060302u);
     }
+    s.h = __builtin_bit_cast(v8bf, h);
+    s.m = __builtin_bit_cast(v8bf, m);
+    s.l = __builtin_bit_cast(v8bf, l);
 }
 
 __device__ __forceinline__ v8bf lds8(const __bf16* p) { return *reinterpret_cast<const v8bf*>(p); }
@@ -82,9 +102,6 @@ __device__ __forceinline__ S3 lds3(const __bf16* p)
 {
     return S3{lds8(p), lds8(p + PL), lds8(p + 2 * PL)};
 }
-
-typedef unsigned v4u __attribute__((ext_vector_type(4)));
-typedef unsigned v2u __attribute__((ext_vector_type(2)));
 
 // Row loads through a buffer descriptor: one per-lane offset for the first row
 // and a wave-uniform scalar offset per further row, so a chunk's eight rows cost
@@ -135,15 +152,13 @@ template <int STEP, int FOFF, int LOFF>
 struct EmitBF {
     __bf16* e0;
     __bf16* e1;
+    __device__ __forceinline__ static __bf16 upper(uint32_t w) { return __builtin_bit_cast(__bf16, (uint16_t)(w >> 16)); }
     __device__ __forceinline__ static void put1(__bf16* d, double v)
     {
-        const float f = (float)v;
-        const __bf16 h = (__bf16)f;
-        const float r = f - (float)h;
-        const __bf16 m = (__bf16)r;
-        d[0] = h;
-        d[LOFF] = m;
-        d[2 * LOFF] = (__bf16)(r - (float)m);
+        const P3 p = split3((float)v);
+        d[0] = upper(p.h);
+        d[LOFF] = upper(p.m);
+        d[2 * LOFF] = upper(p.l);
     }
     template <int R>
     __device__ __forceinline__ void put(double v)

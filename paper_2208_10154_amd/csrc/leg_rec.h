@@ -73,6 +73,7 @@ template <>
 struct Rec<0> {
     double v0, v1, t;  // lambda at rows t-2, t-1 (scaled by 2^(600k)); t = 1 - x
     int k;
+    bool any;  // a lane of the wave carried an exponent at the start (k never grows)
     // w: 1, 0.5 (equator ring in the map2alm fold) or 0 (no ring)
     __device__ __forceinline__ void start(const Seed<0>& s, double w)
     {
@@ -80,12 +81,14 @@ struct Rec<0> {
         v1 = w * s.v1;
         t = s.t;
         k = s.k;
+        any = __any(k > 0);
     }
 };
 template <>
 struct Rec<2> {
     double a0, a1, b0, b1, t;  // F+ and F- at rows t-2, t-1; t = 1 - x
     int k;
+    bool any;  // as in Rec<0>
     // F+- = -(P +- M)/2 from the seed pair (P = lambda_{+2}, M = lambda_{-2})
     __device__ __forceinline__ void start(const Seed<2>& s, double w)
     {
@@ -96,6 +99,7 @@ struct Rec<2> {
         b1 = h * (s.p1 - s.q1);
         t = s.t;
         k = s.k;
+        any = __any(k > 0);
     }
 };
 
@@ -123,7 +127,10 @@ struct Emit {
 // Row R of a segment: rows 0 and 1 are the seed pair, later rows come from the
 // recursion with that row's coefficients c (read beforehand from the coefficient
 // tile in LDS).  Rows at or past cnt (beyond lmax) and values still carrying an
-// exponent (k > 0: below 2^-100) are emitted as zeros.
+// exponent (k > 0: below 2^-100) are emitted as zeros.  The exponent handling is
+// a branch taken only by waves that had a lane carrying an exponent when the
+// segment started, marked unlikely so that the compiler keeps it out of the
+// common path instead of evaluating it on every row and selecting.
 template <int R, typename E>
 __device__ __forceinline__ void rec_row(Rec<0>& f, const double (&c)[3], int cnt, E& em)
 {
@@ -136,7 +143,7 @@ __device__ __forceinline__ void rec_row(Rec<0>& f, const double (&c)[3], int cnt
         // lambda_l = (a_l x) lambda_{l-1} - (a_l b_l) lambda_{l-2}, with a_l x formed
         // as a_l - a_l (1 - x): a rounded x near a pole would bias every row alike
         v = fma(-c[0], f.t, c[0]) * f.v1 - c[1] * f.v0;
-        if (__any(f.k > 0)) {
+        if (__builtin_expect(f.any, 0)) {
             if (f.k > 0 && fabs(v) > RESCALE_AT) {
                 v *= SCALE_DOWN;
                 f.v1 *= SCALE_DOWN;
@@ -165,7 +172,7 @@ __device__ __forceinline__ void rec_row(Rec<2>& f, const double (&c)[3], int cnt
         const double ax = fma(-c[0], f.t, c[0]), be = c[1], ga = c[2];  // al x as al - al (1 - x)
         fp = fma(ax, f.a1, fma(be, f.b1, -ga * f.a0));
         fm = fma(ax, f.b1, fma(be, f.a1, -ga * f.b0));
-        if (__any(f.k > 0)) {
+        if (__builtin_expect(f.any, 0)) {
             if (f.k > 0 && fmax(fabs(fp), fabs(fm)) > RESCALE_AT) {
                 fp *= SCALE_DOWN;
                 fm *= SCALE_DOWN;
