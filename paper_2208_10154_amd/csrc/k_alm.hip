@@ -19,6 +19,7 @@ namespace {
 constexpr int NT = 256;
 constexpr int TLB = 64;  // l per tile (= TL)
 constexpr int TK = 32;   // maps per tile
+constexpr int PER = 2 * TK * TLB / NT;  // tile elements per thread
 
 __device__ __forceinline__ int64_t calm(int L, int l, int m, int part)
 {
@@ -56,25 +57,28 @@ __global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
     const int lb = lbase(a.spin, m);
     const int l0 = lb + lt * TLB;
     const int64_t csz = (int64_t)(L + 1) * (L + 1);
-    for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
-        const int part = e / (TK * TLB);
-        const int kk = (e / TLB) % TK;
-        const int li = e % TLB;
-        const int l = l0 + li, k = kb * TK + kk;
-        double v = 0.0;
-        if (l <= L && k < a.nmaps) {
-            const double* base = a.alm_in + (int64_t)k * a.almstride + comp * csz;
-            if (kind == 0) {
-                int64_t o = calm(L, l, m, part);
-                if (o >= 0) v = base[o];
-            } else if (part == 0) {  // Re B' = -Im a_B
-                int64_t o = calm(L, l, m, 1);
-                if (o >= 0) v = -base[o];
-            } else {                 // Im B' = Re a_B
-                v = base[calm(L, l, m, 0)];
-            }
-        }
-        tile[li][2 * kk + part] = v;
+    // Every load of a thread is issued before the first is used: addresses are
+    // clamped into the arrays (so the loads need no predicate) and the values
+    // that lie outside the tile are replaced by zero afterwards.  B' = i a_B takes
+    // Re B' = -Im a_B and Im B' = Re a_B (the parts swap); m = 0 has no Im slot.
+    double v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = (int)threadIdx.x + i * NT;
+        const int part = e / (TK * TLB), kk = (e / TLB) % TK, li = e % TLB;
+        const int l = min(l0 + li, L), k = min(kb * TK + kk, a.nmaps - 1);
+        const int src = kind ? (part ^ 1) : part;
+        const int64_t o = calm(L, l, m, (src && m == 0) ? 0 : src);
+        v[i] = a.alm_in[(int64_t)k * a.almstride + comp * csz + o];
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = (int)threadIdx.x + i * NT;
+        const int part = e / (TK * TLB), kk = (e / TLB) % TK, li = e % TLB;
+        const int src = kind ? (part ^ 1) : part;
+        const bool live = l0 + li <= L && kb * TK + kk < a.nmaps && !(src && m == 0);
+        const double x = (kind && part == 0) ? -v[i] : v[i];
+        tile[li][2 * kk + part] = live ? x : 0.0;
     }
     __syncthreads();
     T* A = static_cast<T*>(a.Aop) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
@@ -83,7 +87,9 @@ __global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
         // latency-bound); rows start on 64-column boundaries of a 256-byte aligned
         // workspace, so every vector is aligned
         struct alignas(16) V4 { T v[4]; };
-        for (int e = threadIdx.x; e < 2 * TK * TLB / 4; e += NT) {
+#pragma unroll
+        for (int i = 0; i < PER / 4; ++i) {
+            const int e = (int)threadIdx.x + i * NT;
             const int li = e / (TK / 2), c = 4 * (e % (TK / 2));
             if (l0 + li > L) continue;
             V4 w;
@@ -94,7 +100,9 @@ __global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
     } else if constexpr (__is_same(T, uint64_t)) {
         // split-BF16 words: two columns per lane, one 16-byte store
         struct alignas(16) W2 { uint64_t v[2]; };
-        for (int e = threadIdx.x; e < 2 * TK * TLB / 2; e += NT) {
+#pragma unroll
+        for (int i = 0; i < PER / 2; ++i) {
+            const int e = (int)threadIdx.x + i * NT;
             const int li = e / TK, c = 2 * (e % TK);
             if (l0 + li > L) continue;
             W2 w;
@@ -103,7 +111,9 @@ __global__ __launch_bounds__(NT) void k_to_mmajor(AlmArgs a)
             *reinterpret_cast<W2*>(A + (int64_t)li * a.ldx + c) = w;
         }
     } else {
-        for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = (int)threadIdx.x + i * NT;
             const int li = e / (2 * TK), c = e % (2 * TK);
             if (l0 + li > L) continue;
             A[(int64_t)li * a.ldx + c] = (T)tile[li][c];
@@ -129,25 +139,46 @@ __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
     const int l0 = lb + lt * TLB;
     const int64_t csz = (int64_t)(L + 1) * (L + 1);
     const T* A = static_cast<const T*>(a.A) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
+    // all loads of a thread first (rows clamped into the m's block, rows past
+    // lmax then read as zero), as in k_to_mmajor
     if constexpr (sizeof(T) == 4) {
         // four columns per lane, one 16-byte load (aligned as in k_to_mmajor)
-        for (int e = threadIdx.x; e < 2 * TK * TLB / 4; e += NT) {
+        float4 v[PER / 4];
+#pragma unroll
+        for (int i = 0; i < PER / 4; ++i) {
+            const int e = (int)threadIdx.x + i * NT;
             const int li = e / (TK / 2), c = 4 * (e % (TK / 2));
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (l0 + li <= L) v = *reinterpret_cast<const float4*>(A + (int64_t)li * a.ldx + c);
-            tile[li][c] = v.x;
-            tile[li][c + 1] = v.y;
-            tile[li][c + 2] = v.z;
-            tile[li][c + 3] = v.w;
+            v[i] = *reinterpret_cast<const float4*>(A + (int64_t)min(li, L - l0) * a.ldx + c);
+        }
+#pragma unroll
+        for (int i = 0; i < PER / 4; ++i) {
+            const int e = (int)threadIdx.x + i * NT;
+            const int li = e / (TK / 2), c = 4 * (e % (TK / 2));
+            const bool live = l0 + li <= L;
+            tile[li][c] = live ? v[i].x : 0.0;
+            tile[li][c + 1] = live ? v[i].y : 0.0;
+            tile[li][c + 2] = live ? v[i].z : 0.0;
+            tile[li][c + 3] = live ? v[i].w : 0.0;
         }
     } else {
-        for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+        T v[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = (int)threadIdx.x + i * NT;
             const int li = e / (2 * TK), c = e % (2 * TK);
-            tile[li][c] = (l0 + li <= L) ? (double)A[(int64_t)li * a.ldx + c] : 0.0;
+            v[i] = A[(int64_t)min(li, L - l0) * a.ldx + c];
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = (int)threadIdx.x + i * NT;
+            const int li = e / (2 * TK), c = e % (2 * TK);
+            tile[li][c] = (l0 + li <= L) ? (double)v[i] : 0.0;
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = (int)threadIdx.x + i * NT;
         const int part = e / (TK * TLB);
         const int kk = (e / TLB) % TK;
         const int li = e % TLB;
@@ -175,7 +206,9 @@ __global__ __launch_bounds__(NT) void k_from_mmajor(AlmArgs a)
         // unless the operand words have a region of their own)
         TO* out = static_cast<TO*>(a.Aop) + comp * a.acomp + (a.rowoff[m] + (l0 - lb)) * a.ldx + kb * 2 * TK;
         const int drop = (m == 0) ? (kind == 0 ? 1 : 0) : -1;
-        for (int e = threadIdx.x; e < 2 * TK * TLB; e += NT) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = (int)threadIdx.x + i * NT;
             const int li = e / (2 * TK), c = e % (2 * TK);
             if (l0 + li > L) continue;
             const bool keep = (c & 1) != drop && kb * TK + (c >> 1) < a.nmaps;
