@@ -18,6 +18,11 @@ import os
 import sys
 import time
 
+# Request buffers of the serving leg come and go in sizes from kilobytes to tens of
+# gigabytes; growable segments keep torch's cache from splitting HBM into pieces
+# too small for the next large request (set before torch is imported).
+os.environ.setdefault("PYTORCH_ALLOC_CONF", "expandable_segments:True")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -593,9 +598,10 @@ def serving(args):
     80% of it gives p50/p99 latency, and the baseline serves the same Poisson
     arrivals in FP64 one request at a time, first come first served, on one
     stream.  The callers hold at most --serve-live-gb of request inputs and outputs
-    in HBM at a time (a request that would exceed it is created once earlier ones
-    finish; its latency still counts from its arrival).  Plan creation happens in
-    a warm-up pass, timed separately."""
+    in HBM at a time: a request that would exceed it is created once earlier ones
+    finish (its latency still counts from its arrival), later requests that fit go
+    ahead of it until it has waited 2 s (independent callers, no starvation).
+    Plan creation happens in a warm-up pass, timed separately."""
     import torch
     from paper_2208_10154_amd import serve
     N = args.serve_requests
@@ -607,8 +613,17 @@ def serving(args):
         L, nc = 3 * nside - 1, (1 if spin == 0 else 3)
         a_shape, m_shape = (n, nc, (L + 1) ** 2), (n, nc, 12 * nside * nside)
         ish, osh = (a_shape, m_shape) if d["direction"] == "alm2map" else (m_shape, a_shape)
-        inp = torch.randn(ish, dtype=torch.float64, device="cuda")
-        out = torch.empty(osh, dtype=torch.float64, device="cuda")
+        for attempt in (0, 1):
+            try:
+                inp = torch.randn(ish, dtype=torch.float64, device="cuda")
+                out = torch.empty(osh, dtype=torch.float64, device="cuda")
+                break
+            except torch.OutOfMemoryError:
+                # freed request tensors cached by torch in pieces too small for this one
+                if attempt:
+                    raise
+                inp = out = None
+                torch.cuda.empty_cache()
         ev = torch.cuda.Event()
         ev.record()
         return inp, out, ev
@@ -625,17 +640,28 @@ def serving(args):
         now = srv.now()
         return [dict(d, arrival=now + 0.05 + d["arrival"] * scale) for d in mix]
 
-    srv = serve.Server(args.serve_budget_gb * 1e9, max_slots=512, depth=2,
+    srv = serve.Server(args.serve_budget_gb * 1e9, max_slots=512, depth=2, slot_bytes_per_plan=args.serve_slot_gb * 1e9,
                        executor=serve.Executor(nstreams=4, graphs=args.serve_graphs))
     init_s = warm_up(srv, sorted({d["precision"] for d in base}))
     log(f"serve: warm-up (plans for {len(srv.plans)} keys) {init_s:.1f}s, {srv.used / 1e9:.1f} GB held")
+    def churn(srv, since):
+        return {"plans_created": srv.plans_created - since[0], "plans_evicted": srv.plans_evicted - since[1],
+                "plan_create_s": round(srv.plan_create_s - since[2], 1)}
+
+    def mark(srv):
+        return (srv.plans_created, srv.plans_evicted, srv.plan_create_s)
+
+    m0 = mark(srv)
     sat = serve.replay(srv, rebased(srv, [dict(d, arrival=0.0) for d in base], 0.0), make_io, max_live_bytes=live)
     st_sat = serve.latency_stats(sat)
+    st_sat.update(churn(srv, m0))
     cap_req = N / st_sat["makespan_s"]
     rate = 0.8 * cap_req
     log(f"serve: saturated {st_sat}")
+    m0 = mark(srv)
     poisson = serve.replay(srv, rebased(srv, base, 1.0 / rate), make_io, max_live_bytes=live)
     st_p = serve.latency_stats(poisson)
+    st_p.update(churn(srv, m0))
     log(f"serve: poisson at {rate:.2f} req/s {st_p}")
     peak = srv.peak
     srv.close()
@@ -643,11 +669,14 @@ def serving(args):
     torch.cuda.empty_cache()
     # baseline: the same arrivals, FP64, one request per launch, in arrival order on one stream
     ser = serve.Server(args.serve_budget_gb * 1e9, max_slots=512, depth=1 << 20, batching=False,
+                       slot_bytes_per_plan=args.serve_slot_gb * 1e9,
                        executor=serve.Executor(nstreams=1))
     warm_up(ser, ["fp64"])
+    m0 = mark(ser)
     serial = serve.replay(ser, rebased(ser, [dict(d, precision="fp64") for d in base], 1.0 / rate), make_io,
                           max_live_bytes=live)
     st_s = serve.latency_stats(serial)
+    st_s.update(churn(ser, m0))
     log(f"serve: serial fp64 fifo {st_s}")
     ser.close()
     del ser
@@ -660,10 +689,15 @@ def serving(args):
            "largest_request_gb": round(max(serve.request_bytes(d) for d in base) / 1e9, 1),
            "rate_req_per_s": round(rate, 3), "capacity_req_per_s": round(cap_req, 3),
            "p50_ms": st_p["p50_ms"], "p99_ms": st_p["p99_ms"], "maps_per_s": st_p["maps_per_s"],
+           "by_nside": st_p["by_nside"],
            "saturated_maps_per_s": st_sat["maps_per_s"],
            "serial_fp64_fifo": {"maps_per_s": st_s["maps_per_s"], "p50_ms": st_s["p50_ms"], "p99_ms": st_s["p99_ms"],
+                                "by_nside": st_s["by_nside"],
                                 "arrivals": "the same Poisson arrivals, one request per launch, first come first served"},
+           "callers": "independent: at most live_request_gb of request buffers, first fit in arrival order, "
+                      "no bypass of a request waiting more than 2 s",
            "graphs": bool(args.serve_graphs), "budget_gb": args.serve_budget_gb, "live_request_gb": args.serve_live_gb,
+           "slot_gb_per_plan": args.serve_slot_gb,
            "peak_server_gb": round(peak / 1e9, 1), "init_s": round(init_s, 1)}
     return out
 
@@ -699,6 +733,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=185.0, help="HBM the server may hold (plans, slots)")
     ap.add_argument("--serve-live-gb", type=float, default=65.0,
                     help="HBM the emulated callers hold for request inputs and outputs at a time")
+    ap.add_argument("--serve-slot-gb", type=float, default=3.0,
+                    help="batch slot buffers per plan and direction, GB (bounds the map sets one batched call holds)")
     ap.add_argument("--serve-mixed", default="bf16x3")
     ap.add_argument("--serve-graphs", action="store_true")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,

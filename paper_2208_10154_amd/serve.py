@@ -315,6 +315,9 @@ class Server:
         self.nstreams = max(1, len(getattr(self.ex, "streams", [0])))
         self.stream_load = [0.0] * self.nstreams  # estimated work in flight per stream
         self.batches = []  # (batch id, key, maps, requests)
+        self.plans_created = 0
+        self.plans_evicted = 0
+        self.plan_create_s = 0.0  # host seconds spent creating plans
         self.t0 = self.ex.start_clock()
         self.ex.set_origin(self.t0)
 
@@ -405,9 +408,12 @@ class Server:
             if not idle:
                 return None
             self._evict(min(idle)[1])
+        t0 = time.perf_counter()
         plan = self._new_plan(req, slots)
+        self.plan_create_s += time.perf_counter() - t0
         if plan is None:
             return None
+        self.plans_created += 1
         nbytes = max(est, self.ex.plan_bytes(plan, slots, "fp64"))
         p = _Plan(plan, 0, slots, nbytes)
         self.plans[pk] = p
@@ -439,6 +445,7 @@ class Server:
             self._evict(min(idle)[1])
 
     def _evict(self, pk) -> None:
+        self.plans_evicted += 1
         p = self.plans.pop(pk)
         self.used -= p.bytes
         self.ex.forget_plan(p.plan)
@@ -563,14 +570,17 @@ def request_bytes(d) -> int:
 
 
 def replay(server: Server, mix, make_io, release: bool = True, poll_sleep: float = 5e-5, stall_s: float = 60.0,
-           max_live_bytes: float | None = None):
+           max_live_bytes: float | None = None, bypass_age_s: float | None = 2.0):
     """Drive `server` with the request descriptors of `mix` (request_mix()
     dictionaries): each request is created with make_io(desc) -> (inp, out, ready)
     when the server clock reaches its arrival time, then submitted; finished
     requests drop their tensors when `release` is set.  With max_live_bytes the
     callers hold at most that many bytes of request inputs and outputs at a time:
-    a request that would exceed it is created, in arrival order, once earlier
-    requests have finished; its latency still counts from its arrival time.
+    a request that would exceed it is created once earlier requests have finished,
+    and its latency still counts from its arrival time.  The callers are
+    independent: a later request whose buffers fit goes ahead of one that does
+    not, unless that one has waited more than bypass_age_s (then it is next, so
+    large requests are not starved; None keeps strict arrival order).
     Returns the requests.  Raises RuntimeError if work is waiting but nothing
     completes for stall_s."""
     order = sorted(range(len(mix)), key=lambda k: mix[k]["arrival"])
@@ -581,14 +591,23 @@ def replay(server: Server, mix, make_io, release: bool = True, poll_sleep: float
         if big > max_live_bytes:
             raise ValueError(f"a request of {big / 1e9:.1f} GB exceeds the {max_live_bytes / 1e9:.1f} GB of live requests")
     reqs, live, i, live_bytes = [], [], 0, 0
+    due = []  # arrived, not yet created (arrival order)
     last_progress = time.perf_counter()
-    while i < len(order) or server.busy():
+    while i < len(order) or due or server.busy():
         now = server.now()
         while i < len(order) and mix[order[i]]["arrival"] <= now:
-            d = mix[order[i]]
+            due.append(order[i])
+            i += 1
+        waiting = []
+        for n_due, k in enumerate(due):
+            d = mix[k]
             nb = request_bytes(d)
             if max_live_bytes is not None and live_bytes + nb > max_live_bytes:
-                break  # the callers' memory is full: create it once earlier requests finish
+                waiting.append(k)
+                if bypass_age_s is None or now - d["arrival"] > bypass_age_s:
+                    waiting.extend(due[n_due + 1:])  # nothing later goes ahead of it
+                    break
+                continue
             inp, out, ready = make_io(d)
             r = Request(nside=d["nside"], spin=d["spin"], direction=d["direction"], precision=d["precision"],
                         nmaps=d["nmaps"], inp=inp, out=out, arrival=d["arrival"], ready=ready)
@@ -596,16 +615,17 @@ def replay(server: Server, mix, make_io, release: bool = True, poll_sleep: float
             reqs.append(r)
             live.append((r, nb))
             live_bytes += nb
-            i += 1
             last_progress = time.perf_counter()
+        due = waiting
         if server.poll():
             last_progress = time.perf_counter()
         else:
             time.sleep(poll_sleep)
-        if server.busy() and time.perf_counter() - last_progress > stall_s:
-            waiting = {k: len(q) for k, q in server.queues.items() if q}
-            raise RuntimeError(f"server stalled: waiting {waiting}, in flight {len(server.inflight)}, "
-                               f"plans {list(server.plans)}, {server.used / 1e9:.1f} of {server.budget / 1e9:.1f} GB")
+        if (server.busy() or due) and time.perf_counter() - last_progress > stall_s:
+            waiting_q = {k: len(q) for k, q in server.queues.items() if q}
+            raise RuntimeError(f"server stalled: waiting {waiting_q}, {len(due)} not created, in flight "
+                               f"{len(server.inflight)}, plans {list(server.plans)}, "
+                               f"{server.used / 1e9:.1f} of {server.budget / 1e9:.1f} GB")
         if release and live:
             keep = []
             for r, nb in live:
@@ -615,6 +635,7 @@ def replay(server: Server, mix, make_io, release: bool = True, poll_sleep: float
                 else:
                     keep.append((r, nb))
             live = keep
+    reqs.sort(key=lambda r: r.arrival)
     return reqs
 
 
@@ -625,7 +646,14 @@ def latency_stats(reqs) -> dict:
     t_start = min(r.arrival for r in reqs)
     sets = sum(r.nmaps for r in reqs if r.status == 0)
     comp = sum(r.nmaps * r.ncomp for r in reqs if r.status == 0)
+    by_nside = {}
+    for ns in sorted({r.nside for r in reqs}):
+        x = np.array([r.latency for r in reqs if r.nside == ns and r.latency is not None]) * 1e3
+        if len(x):
+            by_nside[str(ns)] = {"requests": int(len(x)), "p50_ms": round(float(np.percentile(x, 50)), 2),
+                                 "p99_ms": round(float(np.percentile(x, 99)), 2)}
     return {"requests": len(reqs), "failed": sum(r.status != 0 for r in reqs),
             "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
             "mean_ms": round(float(lat.mean()), 2), "makespan_s": round(t_end - t_start, 3),
-            "map_sets_per_s": round(sets / (t_end - t_start), 2), "maps_per_s": round(comp / (t_end - t_start), 2)}
+            "map_sets_per_s": round(sets / (t_end - t_start), 2), "maps_per_s": round(comp / (t_end - t_start), 2),
+            "by_nside": by_nside}

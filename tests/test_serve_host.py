@@ -224,8 +224,8 @@ def test_request_mix_is_seeded_and_bounded():
 
 def test_replay_bounds_live_request_bytes():
     """Callers that hold at most max_live_bytes of request data: a request that
-    would exceed it is created once earlier ones have finished, in arrival order,
-    and its latency counts from its arrival."""
+    would exceed it is created once earlier ones have finished, and its latency
+    counts from its arrival."""
     ex = RecordingExecutor()
     ex.duration = 0.02
     s = serve.Server(1e12, max_slots=64, executor=ex)
@@ -244,6 +244,43 @@ def test_replay_bounds_live_request_bytes():
     assert all(r.latency >= r.done - r.arrival - 1e-9 for r in reqs)
     with pytest.raises(ValueError):
         serve.replay(s, mix, make_io, max_live_bytes=2 * per)
+
+
+def test_replay_small_callers_go_ahead_of_a_blocked_large_one():
+    """Independent callers: while a large request waits for caller memory, a
+    later small one that fits is created first; a request that has waited longer
+    than bypass_age_s is not passed (no starvation); bypass_age_s=None keeps
+    strict arrival order.  Requests come back in arrival order."""
+    per = serve.mapset_bytes(16, 47, 0)
+
+    def run(age):
+        ex = RecordingExecutor(duration=0.05)
+        s = serve.Server(1e12, max_slots=64, executor=ex)
+        mix = [dict(arrival=0.001 * k, nside=16, spin=0, direction="alm2map", precision="fp64", nmaps=n)
+               for k, n in enumerate((4, 8, 1))]
+        made = []
+
+        def make_io(d):
+            made.append(d["nmaps"])
+            return None, None, None
+        reqs = serve.replay(s, mix, make_io, max_live_bytes=8.5 * per, stall_s=5.0, bypass_age_s=age)
+        assert len(reqs) == 3 and all(r.done is not None for r in reqs)
+        assert [r.nmaps for r in reqs] == [4, 8, 1]
+        return made
+    assert run(10.0) == [4, 1, 8]
+    assert run(None) == [4, 8, 1]
+    assert run(0.0) == [4, 8, 1]
+
+
+def test_latency_stats_by_nside():
+    reqs = []
+    for k, (ns, lat) in enumerate(((16, 0.010), (16, 0.030), (32, 0.5))):
+        r = serve.Request(nside=ns, spin=0, direction="alm2map", precision="fp64", nmaps=1)
+        r.arrival, r.done = float(k), float(k) + lat
+        reqs.append(r)
+    st = serve.latency_stats(reqs)
+    assert st["by_nside"]["16"]["requests"] == 2 and st["by_nside"]["32"]["requests"] == 1
+    assert abs(st["by_nside"]["16"]["p50_ms"] - 20.0) < 1e-6 and abs(st["by_nside"]["32"]["p99_ms"] - 500.0) < 1e-6
 
 
 def test_request_validation():
