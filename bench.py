@@ -690,6 +690,8 @@ def serving(args):
            "rate_req_per_s": round(rate, 3), "capacity_req_per_s": round(cap_req, 3),
            "p50_ms": st_p["p50_ms"], "p99_ms": st_p["p99_ms"], "maps_per_s": st_p["maps_per_s"],
            "by_nside": st_p["by_nside"],
+           "plan_churn": {name: {k: st[k] for k in ("plans_created", "plans_evicted", "plan_create_s")}
+                          for name, st in (("saturated", st_sat), ("poisson", st_p), ("serial", st_s))},
            "saturated_maps_per_s": st_sat["maps_per_s"],
            "serial_fp64_fifo": {"maps_per_s": st_s["maps_per_s"], "p50_ms": st_s["p50_ms"], "p99_ms": st_s["p99_ms"],
                                 "by_nside": st_s["by_nside"],
