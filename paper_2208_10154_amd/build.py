@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsht.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["k_fft.hip", "k_fft_p2.hip", "k_seed.hip", "k_leg.hip", "k_leg_bf16.hip", "k_alm.hip", "k_iter.hip", "sht_api.cpp"]
+SOURCES = ["k_fft.hip", "k_fft_p2.hip", "k_fft_four.hip", "k_seed.hip", "k_leg.hip", "k_leg_bf16.hip", "k_alm.hip", "k_iter.hip", "sht_api.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

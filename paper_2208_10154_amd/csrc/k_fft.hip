@@ -577,86 +577,6 @@ __global__ __launch_bounds__(NT, ELEMS == 16 ? 2 : 4) void k_fft_inv(FftArgs a, 
     }
 }
 
-// Direct DFT of one sequence of length n <= 16 NT held in LDS (nseq = 1), in
-// place: Z_k = sum_j z_j e^{-2 pi i jk / n}.  For ring lengths whose Bluestein
-// convolution would not fit the LDS (n > 4096 with a prime factor above 7, the
-// polar rings of nside >= 2048).  Each thread sums up to 16 bins over all n
-// values; the twiddle of every bin advances by one multiplication per term and
-// is reset to the exact table value every 64 terms, so its rounding error stays
-// at the level of 64 products.  O(n^2) work per sequence.
-constexpr int DKPT = 16;  // bins per thread
-__device__ __forceinline__ void direct_dft(double2* lds, int n, int ls, const double2* tw_n)
-{
-    double2 acc[DKPT], w[DKPT], st[DKPT];
-#pragma unroll
-    for (int q = 0; q < DKPT; ++q) {
-        const int k = min((int)threadIdx.x + q * NT, n - 1);
-        acc[q] = make_double2(0.0, 0.0);
-        st[q] = tw_n[2 * k];  // e^{-2 pi i k / n}
-    }
-    for (int j0 = 0; j0 < n; j0 += 64) {
-#pragma unroll
-        for (int q = 0; q < DKPT; ++q) {
-            const int k = min((int)threadIdx.x + q * NT, n - 1);
-            w[q] = tw_n[2 * (int)(((int64_t)j0 * k) % n)];
-        }
-        const int j1 = min(n, j0 + 64);
-        for (int j = j0; j < j1; ++j) {
-            const double2 z = lds[P(0, j, ls)];
-#pragma unroll
-            for (int q = 0; q < DKPT; ++q) {
-                acc[q] = cadd(acc[q], cmul(z, w[q]));
-                w[q] = cmul(w[q], st[q]);
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < DKPT; ++q) {
-        const int k = (int)threadIdx.x + q * NT;
-        if (k < n) lds[P(0, k, ls)] = acc[q];
-    }
-    __syncthreads();
-}
-
-// Forward ring transform of one map pair by direct DFT (see direct_dft), then
-// the FFT mapping of k_fft_fwd.
-__global__ __launch_bounds__(NT, 1) void k_fft_fwd_direct(FftArgs a, const FftItem* items, int nitems)
-{
-    extern __shared__ double2 lds[];
-    const RingCtx c = ring_ctx(a, items, nitems);
-    if (2 * c.it.pair0 >= a.nmaps) return;  // only padding map sets (see k_fft_p2.hip)
-    const int n = c.rg.n, ls = c.L->lstride;
-    const double* base = a.maps_in + (int64_t)c.comp * a.npix + c.rg.first;
-    const int64_t mstride = (int64_t)a.ncomp * a.npix;
-    const int k = 2 * c.it.pair0;
-    for (int i = threadIdx.x; i < n; i += NT) {
-        const double re = base[min(k, a.nmaps - 1) * mstride + i];
-        const double im = base[min(k + 1, a.nmaps - 1) * mstride + i];
-        lds[P(0, i, ls)] = make_double2(k < a.nmaps ? re : 0.0, k + 1 < a.nmaps ? im : 0.0);
-    }
-    __syncthreads();
-    direct_dft(lds, n, ls, c.tw_n);
-    unfold_store(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
-}
-
-// Inverse ring transform of one map pair by direct DFT: fold, conj(DFT(conj Z)).
-__global__ __launch_bounds__(NT, 1) void k_fft_inv_direct(FftArgs a, const FftItem* items, int nitems)
-{
-    extern __shared__ double2 lds[];
-    const RingCtx c = ring_ctx(a, items, nitems);
-    if (2 * c.it.pair0 >= a.nmaps) return;
-    const int n = c.rg.n, ls = c.L->lstride;
-    fold_load<true>(a, lds, c.L, c.rg.s, c.it.ring, c.it.pair0, c.comp, c.tw_n);
-    direct_dft(lds, n, ls, c.tw_n);
-    const int k = 2 * c.it.pair0;
-    for (int i = threadIdx.x; i < n; i += NT) {
-        const double2 z = lds[P(0, i, ls)];
-        if (k < a.nmaps) a.maps_out[((int64_t)k * a.ncomp + c.comp) * a.npix + c.rg.first + i] = z.x;
-        if (k + 1 < a.nmaps) a.maps_out[((int64_t)(k + 1) * a.ncomp + c.comp) * a.npix + c.rg.first + i] = -z.y;
-    }
-}
-
 // Residual of the iterative map2alm in the Fourier domain, FP64:
 // R_j = F_j - n C_j  (data spectrum minus the synthesised ring spectrum), then
 // T^res_m = e^{-i m phi0} R_{m mod n} written over X; sum |r|^2 = (1/n) sum_j |R_j|^2
@@ -791,27 +711,13 @@ hipError_t launch_one(Kind kind, const FftArgs& a, const FftClass& c, int ncompl
     return hipGetLastError();
 }
 
-hipError_t launch_direct(Kind kind, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st)
-{
-    if (kind == Kind::Res) return hipErrorNotSupported;  // the iteration is not offered for these lengths
-    const size_t sh = (size_t)c.lds * sizeof(double2);
-    const void* f = (kind == Kind::Fwd) ? (const void*)k_fft_fwd_direct : (const void*)k_fft_inv_direct;
-    if (sh > 65536) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        if (e != hipSuccess) return e;
-    }
-    const dim3 grid(c.nitems * ncompl);
-    if (kind == Kind::Fwd) hipLaunchKernelGGL(k_fft_fwd_direct, grid, dim3(NT), sh, st, a, c.items, c.nitems);
-    else hipLaunchKernelGGL(k_fft_inv_direct, grid, dim3(NT), sh, st, a, c.items, c.nitems);
-    return hipGetLastError();
-}
-
 hipError_t launch_classes(Kind kind, const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st)
 {
     for (int i = 0; i < ncls; ++i) {
         if (cls[i].nitems <= 0) continue;
         hipError_t e;
-        if (cls[i].direct) e = launch_direct(kind, a, cls[i], ncompl, st);
+        if (cls[i].four)  // the residual kernel of the iteration does not cover these rings
+            e = kind == Kind::Res ? hipErrorNotSupported : launch_fft_four(kind == Kind::Fwd, a, cls[i], ncompl, st);
         else if (cls[i].p2 && kind != Kind::Res) e = launch_fft_p2(kind == Kind::Fwd, a, cls[i], ncompl, st);
         else if (cls[i].elems <= 2) e = launch_one<2>(kind, a, cls[i], ncompl, st);
         else if (cls[i].elems <= 8) e = launch_one<8>(kind, a, cls[i], ncompl, st);

@@ -304,18 +304,49 @@ int build_fft(sht_plan p)
                 L.m = smooth_at_least(2 * r.n - 1);
             }
             if (L.m > 16 * FFT_THREADS && r.n <= 16 * FFT_THREADS) {
-                // the convolution would not fit the LDS: direct DFT of the ring
-                // (its n values fit), one map pair per workgroup
+                // the convolution would not fit the LDS: n = 4j runs as four
+                // Bluestein DFTs of length j through 4096 points and a radix-4
+                // step, one map pair per workgroup (k_fft_p2.hip); the length-j
+                // Bluestein data sit in an entry of their own
+                const int j = r.n / 4;
+                if (r.n % 4 || 2 * j - 1 > 4096) return fail(SHT_ERR_UNSUPPORTED, "ring FFT length beyond the four-step plan");
+                FftLen J{};
+                J.n = j;
+                J.blue = 1;
+                J.m = 4096;
+                J.bp2 = 12;
+                J.chirp = (int64_t)pool.size();
+                for (int s = 0; s < j; ++s) {
+                    const int64_t q = ((int64_t)s * s) % (2 * (int64_t)j);
+                    const ld ang = PI_L * (ld)q / (ld)j;
+                    pool.push_back(make_double2((double)cosl(ang), (double)(-sinl(ang))));
+                }
+                std::vector<int> radm;
+                factor_radices(J.m, radm);
+                J.nstage = (int)radm.size();
+                for (size_t q = 0; q < radm.size(); ++q) J.radix[q] = radm[q];
+                if (!tw_of.count(J.m)) { tw_of[J.m] = (int64_t)pool.size(); push_twiddles(pool, J.m); }
+                J.tw = J.twm = tw_of[J.m];
+                J.bhat = bhat_total;
+                bhat_total += J.m;
+                J.nseq = 1;
+                J.ldsc = J.m;
+                J.lstride = J.m + J.m / 16;
+                J.lds = J.lstride;
+                max_blue_m = std::max(max_blue_m, J.m);
+                L.sub = (int)p->lens.size();
+                blue.push_back(L.sub);
+                p->lens.push_back(J);
                 L.blue = 0;
-                L.direct = 1;
+                L.four = 1;
                 L.m = 0;
                 L.bp2 = 0;
                 L.nstage = 0;
                 L.nseq = 1;
                 L.lgseq = 0;
                 L.ldsc = r.n;
-                L.lstride = r.n + r.n / 16 + 16;
-                L.lds = L.lstride;
+                L.lstride = r.n;
+                L.lds = r.n;
                 r.len = (int)p->lens.size();
                 len_index[r.n] = r.len;
                 p->lens.push_back(L);
@@ -410,7 +441,7 @@ int build_items(sht_plan p, int npairs)
         return SHT_OK;
     }
     // classes 0..2: runtime-length kernels by LDS size; 3 + (k - 6): length 2^k;
-    // 10 + (k - 6): Bluestein through length 2^k; 17: direct DFT
+    // 10 + (k - 6): Bluestein through length 2^k; 17: four-step (n = 4j)
     constexpr int NCLS = 3 + 7 + 7 + 1;
     std::vector<FftItem> cls_items[NCLS];
     int lds[NCLS] = {};
@@ -419,7 +450,7 @@ int build_items(sht_plan p, int npairs)
         int c = (L.ldsc <= 2 * FFT_THREADS) ? 0 : (L.ldsc <= 8 * FFT_THREADS ? 1 : 2);
         if (L.p2) c = 3 + (L.p2 - 6);
         if (L.bp2) c = 10 + (L.bp2 - 6);
-        if (L.direct) c = NCLS - 1;
+        if (L.four) c = NCLS - 1;
         lds[c] = std::max(lds[c], L.lds);
         if (npairs % L.nseq) return fail(SHT_ERR_UNSUPPORTED, "map pairs per chunk not a multiple of the ring batch");
         for (int q = 0; q < npairs; q += L.nseq) cls_items[c].push_back(FftItem{r, q});
@@ -438,9 +469,9 @@ int build_items(sht_plan p, int npairs)
     for (int c = 0; c < NCLS; ++c) {
         const int elems = c == 0 ? 2 : (c == 2 ? 16 : 8);
         const int lg = c >= 10 ? c - 10 + 6 : (c >= 3 ? c - 3 + 6 : 0);
-        const bool dir = (c == NCLS - 1);
+        const bool four = (c == NCLS - 1);
         set.classes.push_back(FftClass{(const FftItem*)set.dev.p + off[c], (int)cls_items[c].size(), lds[c], elems,
-                                       dir ? 0 : lg, (c >= 10 && !dir) ? 1 : 0, dir ? 1 : 0});
+                                       four ? 0 : lg, (c >= 10 && !four) ? 1 : 0, four ? 1 : 0});
     }
     p->classes = set.classes;
     p->item_sets.emplace(npairs, std::move(set));

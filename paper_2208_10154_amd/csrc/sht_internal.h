@@ -49,7 +49,7 @@ constexpr int MAX_STAGES = 16;
 struct FftLen {
     int n;                  // ring length
     int blue;               // 1: Bluestein through length m
-    int m;                  // Bluestein FFT length (0 if direct)
+    int m;                  // Bluestein FFT length (0 if none)
     int nstage;             // stages of the FFT actually run (length n or m)
     int radix[MAX_STAGES];
     int64_t tw;             // offset of e^{-i pi j / n}, j < 2n
@@ -63,7 +63,9 @@ struct FftLen {
     int lds;                // complex LDS slots per workgroup = nseq * lstride
     int p2;                 // log2(n) when n is a power of two handled by k_fft_p2.hip, else 0
     int bp2;                // log2(m) when a Bluestein length m = 2^bp2 is handled by k_fft_p2.hip, else 0
-    int direct;             // 1: direct DFT in LDS (Bluestein would need a convolution beyond the LDS)
+    int four;               // 1: n = 4j, four Bluestein DFTs of length j and a radix-4 step (Bluestein of
+                            // length n would need a convolution beyond the LDS); k_fft_p2.hip
+    int sub;                // four: index of the length-j Bluestein entry (chirp, kernel spectrum, twiddles)
 };
 
 struct RingDev {
@@ -233,11 +235,13 @@ struct FftClass {
     int elems;   // 2, 8 or 16
     int p2;      // 0: runtime-length kernels; else log2 of the (convolution) length (k_fft_p2.hip)
     int blue;    // with p2: Bluestein rings through a power-of-two convolution
-    int direct;  // direct-DFT rings (FftLen::direct), one map pair per workgroup
+    int four;    // rings of FftLen::four, one map pair per workgroup
 };
 // power-of-two ring lengths 2^6 .. 2^12: map pairs per workgroup (0: not handled)
 int p2_seqs_per_group(int logn);
 hipError_t launch_fft_p2(bool forward, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st);
+// the four-step class (FftLen::four): forward and inverse only
+hipError_t launch_fft_four(bool forward, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st);
 hipError_t launch_fft_forward(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
 hipError_t launch_fft_inverse(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
 hipError_t launch_residual(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
