@@ -306,7 +306,7 @@ int build_fft(sht_plan p)
             if (L.m > 16 * FFT_THREADS && r.n <= 16 * FFT_THREADS) {
                 // the convolution would not fit the LDS: n = 4j runs as four
                 // Bluestein DFTs of length j through 4096 points and a radix-4
-                // step, one map pair per workgroup (k_fft_p2.hip); the length-j
+                // step, one map pair per workgroup (k_fft_four.hip); the length-j
                 // Bluestein data sit in an entry of their own
                 const int j = r.n / 4;
                 if (r.n % 4 || 2 * j - 1 > 4096) return fail(SHT_ERR_UNSUPPORTED, "ring FFT length beyond the four-step plan");

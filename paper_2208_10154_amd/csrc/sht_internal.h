@@ -64,7 +64,7 @@ struct FftLen {
     int p2;                 // log2(n) when n is a power of two handled by k_fft_p2.hip, else 0
     int bp2;                // log2(m) when a Bluestein length m = 2^bp2 is handled by k_fft_p2.hip, else 0
     int four;               // 1: n = 4j, four Bluestein DFTs of length j and a radix-4 step (Bluestein of
-                            // length n would need a convolution beyond the LDS); k_fft_p2.hip
+                            // length n would need a convolution beyond the LDS); k_fft_four.hip
     int sub;                // four: index of the length-j Bluestein entry (chirp, kernel spectrum, twiddles)
 };
 

@@ -7,8 +7,8 @@ of the split by m for resolutions beyond one GPU (Sec. 5):
 * nside 2048, lmax 6143 (the resolution the paper could not hold on one GPU):
   part 0 of 8, one IQU map set, sampled a_lm of its own m against the oracle and
   sampled pixels of its partial synthesis against the oracle's synthesis of the
-  same m only; the polar rings whose Bluestein convolution exceeds the LDS run the
-  direct ring DFT.
+  same m only; the polar rings whose Bluestein convolution exceeds the LDS run as
+  four length-n/4 Bluestein DFTs and a radix-4 step.
 """
 import numpy as np
 import pytest
