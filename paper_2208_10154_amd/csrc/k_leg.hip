@@ -116,8 +116,11 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
             e.e1 = e.e0 + CLS;
             return e;
         };
-        // ring operands of one K-step: north / south rows
+        // ring operands, loaded three K-steps before their MFMAs: raw north /
+        // south rows of two K-steps in flight, and the folded sums of the
+        // current one
         T xb[2][2][NU];  // [K-step parity][north, south][column tile]
+        T xs[2][NU];     // [T_N + T_S, T_N - T_S][column tile]
         auto load_x = [&](int rc, int ks, T (&d)[2][NU]) {
             rc = rsum - rc;
             const int r = min(rc * M_TR + 4 * ks + (lane >> 4), a.rn - 1);
@@ -129,6 +132,14 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
                 d[1][u] = ps[16 * u];
             }
         };
+        auto fold = [&](const T (&d)[2][NU]) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                xs[0][u] = d[0][u] + d[1][u];
+                xs[1][u] = d[0][u] - d[1][u];
+            }
+        };
+        static_assert(KS % 2 == 0 && KS >= 3, "the raw buffers alternate with the K-step parity");
 
         Seed<0> sd;
         Rec<0> f;
@@ -140,6 +151,9 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
         }
         seed_of(sd, min(rc0 + 1, nchunk - 1));
         load_x(rc0, 0, xb[0]);
+        load_x(rc0, 1, xb[1]);
+        fold(xb[0]);
+        load_x(rc0, 2, xb[0]);
         __syncthreads();
         for (int rc = rc0; rc < nchunk; ++rc) {
             const int b = (rc - rc0) & 1;
@@ -149,11 +163,7 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
             const T* lb_ = lam + b * BUF;
             static_for<0, KS>([&](auto ki) {
                 constexpr int ks = decltype(ki)::v;
-                if constexpr (ks + 1 < KS) load_x(rc, ks + 1, xb[(ks + 1) & 1]);
-                else load_x(rcn, 0, xb[0]);
                 if constexpr (ks == KS / 2) seed_of(sd, min(rc + 2, nchunk - 1));
-                // keep the prefetch ahead of this step's compute (the scheduler may sink it)
-                __builtin_amdgcn_sched_barrier(0);
                 const int kr = 4 * ks + (lane >> 4);
                 T av[2][2];
 #pragma unroll
@@ -162,15 +172,18 @@ __global__ __launch_bounds__(NT, 2) void k_m2a_spin0(LegArgs a)
                     for (int t = 0; t < 2; ++t)
                         if (mine(p, t)) av[p][t] = lb_[p * CLS + kr * RS + 16 * t + (lane & 15)];
 #pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    const T bs = xb[ks & 1][0][u] + xb[ks & 1][1][u];
-                    const T bd = xb[ks & 1][0][u] - xb[ks & 1][1][u];
+                for (int u = 0; u < NU; ++u)
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
-                        if (mine(0, t)) acc[0][t][u] = MF::run(av[0][t], bs, acc[0][t][u]);
-                        if (mine(1, t)) acc[1][t][u] = MF::run(av[1][t], bd, acc[1][t][u]);
+                        if (mine(0, t)) acc[0][t][u] = MF::run(av[0][t], xs[0][u], acc[0][t][u]);
+                        if (mine(1, t)) acc[1][t][u] = MF::run(av[1][t], xs[1][u], acc[1][t][u]);
                     }
-                }
+                // sums of the next K-step; its raw buffer then takes the K-step
+                // three ahead (in the next chunk for the last three)
+                fold(xb[(ks + 1) & 1]);
+                if constexpr (ks + 3 < KS) load_x(rc, ks + 3, xb[(ks + 1) & 1]);
+                else load_x(rcn, ks + 3 - KS, xb[(ks + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
                 if (filler) rec_group<ks, RPK>(f, cp, cnt, em);
             });
             __syncthreads();
@@ -444,7 +457,11 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
             e.e1 = e.e0 + CLS;
             return e;
         };
-        T bb[2][2][NU];  // [K-step parity][even, odd class row][column tile]
+        // coefficient operands, loaded PD K-steps ahead: two for FP64, one for
+        // FP32 (whose widest tiling has no registers for more)
+        constexpr int PD = sizeof(T) == 8 ? 2 : 1, NB = 2 * PD;
+        static_assert(KS % NB == 0, "the operand buffers cycle with the K-step index");
+        T bb[NB][2][NU];  // [K-step mod NB][even, odd class row][column tile]
         auto load_a = [&](int c, int ks, T (&d)[2][NU]) {
             const int le = lfirst + TL * c + 2 * (4 * ks + (lane >> 4));
             const T* pe = Am + (int64_t)(min(le, L) - lb) * a.ldx;
@@ -473,7 +490,8 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) seed_of(sd[i], min(1, nch - 1), i);
-        load_a(0, 0, bb[0]);
+#pragma unroll
+        for (int k = 0; k < PD; ++k) load_a(0, k, bb[k]);
         __syncthreads();
         for (int c = 0; c < nch; ++c) {
             const int b = c & 1;
@@ -486,26 +504,47 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0(LegArgs a)
             auto em0 = emit_to(b ^ 1, 0);
             auto em1 = emit_to(b ^ 1, 1);
             const T* lb_ = lam + b * BUF;
+            // recursion operands of one K-step from the LDS tile, read one K-step
+            // ahead within the chunk where the registers allow (wide FP64 tiles)
+            constexpr bool RA = sizeof(T) == 8 && !NW;
+            T aw[RA ? 2 : 1][4][2];  // [K-step parity][ring tile][even, odd class row]
+            auto read_lam = [&](int ks, T (&d)[4][2]) {
+                const int kl = 4 * ks + (lane >> 4);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (!mine(t)) continue;
+                    d[t][0] = lb_[kl * RS + 16 * t + (lane & 15)];
+                    d[t][1] = lb_[CLS + kl * RS + 16 * t + (lane & 15)];
+                }
+            };
+            if constexpr (RA) read_lam(0, aw[0]);
             static_for<0, KS>([&](auto ki) {
                 constexpr int ks = decltype(ki)::v;
-                if constexpr (ks + 1 < KS) load_a(c, ks + 1, bb[(ks + 1) & 1]);
-                else load_a(cn, 0, bb[0]);
+                if constexpr (ks + PD < KS) load_a(c, ks + PD, bb[(ks + PD) % NB]);
+                else load_a(cn, ks + PD - KS, bb[(ks + PD) % NB]);
+                if constexpr (RA && ks + 1 < KS) read_lam(ks + 1, aw[(ks + 1) & 1]);
                 if constexpr (ks == KS / 2) {
 #pragma unroll
                     for (int i = 0; i < 2; ++i) seed_of(sd[i], min(c + 2, nch - 1), i);
                 }
                 // keep the prefetch ahead of this step's compute (the scheduler may sink it)
                 __builtin_amdgcn_sched_barrier(0);
-                const int kl = 4 * ks + (lane >> 4);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     if (!mine(t)) continue;
-                    const T aE = lb_[kl * RS + 16 * t + (lane & 15)];
-                    const T aO = lb_[CLS + kl * RS + 16 * t + (lane & 15)];
+                    T aE, aO;
+                    if constexpr (RA) {
+                        aE = aw[ks & 1][t][0];
+                        aO = aw[ks & 1][t][1];
+                    } else {
+                        const int kl = 4 * ks + (lane >> 4);
+                        aE = lb_[kl * RS + 16 * t + (lane & 15)];
+                        aO = lb_[CLS + kl * RS + 16 * t + (lane & 15)];
+                    }
 #pragma unroll
                     for (int u = 0; u < NU; ++u) {
-                        accE[t][u] = MF::run(aE, bb[ks & 1][0][u], accE[t][u]);
-                        accO[t][u] = MF::run(aO, bb[ks & 1][1][u], accO[t][u]);
+                        accE[t][u] = MF::run(aE, bb[ks % NB][0][u], accE[t][u]);
+                        accO[t][u] = MF::run(aO, bb[ks % NB][1][u], accO[t][u]);
                     }
                 }
                 rec_group<ks, RPK>(f[0], cp0, cnt0, em0);

@@ -32,6 +32,8 @@
 // row 4 (lane / 16) + v, column lane % 16.  The recursion tiles are stored
 // K-contiguous in LDS (rows of 32 values padded to 40), one plane per piece, so
 // each operand vector is one 16-byte LDS read.
+#include <type_traits>
+
 #include "leg_rec.h"
 
 namespace sht {
@@ -171,6 +173,54 @@ struct EmitBF {
         __bf16* d = (R & 1 ? e1 : e0) + (R >> 1) * STEP;
         put1(d, p);
         put1(d + FOFF, q);
+    }
+};
+
+// Emitter for the alm2map tiles, whose class rows are K-contiguous in LDS
+// (STEP 1): a lane's four rows of one parity class in a segment (rows R = c,
+// c + 2, c + 4, c + 6) are four adjacent bf16 of a plane, so they are held in
+// registers and leave as one 8-byte store per plane (and F+-) once the fourth
+// arrives.  Single 2-byte stores from 32 lanes whose rows lie 80 bytes apart
+// fall on a quarter of the banks; the gathered stores issue a quarter as often.
+template <int FOFF, int LOFF>
+struct EmitBF4 {
+    static_assert(SEG == 8, "four rows per parity class and segment");
+    __bf16* e0;
+    __bf16* e1;
+    float v[2][4][2];  // [parity class][row within the class][F+, F-]
+    __device__ __forceinline__ static uint32_t pair(uint32_t lo, uint32_t hi)
+    {
+        return __builtin_amdgcn_perm(hi, lo, 0x07060302u);  // upper halves: lo in bits 0-15
+    }
+    __device__ __forceinline__ static void store4(__bf16* d, const float (&x)[4])
+    {
+        const P3 a = split3(x[0]), b = split3(x[1]), c = split3(x[2]), e = split3(x[3]);
+        *reinterpret_cast<v2u*>(d) = v2u{pair(a.h, b.h), pair(c.h, e.h)};
+        *reinterpret_cast<v2u*>(d + LOFF) = v2u{pair(a.m, b.m), pair(c.m, e.m)};
+        *reinterpret_cast<v2u*>(d + 2 * LOFF) = v2u{pair(a.l, b.l), pair(c.l, e.l)};
+    }
+    template <int C, int NF>
+    __device__ __forceinline__ void flush()
+    {
+        __bf16* d = C ? e1 : e0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const float x[4] = {v[C][0][f], v[C][1][f], v[C][2][f], v[C][3][f]};
+            store4(d + f * FOFF, x);
+        }
+    }
+    template <int R>
+    __device__ __forceinline__ void put(double x)
+    {
+        v[R & 1][R >> 1][0] = (float)x;
+        if constexpr ((R >> 1) == 3) flush<R & 1, 1>();
+    }
+    template <int R>
+    __device__ __forceinline__ void put(double p, double q)
+    {
+        v[R & 1][R >> 1][0] = (float)p;
+        v[R & 1][R >> 1][1] = (float)q;
+        if constexpr ((R >> 1) == 3) flush<R & 1, 2>();
     }
 };
 
@@ -593,8 +643,10 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin0_bf(LegArgs a)
             seed_load(s, a, sb + (int64_t)min(j0 + 4 * i + SPT * c, jmax) * a.rn, frc);
         };
         auto ls_of = [&](int c, int i) { return lfirst + TL * c + SEG * (fs0 + 4 * i); };
+        // gathered 8-byte stores where the registers allow them (one column tile)
+        using EM = typename std::conditional<NU == 1, EmitBF4<0, PL>, EmitBF<1, 0, PL>>::type;
         auto emit_to = [&](int b, int i) {
-            EmitBF<1, 0, PL> e;
+            EM e;
             e.e0 = lam + b * BUF + frl * KP + (SEG / 2) * (fs0 + 4 * i);
             e.e1 = e.e0 + CLS;
             return e;
@@ -775,7 +827,7 @@ __global__ __launch_bounds__(NT, 2) void k_a2m_spin2_bf(LegArgs a)
         auto seed_of = [&](Seed<2>& s, int c) { seed_load(s, a, sb + (int64_t)min(j0 + SPT * c, jmax) * a.rn, frc); };
         auto ls_of = [&](int c) { return lfirst + TL * c + SEG * fs; };
         auto emit_to = [&](int b) {
-            EmitBF<1, FOFF, PL> e;
+            EmitBF4<FOFF, PL> e;
             e.e0 = fpm + b * BUF + po * CLS + frl * KP + (SEG / 2) * fs;
             e.e1 = fpm + b * BUF + (po ^ 1) * CLS + frl * KP + (SEG / 2) * fs;
             return e;
