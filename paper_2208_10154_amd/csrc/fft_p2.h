@@ -4,7 +4,7 @@
 // and the fold / unfold between ring spectra and the m-major coefficient rows.
 // Each translation unit gets its own copy (internal linkage).
 #pragma once
-#include "sht_internal.h"
+#include "fft_internal.h"
 
 namespace sht {
 namespace {

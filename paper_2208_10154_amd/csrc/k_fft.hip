@@ -23,7 +23,7 @@
 // sequence sq, element i at sq * lstride + i + i / 16: the pad slot every 16
 // values and the sequence stride (congruent to 16/nseq modulo 16) spread
 // power-of-two strides over the banks.
-#include "sht_internal.h"
+#include "fft_internal.h"
 
 namespace sht {
 namespace {

@@ -12,7 +12,7 @@
 // with dS_m the synthesis of the update of m on that ring.  Modes processed
 // together (one level of the schedule) never share a bin of a ring on which
 // both carry data, so each thread owns the bins it updates.
-#include "sht_internal.h"
+#include "fft_internal.h"
 
 namespace sht {
 namespace {

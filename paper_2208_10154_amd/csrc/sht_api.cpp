@@ -1,7 +1,7 @@
 // Host side of libsht: plan construction (ring geometry, FFT plans, Legendre seed
 // tables, work lists, workspace) and the C ABI declared in include/sht.h.
 #include "../../include/sht.h"
-#include "sht_internal.h"
+#include "fft_internal.h"
 
 #include <algorithm>
 #include <cmath>
