@@ -7,7 +7,7 @@
 // records the pair (lambda_ls, lambda_ls+1) at every segment start
 // ls = lb(m) + SEG j, in the scaled form mu * 2^(-600 k).  The exponent counter
 // replaces the paper's "safe positions" table (Sec. 3.1 item 11): values below
-// 2^-100 are carried exactly in scaled form and count as zero, which also gives
+// 2^SIG_LOG2 are carried exactly in scaled form and count as zero, which also gives
 // the ring-skipping bounds (Sec. 3.1 item 10) recorded in lsig.
 #include "leg_common.h"
 

@@ -127,7 +127,7 @@ struct Emit {
 // Row R of a segment: rows 0 and 1 are the seed pair, later rows come from the
 // recursion with that row's coefficients c (read beforehand from the coefficient
 // tile in LDS).  Rows at or past cnt (beyond lmax) and values still carrying an
-// exponent (k > 0: below 2^-100) are emitted as zeros.  The exponent handling is
+// exponent (k > 0: below 2^SIG_LOG2) are emitted as zeros.  The exponent handling is
 // a branch taken only by waves that had a lane carrying an exponent when the
 // segment started, marked unlikely so that the compiler keeps it out of the
 // common path instead of evaluating it on every row and selecting.

@@ -482,7 +482,8 @@ int build_items(sht_plan p, int npairs)
 // --------------------------------------------------------------------------
 // Legendre seeds
 // --------------------------------------------------------------------------
-// scaled form of a value given its log2 magnitude: mu * 2^(-600 k), |mu| in [2^-100, 2^500)
+// scaled form of a value given its log2 magnitude: mu * 2^(-SCALE_BITS k),
+// |mu| in [2^SIG_LOG2, 2^(SIG_LOG2 + SCALE_BITS))
 void scaled(ld log2abs, double sign, double& mu, int& k)
 {
     k = 0;

@@ -8,13 +8,16 @@ namespace sht {
 
 // ----------------------------------------------------------------------------
 // Scaled representation of Legendre values: true value = mu * 2^(-SCALE_BITS*k).
-// k >= 1 means |true| < 2^-100, which is treated as exactly zero when the value
-// is fed to the contraction (ring skipping and underflow handling in one rule).
+// k >= 1 means |true| < 2^SIG_LOG2, which is treated as exactly zero when the
+// value is fed to the contraction (ring skipping, the safe starting positions
+// and underflow handling in one rule).  The threshold is the paper's example
+// for the safe positions (Sec. 3.1: amplitudes above about 1e-20; 2^-67 is
+// 6.8e-21): a dropped value is below 1e-16 of FP64 resolution at O(1) peaks.
 // ----------------------------------------------------------------------------
 constexpr int SCALE_BITS = 600;
 constexpr double SCALE_DOWN = 0x1p-600;   // 2^-SCALE_BITS
-constexpr double RESCALE_AT = 0x1p500;    // rescale when |mu| exceeds this and k >= 1
-constexpr int SIG_LOG2 = -100;            // values below 2^SIG_LOG2 count as zero
+constexpr int SIG_LOG2 = -67;             // values below 2^SIG_LOG2 count as zero
+constexpr double RESCALE_AT = 0x1p533;    // 2^(SIG_LOG2 + SCALE_BITS): rescale when |mu| exceeds this and k >= 1
 
 // Legendre tiling: l segments of SEG values start at lb(m) + SEG*j (one stored
 // seed pair each, so SEG rows of one ring can be generated independently);
