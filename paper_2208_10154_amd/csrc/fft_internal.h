@@ -91,23 +91,8 @@ int p2_seqs_per_group(int logn);
 hipError_t launch_fft_p2(bool forward, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st);
 // the four-step class (FftLen::four): forward and inverse only
 hipError_t launch_fft_four(bool forward, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st);
-// Side streams over which a forward or inverse FFT stage spreads its length
-// classes: forked from the caller's stream by one event and joined back into it,
-// so the stage stays ordered on that stream as a whole.  The power-of-two belt
-// rings (bound by HBM) and the Bluestein rings (bound by arithmetic and LDS
-// latency) then share the CUs, and the small classes fill the tails of the large
-// ones.  ok = false (or no fan): every class on the caller's stream, in order.
-struct FftFan {
-    static constexpr int NSIDE = 2;
-    hipStream_t side[NSIDE] = {};
-    hipEvent_t fork = nullptr;
-    hipEvent_t join[NSIDE] = {};
-    bool ok = false;
-};
-hipError_t launch_fft_forward(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st,
-                              const FftFan* fan = nullptr);
-hipError_t launch_fft_inverse(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st,
-                              const FftFan* fan = nullptr);
+hipError_t launch_fft_forward(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
+hipError_t launch_fft_inverse(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
 hipError_t launch_residual(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st);
 hipError_t launch_bluestein_init(const FftLen* lens, const int* blue_lens, int nblue, const double2* tw,
                                  double2* bhat, int lds, hipStream_t st);

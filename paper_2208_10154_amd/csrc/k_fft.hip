@@ -23,8 +23,6 @@
 // sequence sq, element i at sq * lstride + i + i / 16: the pad slot every 16
 // values and the sequence stride (congruent to 16/nseq modulo 16) spread
 // power-of-two strides over the banks.
-#include <algorithm>
-
 #include "fft_internal.h"
 
 namespace sht {
@@ -713,81 +711,37 @@ hipError_t launch_one(Kind kind, const FftArgs& a, const FftClass& c, int ncompl
     return hipGetLastError();
 }
 
-hipError_t launch_class(Kind kind, const FftArgs& a, const FftClass& c, int ncompl, hipStream_t st)
+hipError_t launch_classes(Kind kind, const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st)
 {
-    if (c.four)  // the residual kernel of the iteration does not cover these rings
-        return kind == Kind::Res ? hipErrorNotSupported : launch_fft_four(kind == Kind::Fwd, a, c, ncompl, st);
-    if (c.p2 && kind != Kind::Res) return launch_fft_p2(kind == Kind::Fwd, a, c, ncompl, st);
-    if (c.elems <= 2) return launch_one<2>(kind, a, c, ncompl, st);
-    if (c.elems <= 8) return launch_one<8>(kind, a, c, ncompl, st);
-    return launch_one<16>(kind, a, c, ncompl, st);
-}
-
-// rough work of a class, for spreading the classes over streams: values per
-// workgroup times workgroups, twice for the two transforms of a Bluestein ring
-// and eight times for the four of a four-step ring
-double class_cost(const FftClass& c)
-{
-    return (double)c.nitems * (double)c.lds * (c.four ? 8.0 : (c.blue ? 2.0 : 1.0));
-}
-
-hipError_t launch_classes(Kind kind, const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st,
-                          const FftFan* fan)
-{
-    if (!fan || !fan->ok || kind == Kind::Res || ncls > 64) {
-        for (int i = 0; i < ncls; ++i) {
-            if (cls[i].nitems <= 0) continue;
-            const hipError_t e = launch_class(kind, a, cls[i], ncompl, st);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
+    for (int i = 0; i < ncls; ++i) {
+        if (cls[i].nitems <= 0) continue;
+        hipError_t e;
+        if (cls[i].four)  // the residual kernel of the iteration does not cover these rings
+            e = kind == Kind::Res ? hipErrorNotSupported : launch_fft_four(kind == Kind::Fwd, a, cls[i], ncompl, st);
+        else if (cls[i].p2 && kind != Kind::Res) e = launch_fft_p2(kind == Kind::Fwd, a, cls[i], ncompl, st);
+        else if (cls[i].elems <= 2) e = launch_one<2>(kind, a, cls[i], ncompl, st);
+        else if (cls[i].elems <= 8) e = launch_one<8>(kind, a, cls[i], ncompl, st);
+        else e = launch_one<16>(kind, a, cls[i], ncompl, st);
+        if (e != hipSuccess) return e;
     }
-    // largest class first, each onto the stream with the least work so far
-    constexpr int NS = 1 + FftFan::NSIDE;
-    int order[64];
-    int n = 0;
-    for (int i = 0; i < ncls && n < 64; ++i)
-        if (cls[i].nitems > 0) order[n++] = i;
-    std::sort(order, order + n, [&](int x, int y) { return class_cost(cls[x]) > class_cost(cls[y]); });
-    hipError_t e = hipEventRecord(fan->fork, st);
-    for (int j = 0; j < FftFan::NSIDE && e == hipSuccess; ++j) e = hipStreamWaitEvent(fan->side[j], fan->fork, 0);
-    double load[NS] = {};
-    bool used[NS] = {};
-    for (int q = 0; q < n && e == hipSuccess; ++q) {
-        int s = 0;
-        for (int j = 1; j < NS; ++j)
-            if (load[j] < load[s]) s = j;
-        load[s] += class_cost(cls[order[q]]);
-        used[s] = true;
-        e = launch_class(kind, a, cls[order[q]], ncompl, s == 0 ? st : fan->side[s - 1]);
-    }
-    // join every side stream, also after an error, so none is left forked
-    for (int j = 0; j < FftFan::NSIDE; ++j) {
-        if (!used[j + 1]) continue;
-        hipError_t ej = hipEventRecord(fan->join[j], fan->side[j]);
-        if (ej == hipSuccess) ej = hipStreamWaitEvent(st, fan->join[j], 0);
-        if (e == hipSuccess) e = ej;
-    }
-    return e;
+    return hipSuccess;
 }
 
 }  // namespace
 
-hipError_t launch_fft_forward(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st,
-                              const FftFan* fan)
+hipError_t launch_fft_forward(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st)
 {
-    return launch_classes(Kind::Fwd, a, cls, ncls, ncompl, st, fan);
+    return launch_classes(Kind::Fwd, a, cls, ncls, ncompl, st);
 }
 
-hipError_t launch_fft_inverse(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st,
-                              const FftFan* fan)
+hipError_t launch_fft_inverse(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st)
 {
-    return launch_classes(Kind::Inv, a, cls, ncls, ncompl, st, fan);
+    return launch_classes(Kind::Inv, a, cls, ncls, ncompl, st);
 }
 
 hipError_t launch_residual(const FftArgs& a, const FftClass* cls, int ncls, int ncompl, hipStream_t st)
 {
-    return launch_classes(Kind::Res, a, cls, ncls, ncompl, st, nullptr);
+    return launch_classes(Kind::Res, a, cls, ncls, ncompl, st);
 }
 
 hipError_t launch_bluestein_init(const FftLen* lens, const int* blue_lens, int nblue, const double2* tw,

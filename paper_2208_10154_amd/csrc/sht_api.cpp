@@ -86,7 +86,6 @@ struct sht_plan_s {
     int nring = 0, rn = 0, nrc = 0;
     int64_t npix = 0;
     hipStream_t stream = nullptr;
-    FftFan fan;  // side streams of the FFT stages (created with the plan, on its device)
 
     std::vector<RingDev> rings;
     std::vector<FftLen> lens;
@@ -921,7 +920,7 @@ int run_fft_inv(sht_plan p, double* maps, int nm, int sel)
         HIPCHK(launch_zero_strided(zb, nm, mstride, (int64_t)(3 - ncompl) * p->npix, p->stream));
     }
     StageTimer tm(p, SHT_STAGE_FFT_INV);
-    HIPCHK(launch_fft_inverse(f, p->classes.data(), (int)p->classes.size(), ncompl, p->stream, &p->fan));
+    HIPCHK(launch_fft_inverse(f, p->classes.data(), (int)p->classes.size(), ncompl, p->stream));
     return SHT_OK;
 }
 
@@ -1121,11 +1120,6 @@ void drop_records(sht_plan p)
 void destroy_all(sht_plan p)
 {
     drop_records(p);
-    for (int j = 0; j < FftFan::NSIDE; ++j) {
-        if (p->fan.side[j]) (void)hipStreamDestroy(p->fan.side[j]);
-        if (p->fan.join[j]) (void)hipEventDestroy(p->fan.join[j]);
-    }
-    if (p->fan.fork) (void)hipEventDestroy(p->fan.fork);
     for (auto& d : p->owned)
         if (d.p) (void)hipFree(d.p);
     for (auto& kv : p->item_sets)
@@ -1185,14 +1179,6 @@ int create_plan(sht_plan* out, int nside, int lmax, int spin, int nmaps, int par
         p->nown = (int)mlist.size();
     } else {
         p->nown = lmax + 1;
-    }
-    {
-        // side streams at the default priority, events without timing
-        bool ok = hipEventCreateWithFlags(&p->fan.fork, hipEventDisableTiming) == hipSuccess;
-        for (int j = 0; j < FftFan::NSIDE && ok; ++j)
-            ok = hipStreamCreateWithFlags(&p->fan.side[j], hipStreamNonBlocking) == hipSuccess &&
-                 hipEventCreateWithFlags(&p->fan.join[j], hipEventDisableTiming) == hipSuccess;
-        p->fan.ok = ok;  // else every FFT class runs on the plan's stream
     }
     build_rings(p);
     p->nrc = (p->rn + RCHUNK - 1) / RCHUNK;
@@ -1413,7 +1399,7 @@ int sht_map2alm_sel(sht_plan p, int comps, const double* map, double* alm)
         }
         {
             StageTimer t(p, SHT_STAGE_FFT_FWD);
-            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), ncompl, p->stream, &p->fan));
+            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), ncompl, p->stream));
         }
         if ((rc = run_m2a(p, alm + k0 * astride, nm, 0, comps))) return rc;
     }
@@ -1443,7 +1429,7 @@ int sht_eb_split(sht_plan p, const double* map, double* alm, double* map_e, doub
         f.maps_in = map + k0 * mstride;
         {
             StageTimer t(p, SHT_STAGE_FFT_FWD);
-            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream, &p->fan));
+            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
         }
         double* a = alm + k0 * astride;
         if ((rc = run_m2a(p, a, nm, 0))) return rc;
@@ -1478,7 +1464,7 @@ int sht_map2alm_iter(sht_plan p, const double* map, double* alm, int niter, doub
         f.F = p->F;
         {
             StageTimer t(p, SHT_STAGE_FFT_FWD);
-            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream, &p->fan));
+            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
         }
         if ((rc = run_m2a(p, a, nm, 0))) return rc;
         const int rounds = niter + (resid ? 1 : 0);
@@ -1546,7 +1532,7 @@ int sht_map2alm_immediate(sht_plan p, const double* map, double* alm, int niter,
         f.F = p->F;
         {
             StageTimer t(p, SHT_STAGE_FFT_FWD);
-            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream, &p->fan));
+            HIPCHK(launch_fft_forward(f, p->classes.data(), (int)p->classes.size(), p->ncomp, p->stream));
         }
         if ((rc = run_m2a(p, a, nm, 0))) return rc;
         if (niter == 0 && !resid) continue;
