@@ -2,6 +2,7 @@
 one, and the committed counter record it reads for roofline traffic is complete."""
 import json
 import os
+import re
 import subprocess
 import sys
 
@@ -21,7 +22,8 @@ def test_traffic_record_is_complete():
         rec = json.load(fh)
     assert rec, "no kernel in the traffic record"
     for kernel, e in rec.items():
-        assert kernel.startswith("k_") and "<" in kernel
+        # the names bench.roofline() looks up: direction, spin, precision
+        assert re.fullmatch(r"k_(m2a|a2m)_spin[02](<double>|<float>|_bf)", kernel), kernel
         assert len(e["source_hash"]) == 16
         assert e["bytes_per_launch"] > 0 and e["fetch_kib"] > 0 and e["write_kib"] > 0
         # bytes = 1024 (FETCH x scale + WRITE x scale)
