@@ -16,7 +16,7 @@ namespace {
 // polar rings longer than 4096 pixels without a 7-smooth length, nside >= 2048).
 // Decimation in time splits the length-n DFT into the four length-j DFTs of the
 // pixels 4s + r, each taken by Bluestein through 4096 points (j <= 2047) with the
-// compile-time passes above, and one radix-4 step:
+// compile-time passes of fft_p2.h, and one radix-4 step:
 //   Z[k1 + j k2] = sum_r e^{-2 pi i r k1 / n} (-i)^{r k2} Y_r[k1].
 // One map pair per workgroup of 512 threads; thread tl keeps the outputs of
 // k1 = tl + 512 q (q < 4) for the four k2 in registers while the LDS holds the
